@@ -226,8 +226,14 @@ def to_integers(op: np.ndarray, shift: np.ndarray, axis: int) -> np.ndarray:
 
 
 def residues(Xint: np.ndarray, p: int) -> np.ndarray:
-    """smod(X', p) as int64.  fmod of a float64 integer is exact."""
-    return smod(np.fmod(Xint, p).astype(np.int64), p)
+    """smod(X', p) as int64.  Entries below 2^53 in magnitude are exact int64
+    values and use integer remainder; larger ones use fmod, which is exact
+    for every float64."""
+    small = np.abs(Xint) < 2.0 ** 53
+    r = np.empty(Xint.shape, dtype=np.int64)
+    r[small] = Xint[small].astype(np.int64) % p
+    r[~small] = np.fmod(Xint[~small], p).astype(np.int64)
+    return smod(r, p)
 
 
 def digits_square(u: np.ndarray, s: int):
@@ -331,21 +337,17 @@ def inverse_scale(Cp: np.ndarray, sA: np.ndarray, sB: np.ndarray) -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 
-def emulate(opA: np.ndarray, opB: np.ndarray, num_moduli: int,
-            keep_stages: bool = False):
-    """Chat ~ op(A) op(B) by the FP8 Ozaki-II scheme, accurate mode.
-
-    Returns Chat (m x n float64) and, with keep_stages, a dict of every
-    intermediate quantity.  Implements Sections II and III-B..III-E in the
-    order of the workflow of Section IV-B."""
+def scaling(opA: np.ndarray, opB: np.ndarray, num_moduli: int) -> dict:
+    """Workflow steps 1-3 of Section IV-B: mu', nu', the round-up FP8 bound
+    operands, the bound product's line maxima and the scale exponents.
+    Returns a dict with EA, EB, Abar, Bbar, r18, c18, e, f, sA = log2(mu),
+    sB = log2(nu), the zeroed operands A, B and the non-finite flags."""
     opA = np.asarray(opA, dtype=np.float64)
     opB = np.asarray(opB, dtype=np.float64)
     m, k = opA.shape
-    k2, n = opB.shape
-    assert k == k2
+    n = opB.shape[1]
     mods = hybrid_moduli(num_moduli)
-    moduli = [p for p, _, _ in mods]
-    P = math.prod(moduli)
+    P = math.prod(p for p, _, _ in mods)
 
     # R9: non-finite rows / columns are flagged and quantized as zeros
     badA = ~np.all(np.isfinite(opA), axis=1) if k else np.zeros(m, bool)
@@ -362,39 +364,67 @@ def emulate(opA: np.ndarray, opB: np.ndarray, num_moduli: int,
     W18 = exact_bound_product(Abar, Bbar)
     r18 = W18.max(axis=1) if n else np.zeros(m)
     c18 = W18.max(axis=0) if m else np.zeros(n)
+    del W18
     e = np.array([scale_exponent(v, P) for v in r18], dtype=np.int64)
     f = np.array([scale_exponent(v, P) for v in c18], dtype=np.int64)
-    sA = 7 - EA + e            # log2(mu_i)
-    sB = 7 - EB + f            # log2(nu_j)
+    return dict(moduli=mods, P=P, A=A, B=B, badA=badA, badB=badB, EA=EA, EB=EB,
+                Abar=Abar, Bbar=Bbar, r18=r18, c18=c18, e=e, f=f,
+                sA=7 - EA + e, sB=7 - EB + f)
 
+
+def products(sc: dict, rows, cols, keep_stages: bool = False):
+    """Workflow steps 4-10 for the entries (rows x cols): integers, residues,
+    exact residue products, CRT and inverse scaling."""
+    A = sc["A"][rows]
+    B = sc["B"][:, cols]
+    sA = sc["sA"][rows]
+    sB = sc["sB"][cols]
     # workflow steps 4-6: integers, residues, digits
     Aint = to_integers(A, sA, axis=0)
     Bint = to_integers(B, sB, axis=1)
-
-    planes = []
-    stages_mod = []
-    for p, kind, s in mods:
+    planes, per_mod = [], []
+    for p, kind, s in sc["moduli"]:
         uA = residues(Aint, p)
         uB = residues(Bint, p)
         # workflow steps 7-8: the residue product, exact (eq. CRTmatmul)
-        Cl = residue_product(uA, uB, p)
-        planes.append(Cl)
+        planes.append(residue_product(uA, uB, p))
         if keep_stages:
-            stages_mod.append(dict(p=p, kind=kind, s=s, uA=uA, uB=uB,
-                                   dA=digit_slices(uA, kind, s),
-                                   dB=digit_slices(uB, kind, s)))
-
+            per_mod.append(dict(p=p, kind=kind, s=s, uA=uA, uB=uB,
+                                dA=digit_slices(uA, kind, s),
+                                dB=digit_slices(uB, kind, s)))
     # workflow steps 9-10: CRT and inverse scaling
-    Cp = crt_reconstruct(planes, moduli) if planes else None
+    Cp = crt_reconstruct(planes, [p for p, _, _ in sc["moduli"]])
     Chat = inverse_scale(Cp, sA, sB)
-    Chat[badA, :] = np.nan
-    Chat[:, badB] = np.nan
+    Chat[sc["badA"][rows], :] = np.nan
+    Chat[:, sc["badB"][cols]] = np.nan
+    return Chat, dict(Aint=Aint, Bint=Bint, planes=planes, per_modulus=per_mod, Cp=Cp)
+
+
+def emulate(opA: np.ndarray, opB: np.ndarray, num_moduli: int,
+            keep_stages: bool = False):
+    """Chat ~ op(A) op(B) by the FP8 Ozaki-II scheme, accurate mode.
+
+    Returns Chat (m x n float64) and, with keep_stages, a dict of every
+    intermediate quantity.  Implements Sections II and III-B..III-E in the
+    order of the workflow of Section IV-B."""
+    sc = scaling(opA, opB, num_moduli)
+    m, n = sc["A"].shape[0], sc["B"].shape[1]
+    Chat, st = products(sc, slice(0, m), slice(0, n), keep_stages)
     if not keep_stages:
         return Chat
-    return Chat, dict(moduli=mods, P=P, EA=EA, EB=EB, Abar=Abar, Bbar=Bbar,
-                      r18=r18, c18=c18, e=e, f=f, sA=sA, sB=sB, Aint=Aint,
-                      Bint=Bint, planes=planes, per_modulus=stages_mod, Cp=Cp,
-                      badA=badA, badB=badB)
+    st.update({key: sc[key] for key in ("moduli", "P", "EA", "EB", "Abar", "Bbar", "r18",
+                                        "c18", "e", "f", "sA", "sB", "badA", "badB")})
+    return Chat, st
+
+
+def emulate_sampled(opA: np.ndarray, opB: np.ndarray, num_moduli: int, rows, cols):
+    """The entries Chat[rows][:, cols] of emulate(opA, opB, num_moduli), with
+    the scale exponents of every line (they depend on the whole product) but
+    the residue products, CRT and inverse scaling only for the sample.
+    Returns (Chat_sample, scaling dict)."""
+    sc = scaling(opA, opB, num_moduli)
+    Chat, _ = products(sc, np.asarray(rows), np.asarray(cols), False)
+    return Chat, sc
 
 
 def combine_alpha_beta(Chat: np.ndarray, alpha: float, beta: float,

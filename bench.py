@@ -1,0 +1,212 @@
+"""Benchmark: emulated FP64 DGEMM by FP8 Ozaki-II on one MI355X.
+
+Default workload: m = n = k = 8192, column-major 'N','N', entries
+(U[0,1) - 0.5) exp(0.5 N(0,1)) from a seeded PCG64, alpha = 1, beta = 0,
+12 moduli (the paper's full-accuracy count), accurate mode.  Inputs are
+resident in HBM before the timed region.  One step = one ozaki2_dgemm call
+(every stage of the path).  Prints one JSON line.
+
+Beside the emulated rate it reports: the native FP64 DGEMM (torch.matmul on
+float64, i.e. the vendor BLAS) on the same inputs, the normalised error of
+both against a double-double reference on sampled rows, the residue-product
+kernels against the FP8 MFMA roofline (timed with HIP events on the library's
+stream), and the CPU oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "emulated FP64 TFLOP/s vs native FP64 DGEMM at ≤1e-15 err; FP8 MFMA util %"
+FP8_PEAK_TFLOPS = 5000.0       # MI355X dense FP8 MFMA
+HBM_PEAK_GBS = 8000.0
+
+
+def _parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--size", type=int, default=8192, help="m = n = k")
+    ap.add_argument("--m", type=int, default=None)
+    ap.add_argument("--n", type=int, default=None)
+    ap.add_argument("--k", type=int, default=None)
+    ap.add_argument("--moduli", type=int, default=12)
+    ap.add_argument("--phi", type=float, default=0.5)
+    ap.add_argument("--cpu-rows", type=int, default=48,
+                    help="rows of op(A) in the CPU oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-native", action="store_true")
+    ap.add_argument("--traffic", type=str, default=None,
+                    help="JSON file with measured HBM bytes per residue-product call")
+    return ap.parse_args()
+
+
+def _cpu_baseline(A, B, N, rows):
+    """The oracle, as it stands, on op(A)[:rows] x op(B): a bounded slab of the
+    same workload (its own emulated GEMM of shape rows x n x k)."""
+    import numpy as np
+    from oracle import ozaki2_ref as ref
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # noqa: BLE001
+        threads = os.cpu_count() or 1
+    Asub = np.ascontiguousarray(A[:rows])
+    t0 = time.perf_counter()
+    ref.emulate(Asub, B, N)
+    dt = time.perf_counter() - t0
+    m, k = Asub.shape
+    n = B.shape[1]
+    return {"value": 2.0 * m * n * k / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"oracle emulate() on op(A)[:{rows}] x op(B) ({m}x{n}x{k}, "
+                      f"N={N}), {dt:.1f} s wall"}
+
+
+def main():
+    args = _parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the emulation is a "
+              "single-GPU library and this build measures one MI355X.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2603_10634_amd as oz
+    from workloads import config_seed, phi_matrix
+    from workloads.reference import dd_dot_rows, normalised_error
+
+    m = args.m or args.size
+    n = args.n or args.size
+    k = args.k or args.size
+    N = args.moduli
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+
+    seed = config_seed(2, 0)
+    A = phi_matrix(m, k, args.phi, seed)          # op(A), m x k
+    B = phi_matrix(k, n, args.phi, seed + 1)      # op(B), k x n
+    # column-major storage: A (m x k, lda = m) is A.T in C order
+    tA = torch.from_numpy(np.ascontiguousarray(A.T)).to(dev)
+    tB = torch.from_numpy(np.ascontiguousarray(B.T)).to(dev)
+    tC = torch.empty((n, m), dtype=torch.float64, device=dev)
+
+    stream = torch.cuda.current_stream(dev)
+    oz.ozaki2_set_stream(stream)
+
+    def call():
+        st = oz.ozaki2_dgemm("N", "N", m, n, k, 1.0, tA, m, tB, k, 0.0, tC, m, N)
+        if st != 0:
+            raise oz.Ozaki2Error("ozaki2_dgemm", st)
+
+    for _ in range(args.warmup):
+        call()
+    torch.cuda.synchronize(dev)
+
+    # timed region: K calls; the library records HIP events between its kernel
+    # groups on `stream`, read back after each call
+    oz.ozaki2_set_timing(True)
+    ktimes = []
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        call()
+        ktimes.append(oz.ozaki2_get_kernel_times())
+    torch.cuda.synchronize(dev)
+    wall = time.perf_counter() - t0
+    oz.ozaki2_set_timing(False)
+    ms_per_step = wall / args.steps * 1e3
+    flops = 2.0 * m * n * k
+    value = flops / (ms_per_step * 1e-3) / 1e12
+    kt = np.array(ktimes)                        # steps x 6
+    k_mean = kt.mean(axis=0)
+    k_med = np.median(kt, axis=0)
+    step_med_ms = float(np.median(kt.sum(axis=1)))
+
+    # residue products (3 FP8 products per modulus) against the FP8 MFMA peak
+    gemm_ms = float(k_mean[4])
+    res_flops = 3 * N * flops
+    achieved = res_flops / (gemm_ms * 1e-3) / 1e12
+    traffic = None
+    if args.traffic and os.path.exists(args.traffic):
+        with open(args.traffic) as f:
+            traffic = json.load(f).get("bytes_per_call")
+    roofline = {"bound": "mfma", "achieved": round(achieved, 1), "peak": FP8_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP8_PEAK_TFLOPS, 4),
+                "traffic": traffic,
+                "kernel": "k_residue_gemm (square + Karatsuba launches), "
+                          f"{3 * N} FP8 products of {m}x{n}x{k} per call"}
+
+    # accuracy against a double-double reference on sampled rows
+    Cemu = tC.cpu().numpy().T                    # m x n
+    rows = np.array([0, m // 3, m - 1])
+    cols = np.arange(min(n, 2048))
+    hi, lo = dd_dot_rows(A[rows], B[:, cols])
+    absA = np.abs(A[rows])
+    absB = np.abs(B[:, cols])
+    err_emu = normalised_error(Cemu[np.ix_(rows, cols)], hi, lo, absA, absB)
+
+    native = None
+    if not args.no_native:
+        tAr = torch.from_numpy(A).to(dev)
+        tBr = torch.from_numpy(B).to(dev)
+        for _ in range(max(3, args.warmup // 3)):
+            Cn = torch.matmul(tAr, tBr)
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            Cn = torch.matmul(tAr, tBr)
+        torch.cuda.synchronize(dev)
+        nat_ms = (time.perf_counter() - t0) / args.steps * 1e3
+        Cn_h = Cn.cpu().numpy()
+        err_nat = normalised_error(Cn_h[np.ix_(rows, cols)], hi, lo, absA, absB)
+        native = {"tflops": round(flops / (nat_ms * 1e-3) / 1e12, 2), "ms": round(nat_ms, 3),
+                  "error_normalised": err_nat, "impl": "torch.matmul float64 (vendor BLAS)"}
+        del tAr, tBr, Cn
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = _cpu_baseline(A, B, N, min(args.cpu_rows, m))
+
+    stage = dict(zip(["quant", "gemms", "requant", "dequant", "others"],
+                     [float(k_med[0] + k_med[3]), float(k_med[1] + k_med[4]), 0.0,
+                      float(k_med[5]), float(k_med[2])]))
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp8e4m3-mfma->f64",
+        "data": "synthetic",
+        "config": {"workload": f"emulated dgemm {m}x{n}x{k} col-major NN, phi={args.phi}, "
+                               f"{N} moduli, accurate mode",
+                   "m": m, "n": n, "k": k, "num_moduli": N, "phi": args.phi,
+                   "alpha": 1.0, "beta": 0.0},
+        "error_normalised": err_emu,
+        "native_fp64": native,
+        "speedup_vs_native": (round(value / native["tflops"], 3) if native else None),
+        "mfma_util_pct": round(100 * achieved / FP8_PEAK_TFLOPS, 2),
+        "stage_ms_median": {kk: round(v, 4) for kk, v in stage.items()},
+        "kernel_ms_mean": [round(float(x), 4) for x in k_mean],
+        "step_ms_median_events": round(step_med_ms, 4),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

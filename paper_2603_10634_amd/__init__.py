@@ -1,0 +1,186 @@
+"""MI355X (gfx950) FP8 Ozaki-II DGEMM emulation: Python binding.
+
+A thin ctypes layer over liboz2.so, whose C ABI is declared in
+include/ozaki2.h.  Every function here only marshals arguments; all of the
+arithmetic runs in the library's HIP kernels.  Device memory and streams come
+from PyTorch.  There is no fallback: if the library is not built, or no
+gfx950 GPU is current, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+__all__ = [
+    "Ozaki2Error", "lib", "ozaki2_dgemm", "ozaki2_workspace_bytes", "ozaki2_set_stream",
+    "ozaki2_set_workspace", "ozaki2_set_timing", "ozaki2_get_stage_times",
+    "ozaki2_get_kernel_times", "ozaki2_moduli", "ozaki2_workspace_layout", "ozaki2_release",
+    "ozaki2_status_string", "dgemm", "LIB_PATH", "HEADER_PATH", "header_functions",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboz2.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "ozaki2.h")
+
+_i64 = ctypes.c_int64
+_vp = ctypes.c_void_p
+
+
+class Ozaki2Error(RuntimeError):
+    """A nonzero status returned by the library."""
+
+    def __init__(self, func: str, status: int):
+        self.status = status
+        super().__init__(f"{func} returned {status}: {ozaki2_status_string(status)}")
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded liboz2.so (loaded on first use)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is not built; run `python -m paper_2603_10634_amd.build` "
+            "(hipcc, gfx950) first")
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "ozaki2_dgemm": (ctypes.c_int, [ctypes.c_char, ctypes.c_char, _i64, _i64, _i64,
+                                        ctypes.c_double, _vp, _i64, _vp, _i64,
+                                        ctypes.c_double, _vp, _i64, ctypes.c_int]),
+        "ozaki2_workspace_bytes": (ctypes.c_size_t, [_i64, _i64, _i64, ctypes.c_int]),
+        "ozaki2_set_stream": (ctypes.c_int, [_vp]),
+        "ozaki2_set_workspace": (ctypes.c_int, [_vp, ctypes.c_size_t]),
+        "ozaki2_set_timing": (ctypes.c_int, [ctypes.c_int]),
+        "ozaki2_get_stage_times": (ctypes.c_int, [ctypes.POINTER(ctypes.c_float)]),
+        "ozaki2_get_kernel_times": (ctypes.c_int, [ctypes.POINTER(ctypes.c_float), ctypes.c_int]),
+        "ozaki2_moduli": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_int32)]),
+        "ozaki2_workspace_layout": (ctypes.c_int, [_i64, _i64, _i64, ctypes.c_int,
+                                                   ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+        "ozaki2_release": (ctypes.c_int, []),
+        "ozaki2_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def header_functions() -> list[str]:
+    """Names of the functions declared in include/ozaki2.h."""
+    with open(HEADER_PATH) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ozaki2_\w+)\s*\(", text)))
+
+
+def _ptr(x) -> int:
+    if x is None:
+        return 0
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _ch(c: str) -> bytes:
+    return c.encode() if isinstance(c, str) else bytes([c])
+
+
+def ozaki2_status_string(status: int) -> str:
+    return lib().ozaki2_status_string(int(status)).decode()
+
+
+def ozaki2_dgemm(transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                 num_moduli) -> int:
+    """Column-major C <- alpha op(A) op(B) + beta C (see include/ozaki2.h).
+    A, B, C are device pointers (int) or tensors; returns the status code."""
+    return lib().ozaki2_dgemm(_ch(transA), _ch(transB), m, n, k, float(alpha), _ptr(A), lda,
+                              _ptr(B), ldb, float(beta), _ptr(C), ldc, int(num_moduli))
+
+
+def ozaki2_workspace_bytes(m, n, k, num_moduli) -> int:
+    return lib().ozaki2_workspace_bytes(m, n, k, num_moduli)
+
+
+def ozaki2_set_stream(stream) -> int:
+    """stream: a torch.cuda.Stream, a raw hipStream_t (int) or None."""
+    raw = getattr(stream, "cuda_stream", stream)
+    return lib().ozaki2_set_stream(raw or None)
+
+
+def ozaki2_set_workspace(ptr, nbytes: int) -> int:
+    return lib().ozaki2_set_workspace(_ptr(ptr) or None, nbytes)
+
+
+def ozaki2_set_timing(on: bool) -> int:
+    return lib().ozaki2_set_timing(1 if on else 0)
+
+
+def ozaki2_get_stage_times() -> list[float]:
+    """[quant, gemms, requant, dequant, others] milliseconds of the last timed call."""
+    buf = (ctypes.c_float * 5)()
+    st = lib().ozaki2_get_stage_times(buf)
+    if st != 0:
+        raise Ozaki2Error("ozaki2_get_stage_times", st)
+    return list(buf)
+
+
+def ozaki2_get_kernel_times() -> list[float]:
+    """Per-kernel-group milliseconds of the last timed call (6 entries)."""
+    buf = (ctypes.c_float * 6)()
+    r = lib().ozaki2_get_kernel_times(buf, 6)
+    if r < 0:
+        raise Ozaki2Error("ozaki2_get_kernel_times", -r)
+    return list(buf)[:r]
+
+
+def ozaki2_moduli(num_moduli: int) -> tuple[list[int], list[int]]:
+    p = (ctypes.c_int32 * num_moduli)()
+    kinds = (ctypes.c_int32 * num_moduli)()
+    if lib().ozaki2_moduli(num_moduli, p, kinds) != 0:
+        raise ValueError(f"invalid number of moduli {num_moduli}")
+    return list(p), list(kinds)
+
+
+def ozaki2_workspace_layout(m, n, k, num_moduli) -> tuple[list[int], dict]:
+    off = (_i64 * 10)()
+    pads = (_i64 * 4)()
+    r = lib().ozaki2_workspace_layout(m, n, k, num_moduli, off, pads)
+    if r < 0:
+        raise ValueError("invalid sizes")
+    return list(off)[:r], dict(mp=pads[0], np=pads[1], kp=pads[2], M=pads[3])
+
+
+def ozaki2_release() -> int:
+    return lib().ozaki2_release()
+
+
+def dgemm(A, B, num_moduli: int = 12, alpha: float = 1.0, beta: float = 0.0, C=None):
+    """Row-major C = alpha A B + beta C for 2-D float64 CUDA tensors (via the
+    column-major identity C^T = B^T A^T).  Runs on torch's current stream."""
+    import torch
+
+    if A.dtype != torch.float64 or B.dtype != torch.float64:
+        raise TypeError("dgemm takes float64 tensors")
+    A = A.contiguous()
+    B = B.contiguous()
+    m, k = A.shape
+    k2, n = B.shape
+    if k != k2:
+        raise ValueError("inner dimensions differ")
+    if C is None:
+        C = torch.empty((m, n), dtype=torch.float64, device=A.device)
+        beta = 0.0
+    ozaki2_set_stream(torch.cuda.current_stream(A.device))
+    st = ozaki2_dgemm("N", "N", n, m, k, alpha, B, max(1, n), A, max(1, k), beta, C,
+                      max(1, n), num_moduli)
+    if st != 0:
+        raise Ozaki2Error("ozaki2_dgemm", st)
+    return C

@@ -1,0 +1,226 @@
+// Chinese-remainder reconstruction and inverse scaling (eqs.
+// CRT_finalreduction, inversescaling), fused with alpha/beta.
+//
+// Per output entry (i, j): u_l = C'_l mod p_l in [0, p_l) from the int16
+// planes; S = sum_l w_l u_l + floor(P/2) in 32-bit limbs (exact); R = S mod P;
+// C' = R - floor(P/2), which lies in (-P/2, P/2) by condition (3).  Then
+// Chat = C' 2^-(log2 mu_i + log2 nu_j) rounded once to nearest-even,
+// including gradual underflow, directly from the integer: no intermediate
+// floating-point rounding.  C = RN(alpha Chat) (+ RN(beta C_in)).
+#include "oz2_internal.h"
+
+namespace oz2 {
+
+namespace {
+
+// Bits [pos, pos + 64) of a little-endian limb array (zeros beyond the end).
+template <int L>
+__device__ __forceinline__ uint64_t window64(const uint32_t (&x)[L], int pos) {
+  const int w = pos >> 5, b = pos & 31;
+  uint32_t x0 = 0, x1 = 0, x2 = 0;
+#pragma unroll
+  for (int q = 0; q < L; ++q) {
+    x0 = (q == w) ? x[q] : x0;
+    x1 = (q == w + 1) ? x[q] : x1;
+    x2 = (q == w + 2) ? x[q] : x2;
+  }
+  const uint64_t lo = (uint64_t)x0 | ((uint64_t)x1 << 32);
+  if (b == 0) return lo;
+  return (lo >> b) | ((uint64_t)x2 << (64 - b));
+}
+
+// True if any bit below position pos is set.
+template <int L>
+__device__ __forceinline__ bool any_below(const uint32_t (&x)[L], int pos) {
+  uint32_t acc = 0;
+#pragma unroll
+  for (int q = 0; q < L; ++q) {
+    const int lo = 32 * q;
+    uint32_t mask;
+    if (pos >= lo + 32)
+      mask = 0xFFFFFFFFu;
+    else if (pos <= lo)
+      mask = 0u;
+    else
+      mask = (1u << (pos - lo)) - 1u;
+    acc |= x[q] & mask;
+  }
+  return acc != 0;
+}
+
+// RN-even of X 2^-t for a non-negative integer X (L limbs).
+template <int L>
+__device__ __forceinline__ double scaled_rn(const uint32_t (&X)[L], int t) {
+  int hb = -1;
+#pragma unroll
+  for (int q = 0; q < L; ++q)
+    if (X[q]) hb = 32 * q + 31 - __clz((int)X[q]);
+  if (hb < 0) return 0.0;
+  // position of the last kept bit: 53 significant bits, but not below 2^-1074
+  int lsb = hb - 52;
+  if (t - 1074 > lsb) lsb = t - 1074;
+  if (lsb < 0) lsb = 0;
+  uint64_t Q = window64<L>(X, lsb) & ((1ull << 54) - 1);  // <= 53 bits are set
+  if (lsb > 0) {
+    const bool rbit = (window64<L>(X, lsb - 1) & 1ull) != 0;
+    const bool sticky = any_below<L>(X, lsb - 1);
+    if (rbit && (sticky || (Q & 1ull))) Q += 1;
+  }
+  return ldexp((double)Q, lsb - t);
+}
+
+template <int L>
+__global__ __launch_bounds__(256) void k_crt(const int16_t *__restrict__ planes,
+                                             const int32_t *__restrict__ shift,
+                                             const uint32_t *__restrict__ flags,
+                                             const Tables *__restrict__ tab, int N, int64_t m,
+                                             int64_t n, int64_t mp, int64_t np, double alpha,
+                                             double beta, double *__restrict__ C, int64_t ldc) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t j = blockIdx.y;
+  if (i >= m) return;
+  const bool bad = ((flags[i] | flags[mp + j]) & kNonFinite) != 0;
+  double chat;
+  if (bad) {
+    chat = __longlong_as_double(0x7FF8000000000000ll);
+  } else {
+    // S = sum_l w_l u_l + floor(P/2), accumulated per limb in 64 bits
+    uint64_t acc[L + 1];
+#pragma unroll
+    for (int q = 0; q < L; ++q) acc[q] = tab->half[q];
+    acc[L] = 0;
+    const int16_t *pl = planes + j * mp + i;
+    const int64_t pstride = mp * np;
+    for (int l = 0; l < N; ++l) {
+      int u = pl[l * pstride];
+      const int p = tab->p[l];
+      if (u < 0) u += p;
+#pragma unroll
+      for (int q = 0; q < L; ++q) acc[q] += (uint64_t)tab->w[l][q] * (uint32_t)u;
+    }
+    uint32_t S[L + 1];
+    uint64_t carry = 0;
+#pragma unroll
+    for (int q = 0; q <= L; ++q) {
+      const uint64_t t = acc[q] + carry;
+      S[q] = (uint32_t)t;
+      carry = t >> 32;
+    }
+    // quotient estimate t ~ S / P (S < 2^16 P), then R = S - t P, corrected once
+    double sd = 0.0;
+#pragma unroll
+    for (int q = 0; q <= L; ++q) sd += ldexp((double)S[q], 32 * q);
+    int64_t tq = (int64_t)floor(sd / tab->P_d);
+    if (tq < 0) tq = 0;
+    uint32_t R[L + 1];
+    int64_t borrow = 0;
+    uint64_t mulc = 0;
+#pragma unroll
+    for (int q = 0; q <= L; ++q) {
+      const uint64_t pq = (q < L) ? (uint64_t)tab->P[q] : 0ull;
+      const uint64_t prod = pq * (uint64_t)tq + mulc;
+      mulc = prod >> 32;
+      const int64_t d = (int64_t)S[q] - (int64_t)(uint32_t)prod + borrow;
+      R[q] = (uint32_t)d;
+      borrow = d >> 32;  // 0 or -1
+    }
+    // R is now S - tq P as a two's-complement (L+1)-limb number
+    const bool negR = (R[L] >> 31) != 0;
+    if (negR) {  // add P back
+      uint64_t c = 0;
+#pragma unroll
+      for (int q = 0; q <= L; ++q) {
+        const uint64_t t = (uint64_t)R[q] + ((q < L) ? tab->P[q] : 0u) + c;
+        R[q] = (uint32_t)t;
+        c = t >> 32;
+      }
+    } else {  // subtract P if R >= P
+      bool ge = R[L] != 0;
+      bool decided = ge;
+#pragma unroll
+      for (int q = L - 1; q >= 0; --q) {
+        if (!decided && R[q] != tab->P[q]) {
+          ge = R[q] > tab->P[q];
+          decided = true;
+        }
+      }
+      if (!decided) ge = true;  // equal
+      if (ge) {
+        int64_t b = 0;
+#pragma unroll
+        for (int q = 0; q <= L; ++q) {
+          const int64_t d = (int64_t)R[q] - (int64_t)((q < L) ? tab->P[q] : 0u) + b;
+          R[q] = (uint32_t)d;
+          b = d >> 32;
+        }
+      }
+    }
+    // C' = R - floor(P/2): magnitude and sign
+    bool ge = false, decided = false;
+#pragma unroll
+    for (int q = L - 1; q >= 0; --q) {
+      if (!decided && R[q] != tab->half[q]) {
+        ge = R[q] > tab->half[q];
+        decided = true;
+      }
+    }
+    if (!decided) ge = true;
+    uint32_t mag[L];
+    int64_t b = 0;
+#pragma unroll
+    for (int q = 0; q < L; ++q) {
+      const int64_t d = ge ? (int64_t)R[q] - (int64_t)tab->half[q] + b
+                           : (int64_t)tab->half[q] - (int64_t)R[q] + b;
+      mag[q] = (uint32_t)d;
+      b = d >> 32;
+    }
+    const int t = shift[i] + shift[mp + j];
+    chat = scaled_rn<L>(mag, t);
+    if (!ge) chat = -chat;
+  }
+  double out = __dmul_rn(alpha, chat);
+  if (beta != 0.0) out = __dadd_rn(out, __dmul_rn(beta, C[i + j * ldc]));
+  C[i + j * ldc] = out;
+}
+
+__global__ void k_scal(int64_t m, int64_t n, double beta, double *__restrict__ C, int64_t ldc) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t j = blockIdx.y;
+  if (i >= m) return;
+  double *c = C + i + j * ldc;
+  *c = beta == 0.0 ? 0.0 : __dmul_rn(beta, *c);
+}
+
+}  // namespace
+
+hipError_t launch_crt(const Geometry &g, const Tables *dt, const Work &w, double alpha,
+                      double beta, double *C, int64_t ldc, int limbs, hipStream_t st) {
+  dim3 grid((unsigned)((g.m + 255) / 256), (unsigned)g.n);
+#define OZ2_CRT_CASE(LL)                                                                      \
+  case LL:                                                                                    \
+    hipLaunchKernelGGL(k_crt<LL>, grid, dim3(256), 0, st, w.planes, w.shift, w.flags, dt, g.N, \
+                       g.m, g.n, g.mp, g.np, alpha, beta, C, ldc);                            \
+    break;
+  switch (limbs) {
+    OZ2_CRT_CASE(1)
+    OZ2_CRT_CASE(2)
+    OZ2_CRT_CASE(3)
+    OZ2_CRT_CASE(4)
+    OZ2_CRT_CASE(5)
+    OZ2_CRT_CASE(6)
+    OZ2_CRT_CASE(7)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef OZ2_CRT_CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_scal(int64_t m, int64_t n, double beta, double *C, int64_t ldc, hipStream_t st) {
+  if (m == 0 || n == 0) return hipSuccess;
+  dim3 grid((unsigned)((m + 255) / 256), (unsigned)n);
+  hipLaunchKernelGGL(k_scal, grid, dim3(256), 0, st, m, n, beta, C, ldc);
+  return hipGetLastError();
+}
+
+}  // namespace oz2

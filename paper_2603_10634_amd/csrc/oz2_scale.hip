@@ -1,0 +1,137 @@
+// Scale exponents (Section III-E).
+//
+// For each row i of op(A) let r_i be the maximum over j of the bound product
+// (Abar Bbar)_ij, and likewise c_j for the columns of op(B).  The scale
+// exponent is e_i = max{e : 2^(2e+1) r_i <= P - 1}, giving log2 mu_i =
+// log2 mu'_i + e_i; this makes 2 mu_i nu_j sum |a||b| < P (condition (3)),
+// because each bound entry is at most sqrt(r_i c_j).
+//
+// The bound product runs on FP8 MFMA with FP32 accumulation, so the computed
+// maxima r'_i carry a rounding error: every entry satisfies |c' - c| <=
+// (k - 1) u c with u = 2^-24 (the summation bound the paper uses), which we
+// widen to gamma = k 2^-23 to also cover truncating accumulators.  When the
+// whole interval [r'(1 - gamma), r'(1 + 2 gamma)] gives the same exponent,
+// that exponent is the one of the exact r_i.  Lines whose interval straddles
+// a threshold are recomputed exactly: Abar and Bbar are multiples of 2^-9 up
+// to 256, so 2^18 (Abar Bbar)_ij is an integer below 2^52 for k <= 2^18 and is
+// summed exactly in 64-bit integers.  The result is a deterministic function
+// of the inputs, independent of the MFMA's summation order.
+#include "oz2_internal.h"
+
+namespace oz2 {
+
+namespace {
+
+// max{e : x 2^(2e+1) <= D} for a double x > 0, where D is the largest double
+// not above P - 1 (so for a double y, y <= P - 1 iff y <= D).
+__device__ __forceinline__ int exponent_rule(double x, double D) {
+  int ex, eD;
+  const double mx = frexp(x, &ex);
+  const double mD = frexp(D, &eD);
+  const int d = eD - ex - 1 - (mx > mD ? 1 : 0);
+  return d >= 0 ? d / 2 : -((-d + 1) / 2);  // floor(d / 2)
+}
+
+__global__ void k_scale_decide(const uint32_t *__restrict__ rmax, uint32_t *__restrict__ flags,
+                               int32_t *__restrict__ e, uint32_t *__restrict__ amb,
+                               int64_t lines, double gamma, const Tables *__restrict__ tab) {
+  const int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (L >= lines) return;
+  const float r = __uint_as_float(rmax[L]);
+  int ev = 0;
+  if (r > 0.0f && !(flags[L] & kZeroLine)) {
+    const double D = tab->D;
+    const double rd = (double)r;
+    const double lo = rd * (1.0 - gamma) * (1.0 - 0x1p-50);
+    const double hi = rd * (1.0 + 2.0 * gamma) * (1.0 + 0x1p-50);
+    const int e_small = exponent_rule(hi, D);
+    const int e_large = exponent_rule(lo, D);
+    ev = e_small;
+    if (e_small != e_large) {
+      const uint32_t slot = atomicAdd(&amb[0], 1u);
+      amb[1 + slot] = (uint32_t)L;
+      flags[L] |= kFixup;
+    }
+  }
+  e[L] = ev;
+}
+
+// Exact maxima of the bound product over the flagged lines.  Persistent: each
+// workgroup walks (line, block of 32 partner lines) items until all are done.
+__global__ __launch_bounds__(256) void k_scale_fixup(const uint8_t *__restrict__ Abar,
+                                                     const uint8_t *__restrict__ Bbar,
+                                                     int64_t mp, int64_t np, int64_t kp,
+                                                     const uint32_t *__restrict__ amb,
+                                                     uint64_t *__restrict__ rfix) {
+  const uint32_t count = amb[0];
+  const int64_t nblk = ((mp > np ? mp : np) + 31) / 32;
+  const int64_t items = (int64_t)count * nblk;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+    const int64_t L = amb[1 + it / nblk];
+    const int64_t blk = it % nblk;
+    const bool rowA = L < mp;
+    const uint8_t *own = rowA ? Abar + L * kp : Bbar + (L - mp) * kp;
+    const uint8_t *part = rowA ? Bbar : Abar;
+    const int64_t npart = rowA ? np : mp;
+    uint64_t best = 0;
+    for (int z = 0; z < 8; ++z) {
+      const int64_t j = blk * 32 + wave * 8 + z;
+      if (j >= npart) break;
+      const uint8_t *other = part + j * kp;
+      uint64_t sum = 0;
+      for (int64_t h = (int64_t)lane * 8; h < kp; h += 512) {
+        const uint64_t a8 = *(const uint64_t *)(own + h);
+        const uint64_t b8 = *(const uint64_t *)(other + h);
+#pragma unroll
+        for (int z8 = 0; z8 < 8; ++z8) {
+          const uint32_t ca = (uint32_t)(a8 >> (8 * z8)) & 0x7Fu;
+          const uint32_t cb = (uint32_t)(b8 >> (8 * z8)) & 0x7Fu;
+          // 2^9 x value of a non-negative E4M3 code: m (subnormal) or (8 + m) 2^(e - 1)
+          const uint32_t qa = (ca >> 3) ? (8u + (ca & 7u)) << ((ca >> 3) - 1) : (ca & 7u);
+          const uint32_t qb = (cb >> 3) ? (8u + (cb & 7u)) << ((cb >> 3) - 1) : (cb & 7u);
+          sum += (uint64_t)qa * qb;
+        }
+      }
+      for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+      best = sum > best ? sum : best;
+    }
+    if (lane == 0 && best) atomicMax((unsigned long long *)&rfix[L], (unsigned long long)best);
+  }
+}
+
+__global__ void k_scale_finalize(const uint32_t *__restrict__ flags,
+                                 const uint64_t *__restrict__ rfix, const int32_t *__restrict__ E,
+                                 int32_t *__restrict__ e, int32_t *__restrict__ shift,
+                                 int64_t lines, const Tables *__restrict__ tab) {
+  const int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (L >= lines) return;
+  int ev = e[L];
+  if (flags[L] & kFixup) {
+    const uint64_t r18 = rfix[L];  // 2^18 x the exact line maximum, < 2^53
+    ev = r18 ? exponent_rule(ldexp((double)r18, -18), tab->D) : 0;
+    e[L] = ev;
+  }
+  shift[L] = 7 - E[L] + ev;
+}
+
+}  // namespace
+
+hipError_t launch_scale(const Geometry &g, const Tables *dt, const Work &w, hipStream_t st) {
+  const int64_t lines = g.mp + g.np;
+  const unsigned blocks = (unsigned)((lines + 255) / 256);
+  const double gamma = ldexp((double)g.kp, -23);
+  hipLaunchKernelGGL(k_scale_decide, dim3(blocks), dim3(256), 0, st, w.rmax, w.flags, w.e, w.amb,
+                     lines, gamma, dt);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_scale_fixup, dim3(512), dim3(256), 0, st, w.Abar, w.Bbar, g.mp, g.np, g.kp,
+                     w.amb, w.rfix);
+  err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_scale_finalize, dim3(blocks), dim3(256), 0, st, w.flags, w.rfix, w.E, w.e,
+                     w.shift, lines, dt);
+  return hipGetLastError();
+}
+
+}  // namespace oz2

@@ -1,0 +1,188 @@
+// Host construction of the moduli and CRT constants.
+//
+// Moduli: the hybrid list of Section III-D.  Candidates are the squares s^2
+// (2 <= s <= 33) together with the integers 2..513, scanned in descending
+// order; a candidate is kept when it is coprime to every kept modulus.  This
+// puts 1089, 1024, 961, 841, 625, 529 first and continues 511, 509, 503, ...
+// Squares use the modular-reduction split with s = sqrt(p) (Section III-C),
+// the others the Karatsuba split with s = 16 (Section III-B).
+//
+// CRT: with P the product of the moduli, w_l = q_l P / p_l where q_l is the
+// inverse of P / p_l modulo p_l (eq. CRT_finalreduction), stored as 32-bit
+// little-endian limbs.
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "oz2_internal.h"
+
+namespace oz2 {
+namespace {
+
+using Big = std::vector<uint32_t>;  // little-endian base-2^32 digits
+
+int gcd_int(int a, int b) {
+  while (b) {
+    int t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+void big_mul_small(Big &x, uint32_t v) {
+  uint64_t carry = 0;
+  for (auto &d : x) {
+    uint64_t t = (uint64_t)d * v + carry;
+    d = (uint32_t)t;
+    carry = t >> 32;
+  }
+  if (carry) x.push_back((uint32_t)carry);
+}
+
+uint32_t big_mod_small(const Big &x, uint32_t p) {
+  uint64_t r = 0;
+  for (size_t i = x.size(); i-- > 0;) r = ((r << 32) | x[i]) % p;
+  return (uint32_t)r;
+}
+
+void big_sub_one(Big &x) {
+  for (auto &d : x) {
+    if (d-- != 0) break;
+  }
+}
+
+void big_shr1(Big &x) {
+  for (size_t i = 0; i < x.size(); ++i) {
+    x[i] >>= 1;
+    if (i + 1 < x.size()) x[i] |= (x[i + 1] & 1u) << 31;
+  }
+}
+
+int big_bits(const Big &x) {
+  for (size_t i = x.size(); i-- > 0;)
+    if (x[i]) return (int)(32 * i) + 32 - __builtin_clz(x[i]);
+  return 0;
+}
+
+// value of x rounded toward zero to 53 bits (round=false) or to nearest-ish
+// (round=true, used only as an estimate)
+double big_to_double(const Big &x, bool round) {
+  int nb = big_bits(x);
+  if (nb == 0) return 0.0;
+  // gather the top 64 bits
+  uint64_t top = 0;
+  int shift = nb - 64;  // bit position of the lowest gathered bit
+  for (int b = 0; b < 64; ++b) {
+    int pos = shift + b;
+    if (pos < 0) continue;
+    uint32_t bit = (x[pos / 32] >> (pos % 32)) & 1u;
+    top |= (uint64_t)bit << b;
+  }
+  // keep 53 bits
+  int drop = 64 - 53;
+  uint64_t mant = top >> drop;
+  if (round && ((top >> (drop - 1)) & 1u)) mant += 1;
+  return std::ldexp((double)mant, shift + drop);
+}
+
+int inv_mod(int a, int p) {  // a^{-1} mod p, gcd(a, p) = 1
+  int t = 0, nt = 1, r = p, nr = a % p;
+  while (nr) {
+    int q = r / nr;
+    int tmp = t - q * nt;
+    t = nt;
+    nt = tmp;
+    tmp = r - q * nr;
+    r = nr;
+    nr = tmp;
+  }
+  return t < 0 ? t + p : t;
+}
+
+std::vector<int> hybrid_list(int N) {
+  std::vector<int> cand;
+  for (int s = 2; s <= 33; ++s) cand.push_back(s * s);
+  for (int v = 2; v <= 513; ++v) cand.push_back(v);
+  std::sort(cand.begin(), cand.end(), [](int a, int b) { return a > b; });
+  cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+  std::vector<int> out;
+  for (int c : cand) {
+    if ((int)out.size() == N) break;
+    bool ok = true;
+    for (int q : out) ok = ok && gcd_int(c, q) == 1;
+    if (ok) out.push_back(c);
+  }
+  return out;
+}
+
+}  // namespace
+
+bool build_tables(int N, Tables *t) {
+  if (N < 1 || N > kMaxN) return false;
+  memset(t, 0, sizeof(*t));
+  std::vector<int> p = hybrid_list(N);
+  if ((int)p.size() != N) return false;
+  t->N = N;
+  int slice = 0;
+  for (int l = 0; l < N; ++l) {
+    int r = (int)std::lround(std::sqrt((double)p[l]));
+    bool square = r * r == p[l];
+    t->p[l] = p[l];
+    t->kind[l] = square ? 0 : 1;
+    t->s[l] = square ? r : 16;
+    t->slice0[l] = slice;
+    slice += square ? 2 : 3;
+    t->inv_p[l] = 1.0f / (float)p[l];
+    t->inv_pd[l] = 1.0 / (double)p[l];
+    t->smag[l] = (65536 + t->s[l] - 1) / t->s[l];
+    if (!square) {
+      // 16 t - 15 G2 = -15 (G2 + t') with t' = -16 t / 15 (mod p); p is coprime
+      // to 15 because 1089 = 3^2 11^2 and 625 = 5^4 precede every Karatsuba modulus
+      int c = (int)((int64_t)(p[l] - 16) * inv_mod(15 % p[l], p[l]) % p[l]);
+      if (c > p[l] - 1 - p[l] / 2) c -= p[l];
+      t->kinit[l] = c;
+    }
+    uint64_t v = 1;
+    for (int e = 0; e < 64; ++e) {
+      t->pow2lo[l][e] = (int32_t)v;
+      v = (v * 2) % p[l];
+    }
+    uint64_t v64 = v;  // 2^64 mod p
+    uint64_t acc = 1;
+    for (int e = 0; e < 4; ++e) {
+      t->pow2hi[l][e] = (int32_t)acc;
+      acc = (acc * v64) % p[l];
+    }
+    t->pow2_32[l] = t->pow2lo[l][32];
+  }
+  t->M = slice;
+
+  Big P{1};
+  for (int l = 0; l < N; ++l) big_mul_small(P, (uint32_t)p[l]);
+  int limbs = (int)P.size();
+  if (limbs + 1 > kLimbs) return false;
+  t->limbs = limbs;
+  for (int i = 0; i < limbs; ++i) t->P[i] = P[i];
+  Big half = P;
+  big_shr1(half);
+  for (size_t i = 0; i < half.size(); ++i) t->half[i] = half[i];
+  for (int l = 0; l < N; ++l) {
+    Big others{1};
+    for (int j = 0; j < N; ++j)
+      if (j != l) big_mul_small(others, (uint32_t)p[j]);
+    int q = inv_mod((int)big_mod_small(others, (uint32_t)p[l]), p[l]);
+    big_mul_small(others, (uint32_t)q);
+    if ((int)others.size() > limbs) return false;
+    for (size_t i = 0; i < others.size(); ++i) t->w[l][i] = others[i];
+  }
+  t->P_d = big_to_double(P, true);
+  Big Pm1 = P;
+  big_sub_one(Pm1);
+  t->D = big_to_double(Pm1, false);
+  return true;
+}
+
+}  // namespace oz2

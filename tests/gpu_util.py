@@ -1,0 +1,127 @@
+"""Helpers for the GPU tests: run the library through its C ABI on seeded
+inputs and read back the output and the intermediate buffers of the
+workspace."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+import paper_2603_10634_amd as oz
+from oracle import ozaki2_ref as ref
+from workloads import to_colmajor, from_colmajor
+
+
+def device():
+    return torch.device("cuda", 0)
+
+
+class Run:
+    """Output of one ozaki2_dgemm call."""
+
+    def __init__(self, status, C, ldc, m, n, ws=None, off=None, pads=None):
+        self.status = status
+        self.Cbuf = C
+        self.ldc = ldc
+        self.C = from_colmajor(C, m, n, ldc) if status == 0 and m and n else None
+        self.ws = ws
+        self.off = off
+        self.pads = pads
+        self.m, self.n = m, n
+
+    # ---- workspace views (see ozaki2_workspace_layout) ----
+    def _vec(self, idx, dtype, count):
+        o = self.off[idx]
+        return np.frombuffer(self.ws[o:o + count * np.dtype(dtype).itemsize].tobytes(), dtype=dtype)
+
+    def lines(self, idx, dtype=np.int32):
+        mp, np_ = self.pads["mp"], self.pads["np"]
+        v = self._vec(idx, dtype, mp + np_)
+        return v[:self.m], v[mp:mp + self.n]
+
+    def bar(self, which):
+        mp, np_, kp = self.pads["mp"], self.pads["np"], self.pads["kp"]
+        rows = mp if which == "A" else np_
+        o = self.off[3 if which == "A" else 4]
+        return self.ws[o:o + rows * kp].reshape(rows, kp)
+
+    def slices(self, which):
+        mp, np_, kp, M = self.pads["mp"], self.pads["np"], self.pads["kp"], self.pads["M"]
+        rows = mp if which == "A" else np_
+        o = self.off[5 if which == "A" else 6]
+        return self.ws[o:o + M * rows * kp].reshape(M, rows, kp)
+
+    def planes(self, N):
+        mp, np_ = self.pads["mp"], self.pads["np"]
+        o = self.off[7]
+        return np.frombuffer(self.ws[o:o + 2 * N * mp * np_].tobytes(),
+                             dtype=np.int16).reshape(N, np_, mp)
+
+
+def run(opA, opB, N, transA="N", transB="N", alpha=1.0, beta=0.0, Cin=None,
+        pad=(0, 0, 0), keep_ws=False, stream=None):
+    """Column-major ozaki2_dgemm on op(A) (m x k) and op(B) (k x n) given as
+    numpy arrays; leading-dimension padding is filled with NaN (A, B) or 7.0
+    (C) so reads or writes outside the views show."""
+    m, k = opA.shape
+    n = opB.shape[1]
+    Ab, lda = to_colmajor(opA, transA, ld=(max(1, m) if transA in "Nn" else max(1, k)) + pad[0])
+    Bb, ldb = to_colmajor(opB, transB, ld=(max(1, k) if transB in "Nn" else max(1, n)) + pad[1])
+    ldc = max(1, m) + pad[2]
+    Cmat = np.zeros((m, n)) if Cin is None else Cin
+    Cb, _ = to_colmajor(Cmat, "N", ld=ldc, fill=7.0)
+    dev = device()
+    tA = torch.from_numpy(Ab.copy()).to(dev)
+    tB = torch.from_numpy(Bb.copy()).to(dev)
+    tC = torch.from_numpy(Cb.copy()).to(dev)
+    wbytes = oz.ozaki2_workspace_bytes(m, n, k, N)
+    ws = torch.full((wbytes + 256,), 0xEE, dtype=torch.uint8, device=dev)
+    base = (ws.data_ptr() + 255) // 256 * 256
+    oz.ozaki2_set_workspace(base, wbytes)
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    oz.ozaki2_set_stream(s)
+    try:
+        st = oz.ozaki2_dgemm(transA, transB, m, n, k, alpha, tA, lda, tB, ldb, beta, tC, ldc, N)
+        torch.cuda.synchronize(dev)
+    finally:
+        oz.ozaki2_set_workspace(None, 0)
+    off = pads = None
+    wsh = None
+    if keep_ws:
+        off, pads = oz.ozaki2_workspace_layout(m, n, k, N)
+        shift = base - ws.data_ptr()
+        wsh = ws[shift:shift + wbytes].cpu().numpy()
+    return Run(st, tC.cpu().numpy(), ldc, m, n, wsh, off, pads)
+
+
+def check_stages(r: Run, opA, opB, N, st=None):
+    """Every stored intermediate equals the oracle's, bit for bit."""
+    if st is None:
+        _, st = ref.emulate(opA, opB, N, keep_stages=True)
+    m, k = opA.shape
+    n = opB.shape[1]
+    EA, EB = r.lines(1)
+    assert np.array_equal(EA, st["EA"]) and np.array_equal(EB, st["EB"]), "ufp exponents"
+    eA, eB = r.lines(2)
+    assert np.array_equal(eA, st["e"]) and np.array_equal(eB, st["f"]), "scale exponents"
+    sA, sB = r.lines(0)
+    assert np.array_equal(sA, st["sA"]) and np.array_equal(sB, st["sB"]), "shifts"
+    Ab = r.bar("A")
+    Bb = r.bar("B")
+    assert np.array_equal(Ab[:m, :k], ref.e4m3_encode_exact(st["Abar"])), "Abar"
+    assert np.array_equal(Bb[:n, :k], ref.e4m3_encode_exact(st["Bbar"].T)), "Bbar"
+    assert not Ab[m:].any() and not Ab[:, k:].any(), "Abar padding"
+    assert not Bb[n:].any() and not Bb[:, k:].any(), "Bbar padding"
+    SA = r.slices("A")
+    SB = r.slices("B")
+    sl = 0
+    for pm in st["per_modulus"]:
+        for dA, dB in zip(pm["dA"], pm["dB"]):
+            assert np.array_equal(SA[sl, :m, :k], ref.e4m3_encode_exact(dA)), f"A slice {sl}"
+            assert np.array_equal(SB[sl, :n, :k], ref.e4m3_encode_exact(dB.T)), f"B slice {sl}"
+            assert not SA[sl, m:].any() and not SA[sl, :, k:].any(), f"A slice {sl} padding"
+            assert not SB[sl, n:].any() and not SB[sl, :, k:].any(), f"B slice {sl} padding"
+            sl += 1
+    assert sl == r.pads["M"]
+    P = r.planes(N)
+    for l, plane in enumerate(st["planes"]):
+        assert np.array_equal(P[l, :n, :m].T.astype(np.int64), plane), f"plane {l}"

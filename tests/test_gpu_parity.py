@@ -1,0 +1,278 @@
+"""Parity of the HIP path with the CPU oracle, through the C ABI.
+
+Every stage the library stores (exponents, FP8 bound operands, FP8 digit
+slices, int16 residue planes) and the final C are compared bit for bit with
+the oracle on seeded inputs whose sizes span several tiles and leave ragged
+tails; the full-size workload is checked on sampled outputs."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2603_10634_amd as oz
+from oracle import ozaki2_ref as ref
+from workloads import phi_matrix, integer_matrix, normal_matrix, config_seed
+from workloads.reference import dd_dot_rows, normalised_error
+
+from gpu_util import run, check_stages
+
+pytestmark = pytest.mark.gpu
+
+
+def _inputs(m, n, k, phi, seed):
+    if phi is None:
+        return normal_matrix(m, k, seed), normal_matrix(k, n, seed + 1)
+    return phi_matrix(m, k, phi, seed), phi_matrix(k, n, phi, seed + 1)
+
+
+def _same(a, b):
+    """Bit-identical float64 arrays (NaN payloads aside)."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    both_nan = np.isnan(a) & np.isnan(b)
+    return bool(np.all(both_nan | (a.view(np.int64) == b.view(np.int64))))
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 6, 7, 12, 13, 20])
+def test_stage_parity_ragged(N):
+    print(f"stage parity N={N} shape=(300, 200, 700)", flush=True)
+    A, B = _inputs(300, 200, 700, 1.0, 1000 + N)
+    r = run(A, B, N, keep_ws=True)
+    assert r.status == 0
+    Chat, st = ref.emulate(A, B, N, keep_stages=True)
+    check_stages(r, A, B, N, st)
+    assert _same(r.C, Chat)
+
+
+@pytest.mark.parametrize("phi", [None, 0.5, 2.0, 4.0, 6.0])
+@pytest.mark.parametrize("shape", [(256, 256, 256), (129, 385, 200), (64, 64, 1),
+                                   (1, 300, 513), (520, 1, 77)])
+def test_parity_shapes(phi, shape):
+    m, n, k = shape
+    print(f"parity shape={shape} phi={phi}", flush=True)
+    A, B = _inputs(m, n, k, phi, 2000 + m + n + k)
+    r = run(A, B, 12, keep_ws=True)
+    assert r.status == 0
+    Chat, st = ref.emulate(A, B, 12, keep_stages=True)
+    check_stages(r, A, B, 12, st)
+    assert _same(r.C, Chat)
+
+
+def test_row_major_config_256():
+    # 256^3 row-major, entries (U-0.5) exp(0.5 N(0,1)), alpha 1, beta 0, N = 12
+    s = config_seed(1)
+    A = phi_matrix(256, 256, 0.5, s)
+    B = phi_matrix(256, 256, 0.5, s + 1)
+    tA = torch.from_numpy(A).cuda()
+    tB = torch.from_numpy(B).cuda()
+    C = oz.dgemm(tA, tB, 12)
+    torch.cuda.synchronize()
+    assert _same(C.cpu().numpy(), ref.emulate(A, B, 12))
+
+
+@pytest.mark.parametrize("ta,tb", [("N", "N"), ("N", "T"), ("T", "N"), ("T", "T"),
+                                   ("t", "c"), ("C", "n")])
+def test_transposes(ta, tb):
+    print(f"transposes {ta}{tb}", flush=True)
+    A, B = _inputs(190, 260, 333, 1.0, 3000)
+    want = ref.emulate(A, B, 12)
+    r = run(A, B, 12, transA=ta, transB=tb, pad=(3, 5, 2))
+    assert r.status == 0
+    assert _same(r.C, want)
+    # entries of C outside the m x n view are untouched
+    Cb = r.Cbuf.reshape(-1, r.ldc)
+    assert np.all(Cb[:, r.m:] == 7.0)
+
+
+@pytest.mark.parametrize("alpha,beta", [(1.0, 0.0), (-2.5, 0.0), (0.75, 1.0), (1.0, -0.5),
+                                        (0.0, 3.0), (0.0, 0.0)])
+def test_alpha_beta(alpha, beta):
+    A, B = _inputs(100, 90, 150, 1.0, 4000)
+    Cin = phi_matrix(100, 90, 1.0, 4002)
+    r = run(A, B, 12, alpha=alpha, beta=beta, Cin=Cin, pad=(0, 0, 4))
+    assert r.status == 0
+    if alpha == 0.0:
+        want = np.zeros_like(Cin) if beta == 0.0 else beta * Cin
+    else:
+        want = ref.combine_alpha_beta(ref.emulate(A, B, 12), alpha, beta, Cin)
+    assert _same(r.C, want)
+
+
+def test_beta_zero_does_not_read_C():
+    A, B = _inputs(70, 50, 40, 1.0, 4100)
+    Cin = np.full((70, 50), np.nan)
+    r = run(A, B, 12, Cin=Cin)
+    assert r.status == 0 and not np.any(np.isnan(r.C))
+
+
+def test_zero_lines_and_nonfinite():
+    A, B = _inputs(150, 140, 90, 1.0, 5000)
+    A[3, :] = 0.0
+    B[:, 7] = 0.0
+    A[10, 5] = np.inf
+    A[11, 0] = -np.inf
+    B[20, 9] = np.nan
+    r = run(A, B, 12, keep_ws=True)
+    assert r.status == 0
+    Chat, st = ref.emulate(A, B, 12, keep_stages=True)
+    assert _same(r.C, Chat)
+    assert np.all(np.isnan(r.C[10])) and np.all(np.isnan(r.C[:, 9]))
+    assert np.all(r.C[3, :9] == 0) and not np.signbit(r.C[3, :9]).any()
+    check_stages(r, A, B, 12, st)
+
+
+def test_subnormal_and_extreme_magnitudes():
+    A, B = _inputs(96, 80, 120, 1.0, 5100)
+    A[0] *= 2.0 ** -1060           # row of subnormals and tiny normals
+    A[1, :] = 0.0
+    A[1, 3] = 5e-324               # a lone smallest subnormal
+    A[2] *= 2.0 ** 900             # huge row
+    B[:, 0] *= 2.0 ** -1000
+    B[:, 1] *= 2.0 ** 1000
+    r = run(A, B, 12, keep_ws=True)
+    assert r.status == 0
+    Chat, st = ref.emulate(A, B, 12, keep_stages=True)
+    check_stages(r, A, B, 12, st)
+    assert _same(r.C, Chat)
+
+
+def test_integer_inputs_give_exact_product():
+    A = integer_matrix(200, 300, 1000, 5200)
+    B = integer_matrix(300, 150, 1000, 5201)
+    r = run(A, B, 12)
+    assert r.status == 0
+    assert np.array_equal(r.C, A @ B)      # |sums| < 2^53: the float64 matmul is exact
+
+
+@pytest.mark.parametrize("k", [32768, 40000, 65536, 65536 + 300])
+def test_long_k_chunks(k):
+    # beyond 2^15 the residue products are summed over several launches
+    print(f"long k={k}", flush=True)
+    A, B = _inputs(40, 72, k, 1.0, 6000 + k)
+    r = run(A, B, 12, keep_ws=True)
+    assert r.status == 0
+    Chat, st = ref.emulate(A, B, 12, keep_stages=True)
+    P = r.planes(12)
+    for l, plane in enumerate(st["planes"]):
+        assert np.array_equal(P[l, :72, :40].T.astype(np.int64), plane), f"plane {l}"
+    assert _same(r.C, Chat)
+
+
+def _constant_case(k):
+    """Constant op(A) = c 2^-7 and op(B) = d 2^-7 (c, d in [128, 256)) chosen
+    so that some digit product is 16 x 16: every FP8 product sum of that
+    modulus then reaches 256 k, the exactness limit's order at k = 2^15."""
+    for c in range(128, 256):
+        for d in (c, 255, 200, 129):
+            A = np.full((1, k), c / 128.0)
+            B = np.full((k, 1), d / 128.0)
+            _, st = ref.emulate(A, B, 12, keep_stages=True)
+            for pm in st["per_modulus"]:
+                pairs = ([(0, 1), (1, 0), (1, 1)] if pm["kind"] == "square"
+                         else [(0, 0), (1, 1), (2, 2)])
+                for x, y in pairs:
+                    if abs(int(pm["dA"][x][0, 0]) * int(pm["dB"][y][0, 0])) == 256:
+                        return c / 128.0, d / 128.0
+    raise AssertionError("no extreme-digit constant found")
+
+
+def test_extreme_digit_sums_exact():
+    # product sums of 256 k = 2^23 per FP8 product at k = 2^15 must be exact
+    k = 32768
+    a, b = _constant_case(k)
+    A = np.full((64, k), a)
+    B = np.full((k, 96), b)
+    A[1::2] *= -1.0
+    r = run(A, B, 12, keep_ws=True)
+    assert r.status == 0
+    Chat, st = ref.emulate(A, B, 12, keep_stages=True)
+    check_stages(r, A, B, 12, st)
+    assert _same(r.C, Chat)
+
+
+def test_bound_maxima_within_interval():
+    # the GPU's FP32 line maxima of the bound product bracket the exact ones
+    A, B = _inputs(300, 280, 1000, 2.0, 7000)
+    r = run(A, B, 12, keep_ws=True)
+    _, st = ref.emulate(A, B, 12, keep_stages=True)
+    rA, rB = r.lines(8, np.uint32)
+    gA = rA.view(np.float32).astype(np.float64)
+    gB = rB.view(np.float32).astype(np.float64)
+    kp = r.pads["kp"]
+    gamma = kp * 2.0 ** -23          # the window the library decides with
+    worst = 0.0
+    for g, exact18 in ((gA, st["r18"]), (gB, st["c18"])):
+        exact = np.ldexp(exact18, -18)
+        assert np.all(g >= exact * (1 - gamma)) and np.all(g <= exact * (1 + gamma))
+        nz = exact > 0
+        worst = max(worst, float(np.max(np.abs(g[nz] / exact[nz] - 1))))
+    print(f"bound maxima: worst relative error {worst:.3e} (k 2^-24 = {kp * 2.0 ** -24:.3e})")
+
+
+def test_deterministic_and_stream():
+    A, B = _inputs(257, 255, 300, 1.0, 8000)
+    r1 = run(A, B, 12)
+    s = torch.cuda.Stream()
+    r2 = run(A, B, 12, stream=s)
+    assert _same(r1.C, r2.C)
+
+
+def test_library_workspace_and_timing():
+    # library-owned workspace (grown on demand), per-stage timing
+    A, B = _inputs(300, 300, 300, 0.5, 9000)
+    tA = torch.from_numpy(A).cuda()
+    tB = torch.from_numpy(B).cuda()
+    oz.ozaki2_set_timing(True)
+    C = oz.dgemm(tA, tB, 12)
+    torch.cuda.synchronize()
+    times = oz.ozaki2_get_stage_times()
+    kt = oz.ozaki2_get_kernel_times()
+    oz.ozaki2_set_timing(False)
+    assert len(times) == 5 and all(t >= 0 for t in times) and times[1] > 0
+    assert len(kt) == 6
+    assert _same(C.cpu().numpy(), ref.emulate(A, B, 12))
+    oz.ozaki2_release()
+
+
+def test_workspace_too_small():
+    A, B = _inputs(64, 64, 64, 1.0, 9100)
+    ws = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    base = (ws.data_ptr() + 255) // 256 * 256
+    oz.ozaki2_set_workspace(base, 512)
+    try:
+        tA = torch.from_numpy(A).cuda()
+        tB = torch.from_numpy(B).cuda()
+        tC = torch.zeros((64, 64), dtype=torch.float64, device="cuda")
+        st = oz.ozaki2_dgemm("N", "N", 64, 64, 64, 1.0, tA, 64, tB, 64, 0.0, tC, 64, 12)
+    finally:
+        oz.ozaki2_set_workspace(None, 0)
+    assert st == 3
+
+
+def test_full_size_sampled():
+    # the benchmark workload: m = n = k = 8192, phi = 0.5, N = 12, in the
+    # benchmark's launch configuration; every line's shift is compared and C on
+    # sampled rows (all columns) and sampled columns (all rows)
+    n = 8192
+    s = config_seed(2, 0)
+    print("full size: generating", flush=True)
+    A = phi_matrix(n, n, 0.5, s)
+    B = phi_matrix(n, n, 0.5, s + 1)
+    print("full size: GPU", flush=True)
+    r = run(A, B, 12, keep_ws=False)
+    assert r.status == 0
+    rows = np.array([0, 1, 777, 4095, 8191])
+    cols = np.arange(n)
+    print("full size: oracle scaling", flush=True)
+    sc = ref.scaling(A, B, 12)
+    print("full size: oracle rows", flush=True)
+    Cs, _ = ref.products(sc, rows, cols)
+    assert _same(r.C[rows], Cs)
+    print("full size: oracle columns", flush=True)
+    cols2 = np.array([5, 4096, 8190])
+    Cs2, _ = ref.products(sc, np.arange(n), cols2)
+    assert _same(r.C[:, cols2], Cs2)
+    # FP64-level accuracy at the full-accuracy moduli count (phi = 0.5)
+    hi, lo = dd_dot_rows(A[rows[:2]], B[:, :1024])
+    err = normalised_error(r.C[rows[:2], :1024], hi, lo, np.abs(A[rows[:2]]), np.abs(B[:, :1024]))
+    print(f"full size: normalised error {err:.3e}", flush=True)
+    assert err <= 1e-15

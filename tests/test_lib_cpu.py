@@ -1,0 +1,104 @@
+"""Host-side checks of liboz2.so that need no GPU: the library loads, exports
+every function include/ozaki2.h declares, uses the same moduli as the oracle,
+lays its workspace out consistently and rejects invalid arguments before it
+touches a device."""
+import ctypes
+import subprocess
+
+import pytest
+
+import paper_2603_10634_amd as oz
+from oracle import ozaki2_ref as ref
+
+
+@pytest.fixture(scope="module")
+def L():
+    return oz.lib()
+
+
+def test_every_header_function_is_exported(L):
+    names = oz.header_functions()
+    assert "ozaki2_dgemm" in names and len(names) >= 10
+    out = subprocess.run(["nm", "-D", "--defined-only", oz.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    for n in names:
+        assert n in exported, n
+        assert hasattr(L, n)
+
+
+def test_moduli_match_oracle(L):
+    for N in range(1, 21):
+        p, kinds = oz.ozaki2_moduli(N)
+        want = ref.hybrid_moduli(N)
+        assert p == [q for q, _, _ in want]
+        assert kinds == [0 if k == "square" else 1 for _, k, _ in want]
+    with pytest.raises(ValueError):
+        oz.ozaki2_moduli(0)
+    with pytest.raises(ValueError):
+        oz.ozaki2_moduli(21)
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (300, 200, 700), (8192, 8192, 8192),
+                                   (1024, 1024, 65536), (16384, 16384, 1024)])
+@pytest.mark.parametrize("N", [1, 6, 7, 12, 20])
+def test_workspace_layout(shape, N):
+    m, n, k = shape
+    off, pads = oz.ozaki2_workspace_layout(m, n, k, N)
+    mp, np_, kp, M = pads["mp"], pads["np"], pads["kp"], pads["M"]
+    assert mp % 256 == 0 and np_ % 256 == 0 and kp % 256 == 0
+    assert mp >= m and np_ >= n and kp >= k and mp - m < 256 and kp - k < 256
+    assert M == sum(2 if kd == "square" else 3 for _, kd, _ in ref.hybrid_moduli(N))
+    total = oz.ozaki2_workspace_bytes(m, n, k, N)
+    assert all(o % 256 == 0 for o in off)
+    sizes = {0: 4 * (mp + np_), 1: 4 * (mp + np_), 2: 4 * (mp + np_), 3: mp * kp,
+             4: np_ * kp, 5: M * mp * kp, 6: M * np_ * kp, 7: 2 * N * mp * np_,
+             8: 4 * (mp + np_), 9: 4 * (mp + np_)}
+    spans = sorted((off[i], off[i] + sizes[i]) for i in range(8))
+    for (a0, a1), (b0, b1) in zip(spans, spans[1:]):
+        assert a1 <= b0                      # no overlap
+    assert max(e for _, e in spans) <= total
+
+
+def test_argument_errors(L):
+    d = 0  # no pointer is dereferenced on these paths
+    call = oz.ozaki2_dgemm
+    assert call("X", "N", 4, 4, 4, 1.0, d, 4, d, 4, 0.0, d, 4, 12) == -1
+    assert call("N", "Q", 4, 4, 4, 1.0, d, 4, d, 4, 0.0, d, 4, 12) == -2
+    assert call("N", "N", -1, 4, 4, 1.0, d, 4, d, 4, 0.0, d, 4, 12) == -3
+    assert call("N", "N", 4, -1, 4, 1.0, d, 4, d, 4, 0.0, d, 4, 12) == -4
+    assert call("N", "N", 4, 4, -1, 1.0, d, 4, d, 4, 0.0, d, 4, 12) == -5
+    assert call("N", "N", 4, 4, 4, 1.0, d, 3, d, 4, 0.0, d, 4, 12) == -8
+    assert call("T", "N", 4, 4, 5, 1.0, d, 4, d, 5, 0.0, d, 4, 12) == -8
+    assert call("N", "N", 4, 4, 4, 1.0, d, 4, d, 3, 0.0, d, 4, 12) == -10
+    assert call("N", "T", 4, 5, 4, 1.0, d, 4, d, 4, 0.0, d, 4, 12) == -10
+    assert call("N", "N", 4, 4, 4, 1.0, d, 4, d, 4, 0.0, d, 3, 12) == -13
+    assert call("N", "N", 4, 4, 4, 1.0, d, 4, d, 4, 0.0, d, 4, 0) == -14
+    assert call("N", "N", 4, 4, 4, 1.0, d, 4, d, 4, 0.0, d, 4, 21) == -14
+    # empty output: nothing to do, success without a device
+    assert call("N", "N", 0, 4, 4, 1.0, d, 1, d, 4, 0.0, d, 1, 12) == 0
+    assert call("n", "t", 4, 0, 4, 1.0, d, 4, d, 1, 0.0, d, 4, 12) == 0
+
+
+def test_no_device_reported_on_cpu(L):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    assert oz.ozaki2_dgemm("N", "N", 4, 4, 4, 1.0, 0, 4, 0, 4, 0.0, 0, 4, 12) == 5
+    assert "gfx950" in oz.ozaki2_status_string(5)
+
+
+def test_status_strings(L):
+    for code in (0, 1, 2, 3, 4, 5, -3):
+        assert oz.ozaki2_status_string(code)
+    assert oz.ozaki2_set_workspace(0x101, 1024) == -1      # misaligned
+    assert oz.ozaki2_set_workspace(None, 0) == 0
+    with pytest.raises(oz.Ozaki2Error):
+        oz.ozaki2_get_stage_times()                        # nothing timed yet
+
+
+def test_library_fails_loudly_when_missing(monkeypatch):
+    monkeypatch.setattr(oz, "_lib", None)
+    monkeypatch.setattr(oz, "LIB_PATH", "/nonexistent/liboz2.so")
+    with pytest.raises(ImportError):
+        oz.lib()

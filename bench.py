@@ -100,6 +100,12 @@ def main():
 
     stream = torch.cuda.current_stream(dev)
     oz.ozaki2_set_stream(stream)
+    # caller-owned workspace (so the fix-up count can be read back afterwards)
+    wbytes = oz.ozaki2_workspace_bytes(m, n, k, N)
+    ws = torch.empty(wbytes + 256, dtype=torch.uint8, device=dev)
+    ws_base = (ws.data_ptr() + 255) // 256 * 256
+    oz.ozaki2_set_workspace(ws_base, wbytes)
+    offs, _ = oz.ozaki2_workspace_layout(m, n, k, N)
 
     def call():
         st = oz.ozaki2_dgemm("N", "N", m, n, k, 1.0, tA, m, tB, k, 0.0, tC, m, N)
@@ -122,6 +128,8 @@ def main():
     torch.cuda.synchronize(dev)
     wall = time.perf_counter() - t0
     oz.ozaki2_set_timing(False)
+    o = ws_base - ws.data_ptr() + offs[10]
+    fixups = int(ws[o:o + 4].cpu().numpy().view(np.uint32)[0])
     ms_per_step = wall / args.steps * 1e3
     flops = 2.0 * m * n * k
     value = flops / (ms_per_step * 1e-3) / 1e12
@@ -200,6 +208,8 @@ def main():
         "speedup_vs_native": (round(value / native["tflops"], 3) if native else None),
         "mfma_util_pct": round(100 * achieved / FP8_PEAK_TFLOPS, 2),
         "stage_ms_median": {kk: round(v, 4) for kk, v in stage.items()},
+        "scale_fixup_lines": fixups,
+        "workspace_bytes": wbytes,
         "kernel_ms_mean": [round(float(x), 4) for x in k_mean],
         "step_ms_median_events": round(step_med_ms, 4),
         "roofline": roofline,

@@ -155,11 +155,13 @@ int ozaki2_moduli(int num_moduli, int32_t *p, int32_t *kinds);
  *   off[7] int16  [N x n_pad x m_pad]  C'_l, entry (i, j) at l*n_pad*m_pad + j*m_pad + i
  *   off[8] uint32 [m_pad + n_pad]  FP32 bits of the bound product's line maxima
  *   off[9] uint32 [m_pad + n_pad]  line flags: 1 non-finite, 2 all zero, 4 exact fix-up
+ *   off[10] uint32 [1 + m_pad + n_pad]  number of lines whose scale exponent
+ *          the FP8 bound could not settle (recomputed exactly), then their indices
  * Lines 0..m_pad-1 are rows of op(A), m_pad..m_pad+n_pad-1 columns of op(B).
  * Slices: modulus l contributes 2 (square) or 3 (Karatsuba) consecutive
  * slices, digit x1 first.  Also writes pads[0..2] = m_pad, n_pad, k_pad and
- * pads[3] = M when pads is not NULL.  Returns the number of offsets (10), or
- * a negative value for invalid sizes.
+ * pads[3] = M when pads is not NULL.  `off` must hold 11 entries.  Returns the
+ * number of offsets written (11), or a negative value for invalid sizes.
  */
 int ozaki2_workspace_layout(int64_t m, int64_t n, int64_t k, int num_moduli,
                             int64_t *off, int64_t *pads);

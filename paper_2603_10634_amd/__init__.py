@@ -150,7 +150,7 @@ def ozaki2_moduli(num_moduli: int) -> tuple[list[int], list[int]]:
 
 
 def ozaki2_workspace_layout(m, n, k, num_moduli) -> tuple[list[int], dict]:
-    off = (_i64 * 10)()
+    off = (_i64 * 11)()
     pads = (_i64 * 4)()
     r = lib().ozaki2_workspace_layout(m, n, k, num_moduli, off, pads)
     if r < 0:

@@ -40,7 +40,7 @@ int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 struct Layout {
   int64_t mp, np, kp;
   int M;
-  size_t off[16];
+  size_t off[17];
   size_t total;
 };
 
@@ -76,6 +76,7 @@ bool make_layout(int64_t m, int64_t n, int64_t k, int N, Layout *L) {
   take(7, sizeof(int16_t) * (size_t)N * L->mp * L->np);  // planes
   L->off[8] = L->off[12];
   L->off[9] = L->off[11];
+  L->off[16] = L->off[14];
   L->total = o;
   return true;
 }
@@ -176,15 +177,17 @@ int ozaki2_workspace_layout(int64_t m, int64_t n, int64_t k, int num_moduli, int
   if (m < 0 || n < 0 || k < 0 || num_moduli < 1 || num_moduli > OZ2_MAX_MODULI) return -1;
   Layout L;
   if (!make_layout(m, n, k, num_moduli, &L)) return -1;
-  if (off)
+  if (off) {
     for (int q = 0; q < 10; ++q) off[q] = (int64_t)L.off[q];
+    off[10] = (int64_t)L.off[16];
+  }
   if (pads) {
     pads[0] = L.mp;
     pads[1] = L.np;
     pads[2] = L.kp;
     pads[3] = L.M;
   }
-  return 10;
+  return 11;
 }
 
 int ozaki2_set_stream(void *stream) {

@@ -6,16 +6,24 @@
 // log2 mu'_i + e_i; this makes 2 mu_i nu_j sum |a||b| < P (condition (3)),
 // because each bound entry is at most sqrt(r_i c_j).
 //
-// The bound product runs on FP8 MFMA with FP32 accumulation, so the computed
-// maxima r'_i carry a rounding error: every entry satisfies |c' - c| <=
-// (k - 1) u c with u = 2^-24 (the summation bound the paper uses), which we
-// widen to gamma = k 2^-23 to also cover truncating accumulators.  When the
-// whole interval [r'(1 - gamma), r'(1 + 2 gamma)] gives the same exponent,
-// that exponent is the one of the exact r_i.  Lines whose interval straddles
-// a threshold are recomputed exactly: Abar and Bbar are multiples of 2^-9 up
-// to 256, so 2^18 (Abar Bbar)_ij is an integer below 2^52 for k <= 2^18 and is
-// summed exactly in 64-bit integers.  The result is a deterministic function
-// of the inputs, independent of the MFMA's summation order.
+// The bound product runs on FP8 MFMA, so the computed maxima r'_i carry an
+// error.  The paper bounds it by (k - 1) u with u = 2^-24, the bound for FP32
+// summation rounded to nearest; gfx950's FP8 MFMA does not meet it.  Measured
+// behaviour of v_mfma_f32_32x32x64_f8f6f4: products are summed in groups of
+// 8 consecutive k, and inside a group every product is truncated to the grid
+// 2^-13 below the group's largest product (smaller ones vanish); group sums
+// and the accumulator are then combined at FP32 precision, mostly truncating,
+// at most one FP32 rounding upwards per instruction.  For non-negative terms
+// that gives  r' (1 - (k/64 + 2) 2^-23) <= r <= r' / (1 - g),
+// g = 7 2^-13 + (k/7) 2^-23; the decision window uses 2g.  When the whole
+// window gives the same exponent, it is the exponent of the exact r_i.  Lines
+// whose window straddles a threshold are recomputed exactly: Abar and Bbar are
+// multiples of 2^-9 up to 256, so 2^18 (Abar Bbar)_ij is an integer below
+// 2^52 for k <= 2^18 and is summed exactly in 64-bit integers.  The result is
+// a deterministic function of the inputs, independent of the MFMA's
+// summation order.  (Integer digit products stay exact: every product is an
+// integer of magnitude <= 256, far inside the 2^-13 window, and every partial
+// sum is at most 2^24.)
 #include "oz2_internal.h"
 
 namespace oz2 {
@@ -34,7 +42,8 @@ __device__ __forceinline__ int exponent_rule(double x, double D) {
 
 __global__ void k_scale_decide(const uint32_t *__restrict__ rmax, uint32_t *__restrict__ flags,
                                int32_t *__restrict__ e, uint32_t *__restrict__ amb,
-                               int64_t lines, double gamma, const Tables *__restrict__ tab) {
+                               int64_t lines, double g_lo, double g_hi,
+                               const Tables *__restrict__ tab) {
   const int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (L >= lines) return;
   const float r = __uint_as_float(rmax[L]);
@@ -42,8 +51,8 @@ __global__ void k_scale_decide(const uint32_t *__restrict__ rmax, uint32_t *__re
   if (r > 0.0f && !(flags[L] & kZeroLine)) {
     const double D = tab->D;
     const double rd = (double)r;
-    const double lo = rd * (1.0 - gamma) * (1.0 - 0x1p-50);
-    const double hi = rd * (1.0 + 2.0 * gamma) * (1.0 + 0x1p-50);
+    const double lo = rd * (1.0 - g_lo) * (1.0 - 0x1p-50);
+    const double hi = rd * (1.0 + 2.0 * g_hi) * (1.0 + 0x1p-50);  // >= r' / (1 - g_hi)
     const int e_small = exponent_rule(hi, D);
     const int e_large = exponent_rule(lo, D);
     ev = e_small;
@@ -120,9 +129,11 @@ __global__ void k_scale_finalize(const uint32_t *__restrict__ flags,
 hipError_t launch_scale(const Geometry &g, const Tables *dt, const Work &w, hipStream_t st) {
   const int64_t lines = g.mp + g.np;
   const unsigned blocks = (unsigned)((lines + 255) / 256);
-  const double gamma = ldexp((double)g.kp, -23);
+  const double kp = (double)g.kp;
+  const double g_lo = (kp / 64.0 + 2.0) * 0x1p-23;
+  const double g_hi = 2.0 * (7.0 * 0x1p-13 + (kp / 7.0) * 0x1p-23);
   hipLaunchKernelGGL(k_scale_decide, dim3(blocks), dim3(256), 0, st, w.rmax, w.flags, w.e, w.amb,
-                     lines, gamma, dt);
+                     lines, g_lo, g_hi, dt);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(k_scale_fixup, dim3(512), dim3(256), 0, st, w.Abar, w.Bbar, g.mp, g.np, g.kp,

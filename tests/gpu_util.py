@@ -38,6 +38,10 @@ class Run:
         v = self._vec(idx, dtype, mp + np_)
         return v[:self.m], v[mp:mp + self.n]
 
+    def fixups(self):
+        """Number of lines whose scale exponent was settled by the exact fix-up."""
+        return int(self._vec(10, np.uint32, 1)[0])
+
     def bar(self, which):
         mp, np_, kp = self.pads["mp"], self.pads["np"], self.pads["kp"]
         rows = mp if which == "A" else np_

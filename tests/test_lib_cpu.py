@@ -54,6 +54,7 @@ def test_workspace_layout(shape, N):
     sizes = {0: 4 * (mp + np_), 1: 4 * (mp + np_), 2: 4 * (mp + np_), 3: mp * kp,
              4: np_ * kp, 5: M * mp * kp, 6: M * np_ * kp, 7: 2 * N * mp * np_,
              8: 4 * (mp + np_), 9: 4 * (mp + np_)}
+    assert len(off) == 11 and off[10] % 256 == 0
     spans = sorted((off[i], off[i] + sizes[i]) for i in range(8))
     for (a0, a1), (b0, b1) in zip(spans, spans[1:]):
         assert a1 <= b0                      # no overlap

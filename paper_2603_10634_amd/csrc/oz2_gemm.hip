@@ -16,23 +16,42 @@
 //
 // Workgroup: 256 threads (4 waves), tile 256 (j) x 128 (i); each wave owns a
 // 128 x 64 block as 4 x 2 MFMA tiles of 32 x 32.  K advances 64 per stage
-// through a double-buffered LDS ring; the next stage's global loads are in
-// flight while the current stage's MFMAs run.
+// through an LDS ring of S stages filled by direct global-to-LDS loads
+// (global_load_lds_dwordx4) issued S - 1 stages ahead, so HBM/L2 latency
+// hides behind S - 1 stages of MFMAs; no VGPRs stage the operands.  LDS rows
+// are 64 B with the four 16 B chunks of row r XOR-swizzled by
+// ((r >> 1) ^ (r >> 3)) & 3, which keeps the fragment reads (ds_read_b128)
+// free of bank conflicts.
 #include "oz2_internal.h"
 
 namespace oz2 {
 
 namespace {
 
+typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v8i __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr int TJ = 256;                  // tile rows (j, from B's slices)
 constexpr int TI = 128;                  // tile columns (i, from A's slices)
 constexpr int BK = 64;                   // k per stage (one MFMA step)
-constexpr int LROW = BK + 16;            // LDS row stride: +16 B keeps ds_read_b128 conflict-free
-constexpr int BSZ = TJ * LROW;           // bytes of one B-side slice tile
-constexpr int ASZ = TI * LROW;           // bytes of one A-side slice tile
+constexpr int ROWB = 64;                 // LDS bytes per tile row
+constexpr int BSZ = TJ * ROWB;           // bytes of one B-side slice tile
+constexpr int ASZ = TI * ROWB;           // bytes of one A-side slice tile
+constexpr int LDS_RING = 147456;         // 144 KB: 3 stages of 2 slices or 6 of 1
+
+__device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
+
+// s_waitcnt with only the vector-memory counter constrained (gfx9 encoding:
+// vmcnt[3:0], expcnt[6:4], lgkmcnt[11:8], vmcnt[5:4] at [15:14])
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 0xF) | (0x7 << 4) | (0xF << 8) | ((N >> 4) << 14));
+}
+__device__ __forceinline__ void wait_lgkm0() {
+  __builtin_amdgcn_s_waitcnt(0xF | (0x7 << 4) | (0x0 << 8) | (0x3 << 14));
+}
 
 enum Pattern { kSquare = 0, kKara1 = 1, kOne = 2 };
 
@@ -42,84 +61,95 @@ __device__ __forceinline__ v16f mfma_f8(v8i a, v8i b, v16f c) {
   return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 0, 0, 0);
 }
 
-// Operand fragment of a 32-row sub-tile: lane l holds row (l % 32) and 32
-// consecutive k bytes starting at 32 * (l / 32).  Both MFMA operands are read
-// with the same k assignment, so the dot products pair matching k.
+// Operand fragment of a 32-row sub-tile: lane l holds row (l % 32) and the 32
+// k bytes of logical chunks 2 (l / 32) and 2 (l / 32) + 1.  Both MFMA operands
+// are read with the same k assignment, so the dot products pair matching k.
 __device__ __forceinline__ v8i lds_frag(const uint8_t *tile, int row0) {
   const int lane = threadIdx.x & 63;
-  const uint8_t *p = tile + (row0 + (lane & 31)) * LROW + (lane >> 5) * 32;
-  const uint4 lo = *(const uint4 *)p;
-  const uint4 hi = *(const uint4 *)(p + 16);
-  v8i f;
-  f[0] = (int)lo.x; f[1] = (int)lo.y; f[2] = (int)lo.z; f[3] = (int)lo.w;
-  f[4] = (int)hi.x; f[5] = (int)hi.y; f[6] = (int)hi.z; f[7] = (int)hi.w;
-  return f;
+  const int r = row0 + (lane & 31);
+  const int g = lane >> 5;
+  const int f = swz(r);
+  const uint8_t *row = tile + r * ROWB;
+  const v4i lo = *(const v4i *)(row + 16 * ((2 * g) ^ f));
+  const v4i hi = *(const v4i *)(row + 16 * ((2 * g + 1) ^ f));
+  return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
 }
 
-// Global -> register prefetch of one stage: NS slices per side, 16 bytes per
-// chunk; B side 256 rows x 4 chunks, A side 128 rows x 4 chunks.
+// Issue the direct-to-LDS loads of one stage (64 k) of NS slices per side into
+// `buf`: NS x (4 + 2) instructions per wave, each filling 1 KB = 16 tile rows.
+// Lane L of the instruction for rows 16q..16q+15 fetches row 16q + L/4, chunk
+// (L & 3) ^ swz(row), which lands at physical chunk L & 3.
 template <int NS>
-struct Prefetch {
-  uint4 b[NS][4];
-  uint4 a[NS][2];
-};
-
-template <int NS>
-__device__ __forceinline__ void stage_load(Prefetch<NS> &pf, const uint8_t *const *gB,
-                                           const uint8_t *const *gA, int64_t kp, int64_t kofs) {
-  const int tid = threadIdx.x;
+__device__ __forceinline__ void stage_issue(const uint8_t *const *gB, const uint8_t *const *gA,
+                                            int64_t kp, int64_t kofs, uint8_t *buf) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rsub = lane >> 2, pc = lane & 3;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int c = tid + 256 * q;
-      pf.b[s][q] = *(const uint4 *)(gB[s] + (int64_t)(c >> 2) * kp + kofs + (c & 3) * 16);
+    for (int u = 0; u < 4; ++u) {
+      const int q = wave + 4 * u;
+      const int r = 16 * q + rsub;
+      const uint8_t *src = gB[s] + (int64_t)r * kp + kofs + 16 * (pc ^ swz(r));
+      __builtin_amdgcn_global_load_lds(
+          (const void *)src,
+          (__attribute__((address_space(3))) void *)(buf + s * BSZ + q * 1024), 16, 0, 0);
     }
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int c = tid + 256 * q;
-      pf.a[s][q] = *(const uint4 *)(gA[s] + (int64_t)(c >> 2) * kp + kofs + (c & 3) * 16);
+    for (int u = 0; u < 2; ++u) {
+      const int q = wave + 4 * u;
+      const int r = 16 * q + rsub;
+      const uint8_t *src = gA[s] + (int64_t)r * kp + kofs + 16 * (pc ^ swz(r));
+      __builtin_amdgcn_global_load_lds(
+          (const void *)src,
+          (__attribute__((address_space(3))) void *)(buf + NS * BSZ + s * ASZ + q * 1024), 16,
+          0, 0);
     }
   }
 }
 
-template <int NS>
-__device__ __forceinline__ void stage_store(const Prefetch<NS> &pf, uint8_t *base) {
-  const int tid = threadIdx.x;
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int c = tid + 256 * q;
-      *(uint4 *)(base + s * BSZ + (c >> 2) * LROW + (c & 3) * 16) = pf.b[s][q];
-    }
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int c = tid + 256 * q;
-      *(uint4 *)(base + NS * BSZ + s * ASZ + (c >> 2) * LROW + (c & 3) * 16) = pf.a[s][q];
-    }
+// Wait until this wave's loads of the current stage have landed while the
+// `ahead` later stages (each NS x 6 loads per lane) may stay in flight.
+template <int NS, int S>
+__device__ __forceinline__ void wait_stage(int ahead) {
+  constexpr int L = NS * 6;
+  if (S > 5 && ahead >= 4) {
+    wait_vm<(S > 5 ? 4 : 0) * L>();
+  } else if (S > 4 && ahead == 3) {
+    wait_vm<(S > 4 ? 3 : 0) * L>();
+  } else if (S > 3 && ahead == 2) {
+    wait_vm<(S > 3 ? 2 : 0) * L>();
+  } else if (ahead == 1) {
+    wait_vm<L>();
+  } else {
+    wait_vm<0>();
   }
 }
 
 // Accumulate over nk stages of 64 k.  gB[s] / gA[s] point at row j0 / i0 of
-// the s-th B-side / A-side slice; `lds` holds 2 stages of NS slices per side.
-// The prefetch of the stage after the last re-reads the last stage (in
-// bounds) and is discarded.
+// the s-th B-side / A-side slice.  S-stage ring in `lds`; one barrier per
+// stage both publishes the stage's loads and frees the buffer of the previous
+// stage for the refill issued right after it.
 template <int NS, int PAT>
 __device__ __forceinline__ void kloop(const uint8_t *const *gB, const uint8_t *const *gA,
                                       int64_t kp, int64_t kbeg, int nk, uint8_t *lds,
                                       v16f (&acc0)[4][2], v16f (&acc1)[4][2]) {
   constexpr int STAGE = NS * (BSZ + ASZ);
+  constexpr int S = NS == 2 ? 3 : 6;
+  static_assert(S * STAGE <= LDS_RING, "LDS ring");
   const int wave = threadIdx.x >> 6;
   const int wj = wave >> 1, wi = wave & 1;
-  Prefetch<NS> pf;
-  stage_load<NS>(pf, gB, gA, kp, kbeg);
-  stage_store<NS>(pf, lds);
-  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < S - 1; ++t)
+    if (t < nk) stage_issue<NS>(gB, gA, kp, kbeg + (int64_t)t * BK, lds + t * STAGE);
   for (int kt = 0; kt < nk; ++kt) {
-    const int nxt = kt + 1 < nk ? kt + 1 : kt;
-    stage_load<NS>(pf, gB, gA, kp, kbeg + (int64_t)nxt * BK);
-    const uint8_t *base = lds + (kt & 1) * STAGE;
+    const int ahead = (nk - 1 - kt) < (S - 2) ? (nk - 1 - kt) : (S - 2);
+    wait_stage<NS, S>(ahead);
+    __builtin_amdgcn_s_barrier();
+    if (kt + S - 1 < nk)
+      stage_issue<NS>(gB, gA, kp, kbeg + (int64_t)(kt + S - 1) * BK,
+                      lds + ((kt + S - 1) % S) * STAGE);
+    const uint8_t *base = lds + (kt % S) * STAGE;
     const uint8_t *lb0 = base;
     const uint8_t *la0 = base + NS * BSZ;
     if (PAT == kSquare) {
@@ -172,9 +202,11 @@ __device__ __forceinline__ void kloop(const uint8_t *const *gB, const uint8_t *c
         for (int ti = 0; ti < 2; ++ti) acc0[tj][ti] = mfma_f8(fb, fa[ti], acc0[tj][ti]);
       }
     }
-    if (kt + 1 < nk) stage_store<NS>(pf, lds + ((kt + 1) & 1) * STAGE);
-    __syncthreads();
+    // this stage's LDS reads complete before any wave passes the next barrier
+    wait_lgkm0();
   }
+  // the ring is free for the next use only when every wave is done with it
+  __builtin_amdgcn_s_barrier();
 }
 
 __device__ __forceinline__ void zero_acc(v16f (&a)[4][2]) {
@@ -200,14 +232,15 @@ __device__ __forceinline__ int smod_i32(int v, int p, float inv_p) {
 // KIND 0: square moduli (blockIdx.z = l), KIND 1: Karatsuba moduli
 // (blockIdx.z = l - l0).
 template <int KIND>
-__global__ __launch_bounds__(256, 1) void k_residue_gemm(const uint8_t *__restrict__ Asl,
-                                                         const uint8_t *__restrict__ Bsl,
+// (operand pointers carry no __restrict__: the prefetch fence in kloop must be
+// able to order their loads)
+__global__ __launch_bounds__(256, 1) void k_residue_gemm(const uint8_t *Asl, const uint8_t *Bsl,
                                                          int16_t *__restrict__ planes,
                                                          const Tables *__restrict__ tab,
                                                          int64_t mp, int64_t np, int64_t kp,
                                                          int64_t kbeg, int nk, int accumulate,
                                                          int l0) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * 2 * (BSZ + ASZ)];
+  __shared__ __attribute__((aligned(1024))) uint8_t lds[LDS_RING];
   const int l = l0 + blockIdx.z;
   const int64_t i0 = (int64_t)blockIdx.x * TI;
   const int64_t j0 = (int64_t)blockIdx.y * TJ;
@@ -282,12 +315,11 @@ __global__ __launch_bounds__(256, 1) void k_residue_gemm(const uint8_t *__restri
   }
 }
 
-__global__ __launch_bounds__(256, 1) void k_bound_gemm(const uint8_t *__restrict__ Abar,
-                                                       const uint8_t *__restrict__ Bbar,
+__global__ __launch_bounds__(256, 1) void k_bound_gemm(const uint8_t *Abar, const uint8_t *Bbar,
                                                        int64_t kp, int nk,
                                                        uint32_t *__restrict__ rmaxA,
                                                        uint32_t *__restrict__ rmaxB) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * (BSZ + ASZ)];
+  __shared__ __attribute__((aligned(1024))) uint8_t lds[LDS_RING];
   const int64_t i0 = (int64_t)blockIdx.x * TI;
   const int64_t j0 = (int64_t)blockIdx.y * TJ;
   v16f acc0[4][2], acc1[4][2];

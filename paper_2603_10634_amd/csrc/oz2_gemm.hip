@@ -75,138 +75,250 @@ __device__ __forceinline__ v8i lds_frag(const uint8_t *tile, int row0) {
   return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
 }
 
-// Issue the direct-to-LDS loads of one stage (64 k) of NS slices per side into
-// `buf`: NS x (4 + 2) instructions per wave, each filling 1 KB = 16 tile rows.
-// Lane L of the instruction for rows 16q..16q+15 fetches row 16q + L/4, chunk
-// (L & 3) ^ swz(row), which lands at physical chunk L & 3.
-template <int NS>
-__device__ __forceinline__ void stage_issue(const uint8_t *const *gB, const uint8_t *const *gA,
-                                            int64_t kp, int64_t kofs, uint8_t *buf) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+// One direct-to-LDS load: each lane fetches 16 B at `base` + `voff`; the
+// wave's 64 chunks land contiguously at LDS byte address `lds_off` (held in
+// M0).  It is issued from inline asm so that the compiler's wait-count
+// analysis does not see an LDS write in flight (which would turn every
+// LDS-read wait in the K-loop into a full drain); the K-loop waits for these
+// loads itself with explicit vmcnt counts.
+__device__ __forceinline__ void dma16(const uint8_t *base, uint32_t voff, uint32_t lds_off) {
+  asm volatile("global_load_lds_dwordx4 %0, %1" ::"v"(voff), "s"(base), "{m0}"(lds_off)
+               : "memory");
+}
+
+__device__ __forceinline__ uint32_t lds_offset(const uint8_t *p) {
+  return (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const uint8_t *)p;
+}
+
+// Per-lane source offsets of the direct-to-LDS loads within a slice: the
+// instruction for tile rows 16q..16q+15 (q = wave + 4u) has lane L fetch row
+// 16q + L/4, logical chunk (L & 3) ^ swz(row), which lands at physical chunk
+// L & 3 of the row.  ob[u] serve the 256-row B side, oa[u] the 128-row A side.
+struct DmaOffsets {
+  uint32_t ob[4], oa[2];
+  uint32_t lds_wave;  // 1024 * wave: this wave's first 1 KB in each tile
+};
+
+__device__ __forceinline__ DmaOffsets dma_offsets(int64_t kp) {
+  DmaOffsets d;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int rsub = lane >> 2, pc = lane & 3;
 #pragma unroll
-  for (int s = 0; s < NS; ++s) {
+  for (int u = 0; u < 4; ++u) {
+    const int r = 16 * (wave + 4 * u) + rsub;
+    d.ob[u] = (uint32_t)(r * kp) + 16u * (uint32_t)(pc ^ swz(r));
+    if (u < 2) d.oa[u] = d.ob[u];
+  }
+  d.lds_wave = 1024u * (uint32_t)wave;
+  return d;
+}
+
+// Direct-to-LDS load number `idx` (0 .. 6 NS - 1) of one stage (64 k) of NS
+// slices per side: per slice four 1 KB loads of the 256-row B-side tile and
+// two of the 128-row A-side tile, each filling 16 rows.  `slot` is the LDS
+// byte address of the stage's ring slot; gB[s] / gA[s] + kofs are the
+// wave-uniform bases of the stage in global memory.
+template <int NS>
+__device__ __forceinline__ void dma_one(int idx, const uint8_t *const *gB,
+                                        const uint8_t *const *gA, const DmaOffsets &d,
+                                        int64_t kofs, uint32_t slot) {
+  const int s = idx / 6, t = idx % 6;
+  const uint32_t w = slot + d.lds_wave;
+  if (t < 4)
+    dma16(gB[s] + kofs, d.ob[t], w + s * BSZ + t * 4096);
+  else
+    dma16(gA[s] + kofs, d.oa[t - 4], w + NS * BSZ + s * ASZ + (t - 4) * 4096);
+}
+
+// The loads of a stage are issued in four parts; part q is loads
+// [q L / 4, (q + 1) L / 4) with L = 6 NS.
+template <int NS, int Q>
+__device__ __forceinline__ void dma_part(const uint8_t *const *gB, const uint8_t *const *gA,
+                                         const DmaOffsets &d, int64_t kofs, uint32_t slot) {
+  constexpr int L = 6 * NS;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int q = wave + 4 * u;
-      const int r = 16 * q + rsub;
-      const uint8_t *src = gB[s] + (int64_t)r * kp + kofs + 16 * (pc ^ swz(r));
-      __builtin_amdgcn_global_load_lds(
-          (const void *)src,
-          (__attribute__((address_space(3))) void *)(buf + s * BSZ + q * 1024), 16, 0, 0);
-    }
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int q = wave + 4 * u;
-      const int r = 16 * q + rsub;
-      const uint8_t *src = gA[s] + (int64_t)r * kp + kofs + 16 * (pc ^ swz(r));
-      __builtin_amdgcn_global_load_lds(
-          (const void *)src,
-          (__attribute__((address_space(3))) void *)(buf + NS * BSZ + s * ASZ + q * 1024), 16,
-          0, 0);
-    }
+  for (int idx = Q * L / 4; idx < (Q + 1) * L / 4; ++idx) {
+    dma_one<NS>(idx, gB, gA, d, kofs, slot);
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
-// Wait until this wave's loads of the current stage have landed while the
-// `ahead` later stages (each NS x 6 loads per lane) may stay in flight.
-template <int NS, int S>
-__device__ __forceinline__ void wait_stage(int ahead) {
-  constexpr int L = NS * 6;
-  if (S > 5 && ahead >= 4) {
-    wait_vm<(S > 5 ? 4 : 0) * L>();
-  } else if (S > 4 && ahead == 3) {
-    wait_vm<(S > 4 ? 3 : 0) * L>();
-  } else if (S > 3 && ahead == 2) {
-    wait_vm<(S > 3 ? 2 : 0) * L>();
-  } else if (ahead == 1) {
-    wait_vm<L>();
+// s_waitcnt vmcnt(a L) for a run-time a in [0, A] (larger a: A L)
+template <int L, int A>
+__device__ __forceinline__ void wait_stages(int a) {
+  if constexpr (A > 0) {
+    if (a >= A) {
+      wait_vm<A * L>();
+      return;
+    }
+    wait_stages<L, A - 1>(a);
   } else {
     wait_vm<0>();
   }
 }
 
+// Register fragments: fa[s][ti] is A-side slice s, 32-row block ti of this
+// wave's 64 rows; fb[s][tj] is B-side slice s, block tj of its 128 rows.
+// The i-th MFMA of block row tj (G per block row: 6 square, 4 Karatsuba
+// first pass, 2 single product).  Two products into one accumulator sit at
+// least 4 MFMAs apart.
+//   kSquare: slices 0 = x1, 1 = x2; acc0 += A2 B2, acc1 += A1 B2 + A2 B1
+//   kKara1:  slices 0 = x1, 1 = x3; acc0 += A3 B3, acc1 += A1 B1
+//   kOne:    acc0 += A B
+template <int PAT>
+constexpr int group_size() { return PAT == kSquare ? 6 : PAT == kKara1 ? 4 : 2; }
+
+template <int PAT, int NS>
+__device__ __forceinline__ void mfma_i(int i, int tj, const v8i (&fa)[NS][2],
+                                       const v8i (&fb)[NS][4], v16f (&acc0)[4][2],
+                                       v16f (&acc1)[4][2]) {
+  if (PAT == kSquare) {
+    if (i < 2) acc1[tj][i] = mfma_f8(fb[1][tj], fa[0][i], acc1[tj][i]);
+    else if (i < 4) acc0[tj][i - 2] = mfma_f8(fb[1][tj], fa[1][i - 2], acc0[tj][i - 2]);
+    else acc1[tj][i - 4] = mfma_f8(fb[0][tj], fa[1][i - 4], acc1[tj][i - 4]);
+  } else if (PAT == kKara1) {
+    if (i < 2) acc1[tj][i] = mfma_f8(fb[0][tj], fa[0][i], acc1[tj][i]);
+    else acc0[tj][i - 2] = mfma_f8(fb[NS - 1][tj], fa[NS - 1][i - 2], acc0[tj][i - 2]);
+  } else {
+    acc0[tj][i] = mfma_f8(fb[0][tj], fa[0][i], acc0[tj][i]);
+  }
+}
+
 // Accumulate over nk stages of 64 k.  gB[s] / gA[s] point at row j0 / i0 of
-// the s-th B-side / A-side slice.  S-stage ring in `lds`; one barrier per
-// stage both publishes the stage's loads and frees the buffer of the previous
-// stage for the refill issued right after it.
+// the s-th B-side / A-side slice.  Stage j sits in ring slot j % S.
+//
+// Schedule of iteration j (four block rows tj of G MFMAs each):
+//   tj = 0..2: first the B-side fragments of block row tj + 1 of stage j are
+//     read, then the MFMAs of block row tj issue with part tj + 1 of the loads
+//     of stage j + S - 1 between them;
+//   barrier B_j: before it each wave waits until its own loads of stage j + 1
+//     have landed and its LDS reads of stage j are complete, so after it
+//     stage j + 1 is readable by all and slot j % S is free;
+//   tj = 3: its MFMAs issue with part 0 of the loads of stage j + S (into
+//     slot j % S) and the reads of stage j + 1's A-side fragments and first
+//     B-side block row between them, so that LDS latency and the barrier hide
+//     behind MFMAs already in registers.
+// Loads are issued S - 2 to S - 1 stages before their barrier; at B_j the
+// loads of stages j + 2 .. j + S - 1 may still be in flight.
+template <int NS, int PAT>
+__device__ __forceinline__ void stage_iter(int j, int nk, const uint8_t *const *gB,
+                                           const uint8_t *const *gA, const DmaOffsets &d,
+                                           int64_t kbeg, const uint8_t *lds, uint32_t ring,
+                                           const v8i (&fa)[NS][2], v8i (&fan)[NS][2],
+                                           v8i (&fb)[NS][4], v16f (&acc0)[4][2],
+                                           v16f (&acc1)[4][2]) {
+  constexpr int STAGE = NS * (BSZ + ASZ);
+  constexpr int S = NS == 2 ? 3 : 6;
+  constexpr int L = 6 * NS;
+  constexpr int G = group_size<PAT>();
+  const int wave = threadIdx.x >> 6;
+  const int wj = wave >> 1, wi = wave & 1;
+  const uint8_t *cur = lds + (j % S) * STAGE;
+  const bool ld_prev = j + S - 1 < nk;  // parts 1..3 of stage j + S - 1
+  const bool ld_next = j + S < nk;      // part 0 of stage j + S
+  const bool rd_next = j + 1 < nk;
+  const int64_t kofs_prev = kbeg + (int64_t)(j + S - 1) * BK;
+  const uint32_t slot_prev = ring + ((j + S - 1) % S) * STAGE;
+#pragma unroll
+  for (int tj = 0; tj < 3; ++tj) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) fb[s][tj + 1] = lds_frag(cur + s * BSZ, wj * 128 + (tj + 1) * 32);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      mfma_i<PAT, NS>(i, tj, fa, fb, acc0, acc1);
+      __builtin_amdgcn_sched_barrier(0);
+      if (i == 0 && ld_prev) {
+        if (tj == 0) dma_part<NS, 1>(gB, gA, d, kofs_prev, slot_prev);
+        if (tj == 1) dma_part<NS, 2>(gB, gA, d, kofs_prev, slot_prev);
+        if (tj == 2) dma_part<NS, 3>(gB, gA, d, kofs_prev, slot_prev);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  // barrier B_j
+  wait_lgkm0();
+  if (rd_next) {
+    wait_stages<L, S - 2>(nk - 2 - j);
+  }
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_sched_barrier(0);
+  const uint8_t *nxt = lds + ((j + 1) % S) * STAGE;
+#pragma unroll
+  for (int i = 0; i < G; ++i) {
+    mfma_i<PAT, NS>(i, 3, fa, fb, acc0, acc1);
+    __builtin_amdgcn_sched_barrier(0);
+    if (i == 0 && ld_next)
+      dma_part<NS, 0>(gB, gA, d, kbeg + (int64_t)(j + S) * BK, ring + (j % S) * STAGE);
+    if (rd_next) {
+      // 3 NS fragment reads spread over the G - 1 gaps after MFMAs 0 .. G - 2
+#pragma unroll
+      for (int f = 0; f < 3 * NS; ++f) {
+        if (f * (G - 1) / (3 * NS) != i) continue;
+        if (f < 2 * NS)
+          fan[f / 2][f % 2] = lds_frag(nxt + NS * BSZ + (f / 2) * ASZ, wi * 64 + (f % 2) * 32);
+        else
+          fb[f - 2 * NS][0] = lds_frag(nxt + (f - 2 * NS) * BSZ, wj * 128);
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 template <int NS, int PAT>
 __device__ __forceinline__ void kloop(const uint8_t *const *gB, const uint8_t *const *gA,
                                       int64_t kp, int64_t kbeg, int nk, uint8_t *lds,
                                       v16f (&acc0)[4][2], v16f (&acc1)[4][2]) {
   constexpr int STAGE = NS * (BSZ + ASZ);
   constexpr int S = NS == 2 ? 3 : 6;
+  constexpr int L = 6 * NS;
   static_assert(S * STAGE <= LDS_RING, "LDS ring");
   const int wave = threadIdx.x >> 6;
   const int wj = wave >> 1, wi = wave & 1;
+  const DmaOffsets d = dma_offsets(kp);
+  const uint32_t ring = lds_offset(lds);
+  // prologue: stages 0 .. S - 2 and part 0 of stage S - 1
 #pragma unroll
   for (int t = 0; t < S - 1; ++t)
-    if (t < nk) stage_issue<NS>(gB, gA, kp, kbeg + (int64_t)t * BK, lds + t * STAGE);
-  for (int kt = 0; kt < nk; ++kt) {
-    const int ahead = (nk - 1 - kt) < (S - 2) ? (nk - 1 - kt) : (S - 2);
-    wait_stage<NS, S>(ahead);
-    __builtin_amdgcn_s_barrier();
-    if (kt + S - 1 < nk)
-      stage_issue<NS>(gB, gA, kp, kbeg + (int64_t)(kt + S - 1) * BK,
-                      lds + ((kt + S - 1) % S) * STAGE);
-    const uint8_t *base = lds + (kt % S) * STAGE;
-    const uint8_t *lb0 = base;
-    const uint8_t *la0 = base + NS * BSZ;
-    if (PAT == kSquare) {
-      // slices: 0 = digit x1, 1 = digit x2.  acc0 += A2 B2, acc1 += A1 B2 + A2 B1
-      const uint8_t *lb1 = lb0 + BSZ, *la1 = la0 + ASZ;
-      v8i fa1[2], fa2[2];
+    if (t < nk) {
 #pragma unroll
-      for (int ti = 0; ti < 2; ++ti) {
-        fa1[ti] = lds_frag(la0, wi * 64 + ti * 32);
-        fa2[ti] = lds_frag(la1, wi * 64 + ti * 32);
-      }
-#pragma unroll
-      for (int tj = 0; tj < 4; ++tj) {
-        const v8i fb1 = lds_frag(lb0, wj * 128 + tj * 32);
-        const v8i fb2 = lds_frag(lb1, wj * 128 + tj * 32);
-#pragma unroll
-        for (int ti = 0; ti < 2; ++ti) {
-          acc0[tj][ti] = mfma_f8(fb2, fa2[ti], acc0[tj][ti]);
-          acc1[tj][ti] = mfma_f8(fb2, fa1[ti], acc1[tj][ti]);
-          acc1[tj][ti] = mfma_f8(fb1, fa2[ti], acc1[tj][ti]);
-        }
-      }
-    } else if (PAT == kKara1) {
-      // slices: 0 = digit x1, 1 = digit x3.  acc0 += A3 B3, acc1 += A1 B1
-      const uint8_t *lb1 = lb0 + BSZ, *la1 = la0 + ASZ;
-      v8i fa1[2], fa3[2];
-#pragma unroll
-      for (int ti = 0; ti < 2; ++ti) {
-        fa1[ti] = lds_frag(la0, wi * 64 + ti * 32);
-        fa3[ti] = lds_frag(la1, wi * 64 + ti * 32);
-      }
-#pragma unroll
-      for (int tj = 0; tj < 4; ++tj) {
-        const v8i fb1 = lds_frag(lb0, wj * 128 + tj * 32);
-        const v8i fb3 = lds_frag(lb1, wj * 128 + tj * 32);
-#pragma unroll
-        for (int ti = 0; ti < 2; ++ti) {
-          acc0[tj][ti] = mfma_f8(fb3, fa3[ti], acc0[tj][ti]);
-          acc1[tj][ti] = mfma_f8(fb1, fa1[ti], acc1[tj][ti]);
-        }
-      }
-    } else {
-      v8i fa[2];
-#pragma unroll
-      for (int ti = 0; ti < 2; ++ti) fa[ti] = lds_frag(la0, wi * 64 + ti * 32);
-#pragma unroll
-      for (int tj = 0; tj < 4; ++tj) {
-        const v8i fb = lds_frag(lb0, wj * 128 + tj * 32);
-#pragma unroll
-        for (int ti = 0; ti < 2; ++ti) acc0[tj][ti] = mfma_f8(fb, fa[ti], acc0[tj][ti]);
-      }
+      for (int idx = 0; idx < L; ++idx)
+        dma_one<NS>(idx, gB, gA, d, kbeg + (int64_t)t * BK, ring + t * STAGE);
     }
-    // this stage's LDS reads complete before any wave passes the next barrier
-    wait_lgkm0();
+  if (S - 1 < nk) dma_part<NS, 0>(gB, gA, d, kbeg + (int64_t)(S - 1) * BK, ring + (S - 1) * STAGE);
+  if (S - 1 < nk)
+    wait_vm<(S - 2) * L + L / 4>();
+  else
+    wait_stages<L, S - 2>(nk - 1);
+  __builtin_amdgcn_s_barrier();
+  v8i fa0[NS][2], fa1[NS][2], fb[NS][4];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti) fa0[s][ti] = lds_frag(lds + NS * BSZ + s * ASZ, wi * 64 + ti * 32);
+    fb[s][0] = lds_frag(lds + s * BSZ, wj * 128);
   }
+  // two stages per trip so that the A-side fragment buffers alternate by name
+  int j = 0;
+  for (; j + 1 < nk; j += 2) {
+    stage_iter<NS, PAT>(j, nk, gB, gA, d, kbeg, lds, ring, fa0, fa1, fb, acc0, acc1);
+    stage_iter<NS, PAT>(j + 1, nk, gB, gA, d, kbeg, lds, ring, fa1, fa0, fb, acc0, acc1);
+  }
+  if (j < nk) stage_iter<NS, PAT>(j, nk, gB, gA, d, kbeg, lds, ring, fa0, fa1, fb, acc0, acc1);
   // the ring is free for the next use only when every wave is done with it
   __builtin_amdgcn_s_barrier();
+}
+
+// Values the epilogue needs are loaded with scalar loads, which complete out
+// of order with LDS reads on the shared LGKM counter: while one is pending,
+// every LDS wait in the K-loop degrades to a full drain.  Consuming them in an
+// empty asm before the loop makes them resident first.
+__device__ __forceinline__ void resident(int a, int b, int c, int d) {
+  asm volatile("" ::"s"(a), "s"(b), "s"(c), "s"(d));
+}
+__device__ __forceinline__ void resident_ptr(const void *a, const void *b) {
+  asm volatile("" ::"s"(a), "s"(b));
 }
 
 __device__ __forceinline__ void zero_acc(v16f (&a)[4][2]) {
@@ -224,8 +336,10 @@ __device__ __forceinline__ int smod_i32(int v, int p, float inv_p) {
   const int lo = -(p >> 1), hi = p - 1 - (p >> 1);
   const int q = (int)rintf((float)v * inv_p);
   int r = v - q * p;
-  if (r > hi) r -= p;
-  if (r < lo) r += p;
+  // branch-free corrections (sign masks rather than compare masks, which the
+  // scheduler would otherwise keep live in scalar register pairs)
+  r -= p & ((hi - r) >> 31);
+  r += p & ((r - lo) >> 31);
   return r;
 }
 
@@ -247,6 +361,10 @@ __global__ __launch_bounds__(256, 1) void k_residue_gemm(const uint8_t *Asl, con
   const int sl0 = tab->slice0[l];
   const int p = tab->p[l];
   const float inv = tab->inv_p[l];
+  const int sv = KIND == 0 ? tab->s[l] : tab->kinit[l];
+  resident(sl0, p, __float_as_int(inv), sv);
+  resident_ptr(planes, planes);
+  resident(accumulate, accumulate, accumulate, accumulate);
   const int64_t sA = mp * kp, sB = np * kp;
   const uint8_t *A0 = Asl + (int64_t)sl0 * sA + i0 * kp;
   const uint8_t *B0 = Bsl + (int64_t)sl0 * sB + j0 * kp;
@@ -271,7 +389,7 @@ __global__ __launch_bounds__(256, 1) void k_residue_gemm(const uint8_t *Asl, con
     const uint8_t *gB[2] = {B0, B0 + sB};
     const uint8_t *gA[2] = {A0, A0 + sA};
     kloop<2, kSquare>(gB, gA, kp, kbeg, nk, lds, acc0, acc1);
-    const int s = tab->s[l];
+    const int s = sv;
     // eq. 3matmult-notKaratsuba: s (A1 B2 + A2 B1) + A2 B2 (mod s^2)
 #pragma unroll
     for (int tj = 0; tj < 4; ++tj)
@@ -290,16 +408,20 @@ __global__ __launch_bounds__(256, 1) void k_residue_gemm(const uint8_t *Asl, con
     // t = 15 C1 + C3.  Modulo p this is -15 (C2 + t'), t' = kinit t: the
     // second pass starts its accumulator at t' (|t'| < 256, so the sum stays
     // an exact FP32 integer) and adds C2 on top.
-    const int kinit = tab->kinit[l];
+    const int kinit = sv;
 #pragma unroll
     for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
       for (int ti = 0; ti < 2; ++ti)
+      {
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
           const int t = smod_i32(15 * (int)acc1[tj][ti][v] + (int)acc0[tj][ti][v], p, inv);
           acc0[tj][ti][v] = (float)smod_i32(kinit * t, p, inv);
         }
+        // one 16-value tile at a time keeps the compare masks few
+        __builtin_amdgcn_sched_barrier(0);
+      }
     {
       const uint8_t *gB[1] = {B0 + sB};
       const uint8_t *gA[1] = {A0 + sA};
@@ -326,6 +448,7 @@ __global__ __launch_bounds__(256, 1) void k_bound_gemm(const uint8_t *Abar, cons
   zero_acc(acc0);
   const uint8_t *gB[1] = {Bbar + j0 * kp};
   const uint8_t *gA[1] = {Abar + i0 * kp};
+  resident_ptr(rmaxA, rmaxB);
   kloop<1, kOne>(gB, gA, kp, 0, nk, lds, acc0, acc1);
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;

@@ -166,8 +166,81 @@ int ozaki2_moduli(int num_moduli, int32_t *p, int32_t *kinds);
 int ozaki2_workspace_layout(int64_t m, int64_t n, int64_t k, int num_moduli,
                             int64_t *off, int64_t *pads);
 
-/* ozaki2_release - free the calling thread's library-owned workspace and
- * timing events. */
+/*
+ * ozaki2_dgemm_batched - `count` independent emulated DGEMMs
+ *   C_q <- alpha_q op(A_q) op(B_q) + beta_q C_q,  q = 0 .. count-1,
+ * of any (uneven) shapes, all with num_moduli moduli.  Every argument after
+ * `count` except num_moduli is a HOST array of `count` entries with the
+ * meaning ozaki2_dgemm gives it (the pointer arrays hold device pointers).
+ * Each C_q is bit-identical to what ozaki2_dgemm returns for problem q.
+ *
+ * Execution: each kernel family of the method (line maxima, bound operands,
+ * bound product, scale exponents, residues and digits, residue products per
+ * k chunk, CRT) runs as ONE grouped launch over all problems, whose blocks
+ * are mapped to (problem, tile) through prefix sums of per-problem tile
+ * counts; the residue products may run persistently (one workgroup per CU
+ * looping over tiles) and in largest-problem-first order, as chosen by the
+ * autotuner (ozaki2_set_autotune).  Problems are packed into sub-batches whose
+ * workspaces fit the workspace at once; sub-batches run one after another.
+ * The per-batch descriptors are built on the host and uploaded once per
+ * distinct argument list (the last 8 are cached per thread, with their
+ * captured graphs, see ozaki2_set_graph).
+ *
+ * Workspace: problem q of a sub-batch uses the layout of
+ * ozaki2_workspace_layout at the sum of ozaki2_workspace_bytes of the
+ * sub-batch's earlier problems.  A caller workspace (ozaki2_set_workspace)
+ * must hold the largest problem; the library-owned one grows to the whole
+ * batch (ozaki2_workspace_bytes_batched), capped at 16 GiB.
+ *
+ * Returns 0; -i for invalid argument i in the order of this signature
+ * (1 count < 0, 2 transA, 3 transB, 4 m, 5 n, 6 k, 7 alpha, 8 A, 9 lda,
+ * 10 B, 11 ldb, 12 beta, 13 C, 14 ldc, 15 num_moduli; an array argument is
+ * invalid when it is NULL or any entry is), nothing launched; or a positive
+ * OZ2_ERR_* code.  Problems with m or n = 0 are skipped; k = 0 or alpha = 0
+ * scales C by beta as in ozaki2_dgemm.  Timing (ozaki2_get_kernel_times)
+ * covers batched calls that run as one sub-batch outside graph mode.
+ */
+int ozaki2_dgemm_batched(int count, const char *transA, const char *transB,
+                         const int64_t *m, const int64_t *n, const int64_t *k,
+                         const double *alpha, const double *const *A, const int64_t *lda,
+                         const double *const *B, const int64_t *ldb, const double *beta,
+                         double *const *C, const int64_t *ldc, int num_moduli);
+
+/* ozaki2_workspace_bytes_batched - workspace for running the whole batch as
+ * one sub-batch (the sum of ozaki2_workspace_bytes over problems with
+ * m, n, k > 0); 0 for invalid sizes. */
+size_t ozaki2_workspace_bytes_batched(int count, const int64_t *m, const int64_t *n,
+                                      const int64_t *k, int num_moduli);
+
+/*
+ * ozaki2_set_graph - when on, the calling thread's ozaki2_dgemm and
+ * ozaki2_dgemm_batched calls capture their launch sequence in a hipGraph the
+ * first time an argument list (sizes, scalars, pointers, workspace) is seen,
+ * on a private stream, and replay that graph on the set stream at every call
+ * with the same arguments.  Captured graphs contain kernels only (buffers are
+ * cleared by kernels, not memset nodes).  Replays need the workspace and the
+ * matrices at the same addresses, which the argument match guarantees.
+ * Timing is not recorded in graph mode.
+ */
+int ozaki2_set_graph(int on);
+
+/*
+ * ozaki2_set_autotune - when on, the first batched call of a new set of
+ * problem shapes times the grouped residue products under each schedule
+ * (tile order: problem order or largest first; one workgroup per tile or
+ * one per CU looping over tiles) on the call's own data, keeps the fastest
+ * for those shapes (process-wide), and then runs the call.  Off (default):
+ * problem order, one workgroup per tile, unless the shapes were tuned before.
+ */
+int ozaki2_set_autotune(int on);
+
+/* ozaki2_get_schedule - residue-product schedule (0..3: bit 0 largest
+ * first, bit 1 one workgroup per CU) of the calling thread's last batched
+ * call, or -1 if there was none. */
+int ozaki2_get_schedule(void);
+
+/* ozaki2_release - free the calling thread's library-owned workspace, timing
+ * events, cached batch plans and graphs. */
 int ozaki2_release(void);
 
 /* ozaki2_status_string - static description of a return code. */

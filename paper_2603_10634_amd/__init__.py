@@ -16,7 +16,9 @@ __all__ = [
     "Ozaki2Error", "lib", "ozaki2_dgemm", "ozaki2_workspace_bytes", "ozaki2_set_stream",
     "ozaki2_set_workspace", "ozaki2_set_timing", "ozaki2_get_stage_times",
     "ozaki2_get_kernel_times", "ozaki2_moduli", "ozaki2_workspace_layout", "ozaki2_release",
-    "ozaki2_status_string", "dgemm", "LIB_PATH", "HEADER_PATH", "header_functions",
+    "ozaki2_status_string", "ozaki2_dgemm_batched", "ozaki2_workspace_bytes_batched",
+    "ozaki2_set_graph", "ozaki2_set_autotune", "ozaki2_get_schedule", "dgemm", "dgemm_batched",
+    "LIB_PATH", "HEADER_PATH", "header_functions",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -25,6 +27,9 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "ozaki2.h")
 
 _i64 = ctypes.c_int64
 _vp = ctypes.c_void_p
+_p64 = ctypes.POINTER(ctypes.c_int64)
+_pd = ctypes.POINTER(ctypes.c_double)
+_pvp = ctypes.POINTER(ctypes.c_void_p)
 
 
 class Ozaki2Error(RuntimeError):
@@ -63,6 +68,14 @@ def lib() -> ctypes.CDLL:
         "ozaki2_workspace_layout": (ctypes.c_int, [_i64, _i64, _i64, ctypes.c_int,
                                                    ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
         "ozaki2_release": (ctypes.c_int, []),
+        "ozaki2_dgemm_batched": (ctypes.c_int, [ctypes.c_int, ctypes.c_char_p, ctypes.c_char_p,
+                                                _p64, _p64, _p64, _pd, _pvp, _p64, _pvp, _p64,
+                                                _pd, _pvp, _p64, ctypes.c_int]),
+        "ozaki2_workspace_bytes_batched": (ctypes.c_size_t, [ctypes.c_int, _p64, _p64, _p64,
+                                                             ctypes.c_int]),
+        "ozaki2_set_graph": (ctypes.c_int, [ctypes.c_int]),
+        "ozaki2_set_autotune": (ctypes.c_int, [ctypes.c_int]),
+        "ozaki2_get_schedule": (ctypes.c_int, []),
         "ozaki2_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     }
     for name, (res, args) in sig.items():
@@ -160,6 +173,80 @@ def ozaki2_workspace_layout(m, n, k, num_moduli) -> tuple[list[int], dict]:
 
 def ozaki2_release() -> int:
     return lib().ozaki2_release()
+
+
+def _arr(ctype, values):
+    values = list(values)
+    return (ctype * max(1, len(values)))(*values)
+
+
+def ozaki2_dgemm_batched(transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                         num_moduli) -> int:
+    """Batched column-major DGEMMs (see include/ozaki2.h).  Every argument but
+    num_moduli is a sequence with one entry per problem; A, B, C entries are
+    device pointers (int) or tensors.  Returns the status code."""
+    count = len(m)
+    if any(len(x) != count for x in (transA, transB, n, k, alpha, A, lda, B, ldb, beta, C, ldc)):
+        raise ValueError("batched arguments differ in length")
+    ta = b"".join(_ch(c) for c in transA) + b"\0"
+    tb = b"".join(_ch(c) for c in transB) + b"\0"
+    return lib().ozaki2_dgemm_batched(
+        count, ta, tb, _arr(ctypes.c_int64, m), _arr(ctypes.c_int64, n),
+        _arr(ctypes.c_int64, k), _arr(ctypes.c_double, [float(x) for x in alpha]),
+        _arr(ctypes.c_void_p, [_ptr(x) or None for x in A]), _arr(ctypes.c_int64, lda),
+        _arr(ctypes.c_void_p, [_ptr(x) or None for x in B]), _arr(ctypes.c_int64, ldb),
+        _arr(ctypes.c_double, [float(x) for x in beta]),
+        _arr(ctypes.c_void_p, [_ptr(x) or None for x in C]), _arr(ctypes.c_int64, ldc),
+        int(num_moduli))
+
+
+def ozaki2_workspace_bytes_batched(m, n, k, num_moduli) -> int:
+    return lib().ozaki2_workspace_bytes_batched(len(m), _arr(ctypes.c_int64, m),
+                                                _arr(ctypes.c_int64, n),
+                                                _arr(ctypes.c_int64, k), num_moduli)
+
+
+def ozaki2_set_graph(on: bool) -> int:
+    return lib().ozaki2_set_graph(1 if on else 0)
+
+
+def ozaki2_set_autotune(on: bool) -> int:
+    return lib().ozaki2_set_autotune(1 if on else 0)
+
+
+def ozaki2_get_schedule() -> int:
+    return lib().ozaki2_get_schedule()
+
+
+def dgemm_batched(As, Bs, num_moduli: int = 12):
+    """Row-major C_q = A_q B_q for lists of 2-D float64 CUDA tensors, as one
+    batched call on torch's current stream; returns the list of C_q."""
+    import torch
+
+    As = [a.contiguous() for a in As]
+    Bs = [b.contiguous() for b in Bs]
+    Cs, args = [], []
+    for a, b in zip(As, Bs):
+        if a.dtype != torch.float64 or b.dtype != torch.float64:
+            raise TypeError("dgemm_batched takes float64 tensors")
+        m, k = a.shape
+        if b.shape[0] != k:
+            raise ValueError("inner dimensions differ")
+        n = b.shape[1]
+        c = torch.empty((m, n), dtype=torch.float64, device=a.device)
+        Cs.append(c)
+        args.append((n, m, k, b, max(1, n), a, max(1, k), c, max(1, n)))
+    if not args:
+        return Cs
+    ozaki2_set_stream(torch.cuda.current_stream(As[0].device))
+    st = ozaki2_dgemm_batched(["N"] * len(args), ["N"] * len(args), [x[0] for x in args],
+                              [x[1] for x in args], [x[2] for x in args], [1.0] * len(args),
+                              [x[3] for x in args], [x[4] for x in args], [x[5] for x in args],
+                              [x[6] for x in args], [0.0] * len(args), [x[7] for x in args],
+                              [x[8] for x in args], num_moduli)
+    if st != 0:
+        raise Ozaki2Error("ozaki2_dgemm_batched", st)
+    return Cs
 
 
 def dgemm(A, B, num_moduli: int = 12, alpha: float = 1.0, beta: float = 0.0, C=None):

@@ -18,7 +18,10 @@ LIB = os.path.join(HERE, "liboz2.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 # Packed FP32 instructions are switched off for every HIP translation unit.
-COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+# Floating-point contraction is off: results are specified with a rounding
+# after every operation (for instance RN(RN(alpha Chat) + RN(beta C))), and
+# only the explicit fma() calls may fuse.
+COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
           "-mllvm", "-disable-promote-alloca-to-lds",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]

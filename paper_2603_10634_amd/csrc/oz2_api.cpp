@@ -1,10 +1,17 @@
-// C ABI: argument checking, workspace management, per-device tables and the
-// launch sequence of one emulated DGEMM (the workflow of Section IV-B).
+// C ABI: argument checking, workspace management, per-device tables, the
+// launch sequence of one emulated DGEMM (the workflow of Section IV-B), and
+// the same sequence over a batch of problems as one grouped launch per
+// kernel family, optionally captured in a hipGraph and with an autotuned
+// residue-product schedule.
 #include <string.h>
 
+#include <algorithm>
+#include <list>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <utility>
+#include <vector>
 
 #include "oz2_internal.h"
 
@@ -13,6 +20,8 @@ using namespace oz2;
 namespace {
 
 constexpr int kEvents = 7;
+
+struct Plan;
 
 struct ThreadState {
   hipStream_t stream = nullptr;
@@ -26,6 +35,12 @@ struct ThreadState {
   int ev_dev = -1;
   hipEvent_t ev[kEvents];
   bool have_times = false;
+  bool graph = false;                      // capture launch sequences in hipGraphs
+  bool autotune = false;                   // tune the grouped residue-product schedule
+  int last_schedule = -1;                  // schedule of the last batched call
+  hipStream_t cap_stream = nullptr;        // private stream used only for capture
+  int cap_dev = -1;
+  std::list<std::unique_ptr<Plan>> plans;  // cached plans, most recent first
 };
 
 thread_local ThreadState g_ts;
@@ -34,6 +49,10 @@ std::mutex g_mu;
 std::map<std::pair<int, int>, Tables *> g_tables;  // (device, N) -> device copy
 std::map<int, bool> g_is_gfx950;
 std::map<int, Tables> g_host_tables;                // N -> host copy
+
+// Schedules of the grouped residue products chosen by the autotuner, keyed
+// by the shapes of a batch (not its pointers).
+std::map<std::vector<int64_t>, int> g_tuned;
 
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
@@ -139,6 +158,343 @@ bool valid_trans(char c) {
   return c == 'N' || c == 'n' || c == 'T' || c == 't' || c == 'C' || c == 'c';
 }
 
+bool is_trans(char c) { return !(c == 'N' || c == 'n'); }
+
+// Problem descriptor of one call whose workspace starts at ws (layout L).
+Problem make_problem(char transA, char transB, int64_t m, int64_t n, int64_t k, double alpha,
+                     const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
+                     double *C, int64_t ldc, int N, uint8_t *ws, const Layout &L,
+                     const Tables *dt, int limbs) {
+  Problem P;
+  memset(&P, 0, sizeof(P));
+  const bool tA = is_trans(transA), tB = is_trans(transB);
+  P.A.ptr = A;
+  P.A.lines = m;
+  P.A.k = k;
+  P.A.sr = tA ? lda : 1;
+  P.A.sh = tA ? 1 : lda;
+  P.B.ptr = B;
+  P.B.lines = n;
+  P.B.k = k;
+  P.B.sr = tB ? 1 : ldb;
+  P.B.sh = tB ? ldb : 1;
+  P.g = Geometry{m, n, k, L.mp, L.np, L.kp, N, L.M};
+  Work &w = P.w;
+  w.amax = (uint64_t *)(ws + L.off[10]);
+  w.flags = (uint32_t *)(ws + L.off[11]);
+  w.rmax = (uint32_t *)(ws + L.off[12]);
+  w.rfix = (uint64_t *)(ws + L.off[13]);
+  w.amb = (uint32_t *)(ws + L.off[14]);
+  w.shift = (int32_t *)(ws + L.off[0]);
+  w.E = (int32_t *)(ws + L.off[1]);
+  w.e = (int32_t *)(ws + L.off[2]);
+  w.Abar = ws + L.off[3];
+  w.Bbar = ws + L.off[4];
+  w.Asl = ws + L.off[5];
+  w.Bsl = ws + L.off[6];
+  w.planes = (int16_t *)(ws + L.off[7]);
+  w.zero = (uint32_t *)(ws + L.off[10]);
+  w.zero_words = (int64_t)((L.off[15] - L.off[10]) / 4);
+  P.tab = dt;
+  P.alpha = alpha;
+  P.beta = beta;
+  P.C = C;
+  P.ldc = ldc;
+  P.limbs = limbs;
+  return P;
+}
+
+int num_chunks(int64_t kp) { return (int)((kp + kChunkK - 1) / kChunkK); }
+
+// Timing marks: event q is recorded after kernel group q - 1.
+struct Marks {
+  ThreadState *ts;
+  hipStream_t st;
+  bool on;
+  int n = 0;
+  void operator()() {
+    if (on) (void)hipEventRecord(ts->ev[n++], st);
+  }
+};
+
+#define OZ2_TRY(expr)                 \
+  do {                                \
+    if ((expr) != hipSuccess) {       \
+      (void)hipGetLastError();        \
+      return OZ2_ERR_HIP;             \
+    }                                 \
+  } while (0)
+
+// The launch sequence of one problem (workflow steps 1-10 of Section IV-B).
+int enqueue_single(const Problem &P, hipStream_t st, Marks &mark) {
+  mark();
+  // step 1: mu', nu' and the FP8 bound operands
+  for (int f : {kFamFill, kFamLmaxA, kFamLmaxB, kFamBarA, kFamBarB})
+    OZ2_TRY(launch_quant_family(f, &P, nullptr, st));
+  mark();
+  // step 2: the FP8 bound product (its line maxima only)
+  OZ2_TRY(launch_gemm_family(kFamBgemm, &P, nullptr, 0, 0, st));
+  mark();
+  // step 3: scale exponents mu, nu
+  for (int f : {kFamDecide, kFamFixup, kFamFinal}) OZ2_TRY(launch_scale_family(f, &P, nullptr, st));
+  mark();
+  // steps 4-6: integers, residues and FP8 digits
+  OZ2_TRY(launch_quant_family(kFamResA, &P, nullptr, st));
+  OZ2_TRY(launch_quant_family(kFamResB, &P, nullptr, st));
+  mark();
+  // steps 7-8: residue products and their reduction modulo p, per k chunk
+  for (int c = 0; c < num_chunks(P.g.kp); ++c) {
+    OZ2_TRY(launch_gemm_family(kFamGemmSq, &P, nullptr, c, 0, st));
+    OZ2_TRY(launch_gemm_family(kFamGemmKa, &P, nullptr, c, 0, st));
+  }
+  mark();
+  // steps 9-10: CRT and inverse scaling
+  OZ2_TRY(launch_crt_family(&P, nullptr, P.limbs, st));
+  mark();
+  return OZ2_SUCCESS;
+}
+
+// ---- batched calls ----
+
+// Grouped residue-product schedules the autotuner chooses from: bit 0 set
+// orders tiles largest problem first (else in problem order), bit 1 set runs
+// one workgroup per CU looping over tiles (else one workgroup per tile).
+constexpr int kNumSchedules = 4;
+
+// One grouped launch of a sub-batch.  The descriptor arrays live in the
+// plan's device buffer at the given byte offsets; G is filled in once the
+// buffer exists.
+struct GLaunch {
+  int fam, chunk, order;  // order: 0 problem order, 1 largest first (products only)
+  size_t off_probs, off_order, off_start;
+  Group G;
+};
+
+// Problems whose workspaces fit together, run as one set of grouped launches.
+struct SubBatch {
+  std::vector<GLaunch> launches;
+  int limbs;
+};
+
+// Everything a batched call (or, in graph mode, a single call) needs beyond
+// its arguments: device-resident descriptors and block maps, the split into
+// sub-batches, the scale-only problems, and the captured graph.  Keyed by the
+// exact argument bytes.
+struct Plan {
+  std::vector<uint8_t> key;
+  int dev = -1;
+  void *dbuf = nullptr;  // device: problems, orders, block maps
+  void *hbuf = nullptr;  // pinned staging copy of dbuf
+  size_t bytes = 0;
+  bool uploaded = false;
+  std::vector<SubBatch> subs;
+  struct Scal {
+    int64_t m, n;
+    double beta;
+    double *C;
+    int64_t ldc;
+  };
+  std::vector<Scal> scal;
+  std::vector<int64_t> shape_key;  // for the autotuner's cache
+  int schedule = -1;
+  bool single = false;
+  Problem single_problem;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~Plan() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (dbuf) (void)hipFree(dbuf);
+    if (hbuf) (void)hipHostFree(hbuf);
+  }
+};
+
+struct KeyBuilder {
+  std::vector<uint8_t> b;
+  template <class T>
+  void add(const T &v) {
+    const uint8_t *p = (const uint8_t *)&v;
+    b.insert(b.end(), p, p + sizeof(T));
+  }
+};
+
+Plan *find_plan(const std::vector<uint8_t> &key) {
+  ThreadState &ts = g_ts;
+  for (auto it = ts.plans.begin(); it != ts.plans.end(); ++it) {
+    if ((*it)->key == key) {
+      ts.plans.splice(ts.plans.begin(), ts.plans, it);  // most recent first
+      return ts.plans.front().get();
+    }
+  }
+  return nullptr;
+}
+
+Plan *add_plan(std::unique_ptr<Plan> p) {
+  ThreadState &ts = g_ts;
+  constexpr size_t kMaxPlans = 8;
+  if (ts.plans.size() >= kMaxPlans) {
+    // a plan being evicted may still be referenced by queued work
+    (void)hipStreamSynchronize(ts.stream);
+    ts.plans.pop_back();
+  }
+  ts.plans.push_front(std::move(p));
+  return ts.plans.front().get();
+}
+
+int capture_stream(int dev, hipStream_t *out) {
+  ThreadState &ts = g_ts;
+  if (ts.cap_stream && ts.cap_dev != dev) {
+    (void)hipStreamDestroy(ts.cap_stream);
+    ts.cap_stream = nullptr;
+  }
+  if (!ts.cap_stream) {
+    if (hipStreamCreateWithFlags(&ts.cap_stream, hipStreamNonBlocking) != hipSuccess) {
+      ts.cap_stream = nullptr;
+      return OZ2_ERR_HIP;
+    }
+    ts.cap_dev = dev;
+  }
+  *out = ts.cap_stream;
+  return OZ2_SUCCESS;
+}
+
+// Runs `enqueue` on st, or (graph mode) replays the plan's graph, capturing
+// it first on the private stream if the plan has none yet.
+template <class F>
+int run_maybe_graph(Plan *plan, int dev, hipStream_t st, F enqueue) {
+  if (!plan) return enqueue(st);
+  if (!plan->exec) {
+    hipStream_t cs;
+    int r = capture_stream(dev, &cs);
+    if (r != OZ2_SUCCESS) return r;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipGetLastError();
+      return OZ2_ERR_HIP;
+    }
+    const int er = enqueue(cs);
+    hipGraph_t graph = nullptr;
+    const hipError_t ee = hipStreamEndCapture(cs, &graph);
+    if (er != OZ2_SUCCESS || ee != hipSuccess || !graph) {
+      if (graph) (void)hipGraphDestroy(graph);
+      (void)hipGetLastError();
+      return er != OZ2_SUCCESS ? er : OZ2_ERR_HIP;
+    }
+    hipGraphExec_t exec = nullptr;
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      (void)hipGetLastError();
+      return OZ2_ERR_HIP;
+    }
+    plan->graph = graph;
+    plan->exec = exec;
+  }
+  OZ2_TRY(hipGraphLaunch(plan->exec, st));
+  return OZ2_SUCCESS;
+}
+
+// Host image of a plan's device buffer (256-byte aligned pieces).
+struct ImageWriter {
+  std::vector<uint8_t> img;
+  size_t put(const void *src, size_t bytes) {
+    const size_t at = (img.size() + 255) / 256 * 256;
+    img.resize(at + bytes);
+    memcpy(img.data() + at, src, bytes);
+    return at;
+  }
+};
+
+// The grouped launches of one sub-batch: every family over all its problems,
+// the residue products per k chunk and in both tile orders.
+void build_subbatch(const std::vector<Problem> &probs, ImageWriter &W, SubBatch *sb) {
+  const int np = (int)probs.size();
+  const size_t at_probs = W.put(probs.data(), sizeof(Problem) * np);
+  std::vector<int32_t> nat(np), lpt(np);
+  for (int q = 0; q < np; ++q) nat[q] = lpt[q] = q;
+  std::stable_sort(lpt.begin(), lpt.end(), [&](int a, int b) {
+    const Geometry &x = probs[a].g, &y = probs[b].g;
+    return (double)x.mp * x.np * x.kp > (double)y.mp * y.np * y.kp;
+  });
+  const size_t at_nat = W.put(nat.data(), sizeof(int32_t) * np);
+  const size_t at_lpt = W.put(lpt.data(), sizeof(int32_t) * np);
+  int chunks = 0;
+  for (const Problem &P : probs) chunks = std::max(chunks, num_chunks(P.g.kp));
+  auto add = [&](int fam, int chunk, int order) {
+    const std::vector<int32_t> &ord = order ? lpt : nat;
+    std::vector<int64_t> start(np + 1, 0);
+    for (int q = 0; q < np; ++q)
+      start[q + 1] = start[q] + family_blocks(fam, probs[ord[q]], chunk);
+    if (start[np] == 0) return;
+    GLaunch L;
+    memset(&L, 0, sizeof(L));
+    L.fam = fam;
+    L.chunk = chunk;
+    L.order = order;
+    L.off_probs = at_probs;
+    L.off_order = order ? at_lpt : at_nat;
+    L.off_start = W.put(start.data(), sizeof(int64_t) * (np + 1));
+    L.G.nseg = np;
+    L.G.total = start[np];
+    sb->launches.push_back(L);
+  };
+  for (int f : {kFamFill, kFamLmaxA, kFamLmaxB, kFamBarA, kFamBarB, kFamBgemm, kFamDecide,
+                kFamFixup, kFamFinal, kFamResA, kFamResB})
+    add(f, 0, 0);
+  for (int order = 0; order < 2; ++order)
+    for (int c = 0; c < chunks; ++c) {
+      add(kFamGemmSq, c, order);
+      add(kFamGemmKa, c, order);
+    }
+  add(kFamCrt, 0, 0);
+}
+
+// Kernel group of a family, as reported by ozaki2_get_kernel_times.
+int family_group(int fam) {
+  switch (fam) {
+    case kFamBgemm: return 1;
+    case kFamDecide: case kFamFixup: case kFamFinal: return 2;
+    case kFamResA: case kFamResB: return 3;
+    case kFamGemmSq: case kFamGemmKa: return 4;
+    case kFamCrt: return 5;
+    default: return 0;
+  }
+}
+
+// Enqueues the kernel groups g0..g1 (numbered as in ozaki2_get_kernel_times)
+// of sub-batch sb with residue-product schedule `sched`.  Marks are placed at
+// every group boundary when the whole sequence runs.  With `ev` non-null,
+// ev[0] and ev[1] bracket the residue products (group 4).
+int enqueue_subbatch(const SubBatch &sb, int sched, int cus, hipStream_t st, Marks &mark,
+                     hipEvent_t *ev, int g0 = 0, int g1 = 5) {
+  const int order = sched & 1;
+  const int64_t grid = (sched & 2) ? cus : 0;
+  int group = -1;
+  auto advance = [&](int to) -> int {
+    while (group < to) {
+      if (group == 3 && ev) OZ2_TRY(hipEventRecord(ev[0], st));
+      if (group == 4 && ev) OZ2_TRY(hipEventRecord(ev[1], st));
+      mark();
+      ++group;
+    }
+    return OZ2_SUCCESS;
+  };
+  for (const GLaunch &L : sb.launches) {
+    const bool gemm = L.fam == kFamGemmSq || L.fam == kFamGemmKa;
+    if (gemm && L.order != order) continue;
+    const int gq = family_group(L.fam);
+    if (gq < g0 || gq > g1) continue;
+    if (advance(gq) != OZ2_SUCCESS) return OZ2_ERR_HIP;
+    if (gemm || L.fam == kFamBgemm)
+      OZ2_TRY(launch_gemm_family(L.fam, nullptr, &L.G, L.chunk, grid, st));
+    else if (L.fam == kFamDecide || L.fam == kFamFixup || L.fam == kFamFinal)
+      OZ2_TRY(launch_scale_family(L.fam, nullptr, &L.G, st));
+    else if (L.fam == kFamCrt)
+      OZ2_TRY(launch_crt_family(nullptr, &L.G, sb.limbs, st));
+    else
+      OZ2_TRY(launch_quant_family(L.fam, nullptr, &L.G, st));
+  }
+  return advance(g1 + 1);
+}
+
 }  // namespace
 
 extern "C" {
@@ -209,6 +565,14 @@ int ozaki2_set_timing(int on) {
 
 int ozaki2_release(void) {
   ThreadState &ts = g_ts;
+  if (!ts.plans.empty()) {
+    (void)hipDeviceSynchronize();
+    ts.plans.clear();
+  }
+  if (ts.cap_stream) {
+    (void)hipStreamDestroy(ts.cap_stream);
+    ts.cap_stream = nullptr;
+  }
   if (ts.own_ws) {
     (void)hipFree(ts.own_ws);
     ts.own_ws = nullptr;
@@ -247,6 +611,36 @@ int ozaki2_get_stage_times(float ms[5]) {
   return OZ2_SUCCESS;
 }
 
+// Workspace of the calling thread for `need` bytes (the caller's if set).
+static int get_workspace(int dev, size_t need, uint8_t **ws, size_t *have) {
+  ThreadState &ts = g_ts;
+  if (ts.user_ws) {
+    *ws = (uint8_t *)ts.user_ws;
+    *have = ts.user_ws_bytes;
+    return ts.user_ws_bytes < need ? OZ2_ERR_WORKSPACE : OZ2_SUCCESS;
+  }
+  if (ts.own_ws && (ts.own_ws_bytes < need || ts.own_dev != dev)) {
+    // plans captured over the old workspace must not be replayed
+    (void)hipDeviceSynchronize();
+    ts.plans.clear();
+    (void)hipFree(ts.own_ws);
+    ts.own_ws = nullptr;
+    ts.own_ws_bytes = 0;
+  }
+  if (!ts.own_ws) {
+    if (hipMalloc(&ts.own_ws, need) != hipSuccess) {
+      ts.own_ws = nullptr;
+      (void)hipGetLastError();
+      return OZ2_ERR_ALLOC;
+    }
+    ts.own_ws_bytes = need;
+    ts.own_dev = dev;
+  }
+  *ws = (uint8_t *)ts.own_ws;
+  *have = ts.own_ws_bytes;
+  return OZ2_SUCCESS;
+}
+
 int ozaki2_dgemm(char transA, char transB, int64_t m, int64_t n, int64_t k, double alpha,
                  const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
                  double *C, int64_t ldc, int num_moduli) {
@@ -256,10 +650,8 @@ int ozaki2_dgemm(char transA, char transB, int64_t m, int64_t n, int64_t k, doub
   if (m < 0) return -3;
   if (n < 0) return -4;
   if (k < 0) return -5;
-  const bool tA = !(transA == 'N' || transA == 'n');
-  const bool tB = !(transB == 'N' || transB == 'n');
-  const int64_t rowsA = tA ? k : m;
-  const int64_t rowsB = tB ? n : k;
+  const int64_t rowsA = is_trans(transA) ? k : m;
+  const int64_t rowsB = is_trans(transB) ? n : k;
   if (lda < (rowsA > 1 ? rowsA : 1)) return -8;
   if (ldb < (rowsB > 1 ? rowsB : 1)) return -10;
   if (ldc < (m > 1 ? m : 1)) return -13;
@@ -271,6 +663,7 @@ int ozaki2_dgemm(char transA, char transB, int64_t m, int64_t n, int64_t k, doub
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return OZ2_ERR_NO_DEVICE;
   if (!device_ok(dev)) return OZ2_ERR_NO_DEVICE;
+  ts.have_times = false;
   if (k == 0 || alpha == 0.0)
     return launch_scal(m, n, beta, C, ldc, st) == hipSuccess ? OZ2_SUCCESS : OZ2_ERR_HIP;
   if (k > OZ2_MAX_K) return OZ2_ERR_UNSUPPORTED;
@@ -282,104 +675,296 @@ int ozaki2_dgemm(char transA, char transB, int64_t m, int64_t n, int64_t k, doub
   if (!dt) return OZ2_ERR_HIP;
   const Tables *ht = host_tables(num_moduli);
 
-  // ---- workspace ----
   uint8_t *ws = nullptr;
-  if (ts.user_ws) {
-    if (ts.user_ws_bytes < L.total) return OZ2_ERR_WORKSPACE;
-    ws = (uint8_t *)ts.user_ws;
-  } else {
-    if (ts.own_ws && (ts.own_ws_bytes < L.total || ts.own_dev != dev)) {
-      (void)hipFree(ts.own_ws);
-      ts.own_ws = nullptr;
-      ts.own_ws_bytes = 0;
+  size_t have = 0;
+  int r = get_workspace(dev, L.total, &ws, &have);
+  if (r != OZ2_SUCCESS) return r;
+  const Problem P = make_problem(transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                                 num_moduli, ws, L, dt, ht->limbs);
+
+  if (ts.graph) {
+    KeyBuilder kb;
+    kb.add(dev);
+    kb.add(P);
+    Plan *plan = find_plan(kb.b);
+    if (!plan) {
+      std::unique_ptr<Plan> p(new Plan);
+      p->key = kb.b;
+      p->dev = dev;
+      p->single = true;
+      p->single_problem = P;
+      plan = add_plan(std::move(p));
     }
-    if (!ts.own_ws) {
-      if (hipMalloc(&ts.own_ws, L.total) != hipSuccess) {
-        ts.own_ws = nullptr;
+    return run_maybe_graph(plan, dev, st, [&](hipStream_t s) {
+      Marks none{&ts, s, false};
+      return enqueue_single(plan->single_problem, s, none);
+    });
+  }
+  const bool timed = ts.timing;
+  if (timed) {
+    r = ensure_events(dev);
+    if (r != OZ2_SUCCESS) return r;
+  }
+  Marks mark{&ts, st, timed};
+  r = enqueue_single(P, st, mark);
+  ts.have_times = timed && r == OZ2_SUCCESS;
+  return r;
+}
+
+// Per-problem argument checks of a batched call; returns 0 or -(argument).
+static int check_batch(int count, const char *transA, const char *transB, const int64_t *m,
+                       const int64_t *n, const int64_t *k, const double *alpha,
+                       const double *const *A, const int64_t *lda, const double *const *B,
+                       const int64_t *ldb, const double *beta, double *const *C,
+                       const int64_t *ldc, int num_moduli) {
+  if (count < 0) return -1;
+  if (count == 0) return num_moduli < 1 || num_moduli > OZ2_MAX_MODULI ? -15 : 0;
+  if (!transA) return -2;
+  if (!transB) return -3;
+  if (!m) return -4;
+  if (!n) return -5;
+  if (!k) return -6;
+  if (!alpha) return -7;
+  if (!A) return -8;
+  if (!lda) return -9;
+  if (!B) return -10;
+  if (!ldb) return -11;
+  if (!beta) return -12;
+  if (!C) return -13;
+  if (!ldc) return -14;
+  for (int q = 0; q < count; ++q) {
+    if (!valid_trans(transA[q])) return -2;
+    if (!valid_trans(transB[q])) return -3;
+    if (m[q] < 0) return -4;
+    if (n[q] < 0) return -5;
+    if (k[q] < 0) return -6;
+    const int64_t rowsA = is_trans(transA[q]) ? k[q] : m[q];
+    const int64_t rowsB = is_trans(transB[q]) ? n[q] : k[q];
+    if (lda[q] < (rowsA > 1 ? rowsA : 1)) return -9;
+    if (ldb[q] < (rowsB > 1 ? rowsB : 1)) return -11;
+    if (ldc[q] < (m[q] > 1 ? m[q] : 1)) return -14;
+  }
+  if (num_moduli < 1 || num_moduli > OZ2_MAX_MODULI) return -15;
+  return 0;
+}
+
+static bool emulated(int64_t m, int64_t n, int64_t k, double alpha) {
+  return m > 0 && n > 0 && k > 0 && alpha != 0.0;
+}
+
+size_t ozaki2_workspace_bytes_batched(int count, const int64_t *m, const int64_t *n,
+                                      const int64_t *k, int num_moduli) {
+  if (count < 0 || num_moduli < 1 || num_moduli > OZ2_MAX_MODULI) return 0;
+  if (count > 0 && (!m || !n || !k)) return 0;
+  size_t total = 0;
+  for (int q = 0; q < count; ++q) {
+    if (m[q] < 0 || n[q] < 0 || k[q] < 0) return 0;
+    if (m[q] == 0 || n[q] == 0 || k[q] == 0) continue;
+    Layout L;
+    if (!make_layout(m[q], n[q], k[q], num_moduli, &L)) return 0;
+    total += L.total;
+  }
+  return total;
+}
+
+int ozaki2_dgemm_batched(int count, const char *transA, const char *transB, const int64_t *m,
+                         const int64_t *n, const int64_t *k, const double *alpha,
+                         const double *const *A, const int64_t *lda, const double *const *B,
+                         const int64_t *ldb, const double *beta, double *const *C,
+                         const int64_t *ldc, int num_moduli) {
+  int r = check_batch(count, transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                      num_moduli);
+  if (r != 0) return r;
+  ThreadState &ts = g_ts;
+  ts.have_times = false;
+  if (count == 0) return OZ2_SUCCESS;
+  bool any = false;
+  for (int q = 0; q < count; ++q) {
+    if (m[q] > 0 && n[q] > 0) any = true;
+    if (emulated(m[q], n[q], k[q], alpha[q]) && k[q] > OZ2_MAX_K) return OZ2_ERR_UNSUPPORTED;
+  }
+  if (!any) return OZ2_SUCCESS;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return OZ2_ERR_NO_DEVICE;
+  if (!device_ok(dev)) return OZ2_ERR_NO_DEVICE;
+  hipStream_t st = ts.stream;
+  hipError_t herr = hipSuccess;
+  const Tables *dt = device_tables(dev, num_moduli, &herr);
+  if (!dt) return OZ2_ERR_HIP;
+  const Tables *ht = host_tables(num_moduli);
+
+  // workspace: library-owned grows to the whole batch, capped at 16 GiB
+  // (or the largest single problem); a caller's is used as given
+  std::vector<Layout> lays(count);
+  size_t total = 0, largest = 0;
+  for (int q = 0; q < count; ++q) {
+    if (!emulated(m[q], n[q], k[q], alpha[q])) continue;
+    if (!make_layout(m[q], n[q], k[q], num_moduli, &lays[q])) return OZ2_ERR_UNSUPPORTED;
+    total += lays[q].total;
+    largest = std::max(largest, lays[q].total);
+  }
+  uint8_t *ws = nullptr;
+  size_t have = 0;
+  if (total > 0) {
+    size_t want = total;
+    if (!ts.user_ws) want = std::max(largest, std::min(total, (size_t)16 << 30));
+    r = get_workspace(dev, ts.user_ws ? largest : want, &ws, &have);
+    if (r != OZ2_SUCCESS) return r;
+  }
+
+  KeyBuilder kb;
+  kb.add(dev);
+  kb.add(num_moduli);
+  kb.add(count);
+  kb.add(ws);
+  kb.add(have);
+  for (int q = 0; q < count; ++q) {
+    kb.add(transA[q]);
+    kb.add(transB[q]);
+    kb.add(m[q]);
+    kb.add(n[q]);
+    kb.add(k[q]);
+    kb.add(alpha[q]);
+    kb.add(A[q]);
+    kb.add(lda[q]);
+    kb.add(B[q]);
+    kb.add(ldb[q]);
+    kb.add(beta[q]);
+    kb.add(C[q]);
+    kb.add(ldc[q]);
+  }
+  Plan *plan = find_plan(kb.b);
+  if (!plan) {
+    std::unique_ptr<Plan> p(new Plan);
+    p->key = kb.b;
+    p->dev = dev;
+    ImageWriter W;
+    std::vector<Problem> cur;
+    size_t used = 0;
+    auto flush = [&]() {
+      if (cur.empty()) return;
+      SubBatch sb;
+      sb.limbs = ht->limbs;
+      build_subbatch(cur, W, &sb);
+      p->subs.push_back(std::move(sb));
+      cur.clear();
+      used = 0;
+    };
+    p->shape_key.push_back(num_moduli);
+    for (int q = 0; q < count; ++q) {
+      if (m[q] == 0 || n[q] == 0) continue;
+      if (!emulated(m[q], n[q], k[q], alpha[q])) {
+        p->scal.push_back(Plan::Scal{m[q], n[q], beta[q], C[q], ldc[q]});
+        continue;
+      }
+      const Layout &L = lays[q];
+      if (used + L.total > have) flush();
+      cur.push_back(make_problem(transA[q], transB[q], m[q], n[q], k[q], alpha[q], A[q], lda[q],
+                                 B[q], ldb[q], beta[q], C[q], ldc[q], num_moduli, ws + used, L,
+                                 dt, ht->limbs));
+      used += L.total;
+      for (int64_t v : {m[q], n[q], k[q]}) p->shape_key.push_back(v);
+    }
+    flush();
+    p->bytes = W.img.size();
+    if (p->bytes) {
+      if (hipMalloc(&p->dbuf, p->bytes) != hipSuccess) {
         (void)hipGetLastError();
         return OZ2_ERR_ALLOC;
       }
-      ts.own_ws_bytes = L.total;
-      ts.own_dev = dev;
+      if (hipHostMalloc(&p->hbuf, p->bytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return OZ2_ERR_ALLOC;
+      }
+      memcpy(p->hbuf, W.img.data(), p->bytes);
+      uint8_t *base = (uint8_t *)p->dbuf;
+      for (SubBatch &sb : p->subs)
+        for (GLaunch &L : sb.launches) {
+          L.G.probs = (const Problem *)(base + L.off_probs);
+          L.G.order = (const int32_t *)(base + L.off_order);
+          L.G.start = (const int64_t *)(base + L.off_start);
+        }
     }
-    ws = (uint8_t *)ts.own_ws;
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      auto it = g_tuned.find(p->shape_key);
+      if (it != g_tuned.end()) p->schedule = it->second;
+    }
+    plan = add_plan(std::move(p));
   }
+  if (!plan->uploaded && plan->bytes) {
+    OZ2_TRY(hipMemcpyAsync(plan->dbuf, plan->hbuf, plan->bytes, hipMemcpyHostToDevice, st));
+    plan->uploaded = true;
+  }
+  int cus = 256;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
 
-  Geometry g{m, n, k, L.mp, L.np, L.kp, num_moduli, L.M};
-  Work w;
-  w.amax = (uint64_t *)(ws + L.off[10]);
-  w.flags = (uint32_t *)(ws + L.off[11]);
-  w.rmax = (uint32_t *)(ws + L.off[12]);
-  w.rfix = (uint64_t *)(ws + L.off[13]);
-  w.amb = (uint32_t *)(ws + L.off[14]);
-  w.shift = (int32_t *)(ws + L.off[0]);
-  w.E = (int32_t *)(ws + L.off[1]);
-  w.e = (int32_t *)(ws + L.off[2]);
-  w.Abar = ws + L.off[3];
-  w.Bbar = ws + L.off[4];
-  w.Asl = ws + L.off[5];
-  w.Bsl = ws + L.off[6];
-  w.planes = (int16_t *)(ws + L.off[7]);
+  // autotuner: on the first call of a new batch shape, run the first
+  // sub-batch's residue products under every schedule (the products are
+  // recomputed from the digit slices each time, so the result is the same)
+  // and keep the fastest
+  if (plan->schedule < 0 && ts.autotune && !plan->subs.empty()) {
+    r = ensure_events(dev);
+    if (r != OZ2_SUCCESS) return r;
+    const SubBatch &sb = plan->subs[0];
+    Marks none{&ts, st, false};
+    float best = 0.0f;
+    int best_s = 0;
+    // the stages before the products once, then the products per schedule
+    // (the CRT, which reads C when beta != 0, runs only in the real pass)
+    r = enqueue_subbatch(sb, 0, cus, st, none, nullptr, 0, 3);
+    if (r != OZ2_SUCCESS) return r;
+    for (int sched = 0; sched < kNumSchedules; ++sched) {
+      r = enqueue_subbatch(sb, sched, cus, st, none, ts.ev, 4, 4);
+      if (r != OZ2_SUCCESS) return r;
+      float t = 0.0f;
+      OZ2_TRY(hipEventSynchronize(ts.ev[1]));
+      OZ2_TRY(hipEventElapsedTime(&t, ts.ev[0], ts.ev[1]));
+      if (sched == 0 || t < best) {
+        best = t;
+        best_s = sched;
+      }
+    }
+    plan->schedule = best_s;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_tuned[plan->shape_key] = best_s;
+  }
+  const int sched = plan->schedule < 0 ? 0 : plan->schedule;
+  ts.last_schedule = sched;
 
-  Operand opA, opB;
-  opA.ptr = A;
-  opA.lines = m;
-  opA.k = k;
-  opA.sr = tA ? lda : 1;
-  opA.sh = tA ? 1 : lda;
-  opB.ptr = B;
-  opB.lines = n;
-  opB.k = k;
-  opB.sr = tB ? 1 : ldb;
-  opB.sh = tB ? ldb : 1;
-
-  const bool timed = ts.timing;
+  auto enqueue_all = [&](hipStream_t s, bool timed) -> int {
+    for (const Plan::Scal &c : plan->scal)
+      OZ2_TRY(launch_scal(c.m, c.n, c.beta, c.C, c.ldc, s));
+    for (const SubBatch &sb : plan->subs) {
+      Marks mark{&ts, s, timed};
+      const int e = enqueue_subbatch(sb, sched, cus, s, mark, nullptr);
+      if (e != OZ2_SUCCESS) return e;
+    }
+    return OZ2_SUCCESS;
+  };
+  if (ts.graph)
+    return run_maybe_graph(plan, dev, st, [&](hipStream_t s) { return enqueue_all(s, false); });
+  // timing covers batches that run as one sub-batch
+  const bool timed = ts.timing && plan->subs.size() == 1;
   if (timed) {
-    int r = ensure_events(dev);
+    r = ensure_events(dev);
     if (r != OZ2_SUCCESS) return r;
   }
-  int evn = 0;
-  auto mark = [&]() {
-    if (timed) (void)hipEventRecord(ts.ev[evn++], st);
-  };
+  r = enqueue_all(st, timed);
+  ts.have_times = timed && r == OZ2_SUCCESS;
+  return r;
+}
 
-#define OZ2_TRY(expr)                       \
-  do {                                      \
-    if ((expr) != hipSuccess) {             \
-      ts.have_times = false;                \
-      return OZ2_ERR_HIP;                   \
-    }                                       \
-  } while (0)
-
-  mark();
-  // workflow step 1: mu', nu' and the FP8 bound operands
-  OZ2_TRY(launch_fill_u32((uint32_t *)(ws + L.off[10]), 0u,
-                          (int64_t)((L.off[15] - L.off[10]) / 4), st));
-  OZ2_TRY(launch_line_max(opA, w.amax, w.flags, st));
-  OZ2_TRY(launch_line_max(opB, w.amax + L.mp, w.flags + L.mp, st));
-  OZ2_TRY(launch_bound_operand(opA, L.mp, L.kp, w.amax, w.E, w.flags, w.Abar, st));
-  OZ2_TRY(launch_bound_operand(opB, L.np, L.kp, w.amax + L.mp, w.E + L.mp, w.flags + L.mp,
-                               w.Bbar, st));
-  mark();
-  // workflow step 2: the FP8 bound product (its line maxima only)
-  OZ2_TRY(launch_bound_gemm(g, w.Abar, w.Bbar, w.rmax, w.rmax + L.mp, st));
-  mark();
-  // workflow step 3: scale exponents mu, nu
-  OZ2_TRY(launch_scale(g, dt, w, st));
-  mark();
-  // workflow steps 4-6: integers, residues and FP8 digits
-  OZ2_TRY(launch_residues(opA, L.mp, L.kp, w.shift, dt, num_moduli, w.Asl, st));
-  OZ2_TRY(launch_residues(opB, L.np, L.kp, w.shift + L.mp, dt, num_moduli, w.Bsl, st));
-  mark();
-  // workflow steps 7-8: residue products and their reduction modulo p
-  OZ2_TRY(launch_residue_gemm(g, dt, w.Asl, w.Bsl, w.planes, st));
-  mark();
-  // workflow steps 9-10: CRT and inverse scaling
-  OZ2_TRY(launch_crt(g, dt, w, alpha, beta, C, ldc, ht->limbs, st));
-  mark();
-#undef OZ2_TRY
-  ts.have_times = timed;
+int ozaki2_set_graph(int on) {
+  g_ts.graph = on != 0;
   return OZ2_SUCCESS;
 }
+
+int ozaki2_set_autotune(int on) {
+  g_ts.autotune = on != 0;
+  return OZ2_SUCCESS;
+}
+
+int ozaki2_get_schedule(void) { return g_ts.last_schedule; }
 
 }  // extern "C"

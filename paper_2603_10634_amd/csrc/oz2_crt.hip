@@ -7,6 +7,8 @@
 // Chat = C' 2^-(log2 mu_i + log2 nu_j) rounded once to nearest-even,
 // including gradual underflow, directly from the integer: no intermediate
 // floating-point rounding.  C = RN(alpha Chat) (+ RN(beta C_in)).
+#include <string.h>
+
 #include "oz2_internal.h"
 
 namespace oz2 {
@@ -70,14 +72,13 @@ __device__ __forceinline__ double scaled_rn(const uint32_t (&X)[L], int t) {
 }
 
 template <int L>
-__global__ __launch_bounds__(256) void k_crt(const int16_t *__restrict__ planes,
-                                             const int32_t *__restrict__ shift,
-                                             const uint32_t *__restrict__ flags,
-                                             const Tables *__restrict__ tab, int N, int64_t m,
-                                             int64_t n, int64_t mp, int64_t np, double alpha,
-                                             double beta, double *__restrict__ C, int64_t ldc) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t j = blockIdx.y;
+__device__ __forceinline__ void crt_entry(const int16_t *__restrict__ planes,
+                                          const int32_t *__restrict__ shift,
+                                          const uint32_t *__restrict__ flags,
+                                          const Tables *__restrict__ tab, int N, int64_t m,
+                                          int64_t mp, int64_t np, double alpha, double beta,
+                                          double *__restrict__ C, int64_t ldc, int64_t i,
+                                          int64_t j) {
   if (i >= m) return;
   const bool bad = ((flags[i] | flags[mp + j]) & kNonFinite) != 0;
   double chat;
@@ -183,9 +184,20 @@ __global__ __launch_bounds__(256) void k_crt(const int16_t *__restrict__ planes,
   C[i + j * ldc] = out;
 }
 
-__global__ void k_scal(int64_t m, int64_t n, double beta, double *__restrict__ C, int64_t ldc) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t j = blockIdx.y;
+template <int L, bool GROUPED>
+__global__ __launch_bounds__(256) void k_crt(Problem P1, Group G) {
+  int64_t local;
+  const Problem &P = *locate<GROUPED>(P1, G, blockIdx.x, local);
+  const int64_t nbx = (P.g.m + 255) / 256;
+  const int64_t bx = local % nbx, j = local / nbx;
+  crt_entry<L>(P.w.planes, P.w.shift, P.w.flags, P.tab, P.g.N, P.g.m, P.g.mp, P.g.np, P.alpha,
+               P.beta, P.C, P.ldc, bx * 256 + threadIdx.x, j);
+}
+
+__global__ void k_scal(int64_t m, double beta, double *__restrict__ C, int64_t ldc) {
+  const int64_t nbx = (m + 255) / 256;
+  const int64_t i = (int64_t)(blockIdx.x % nbx) * 256 + threadIdx.x;
+  const int64_t j = blockIdx.x / nbx;
   if (i >= m) return;
   double *c = C + i + j * ldc;
   *c = beta == 0.0 ? 0.0 : __dmul_rn(beta, *c);
@@ -193,13 +205,26 @@ __global__ void k_scal(int64_t m, int64_t n, double beta, double *__restrict__ C
 
 }  // namespace
 
-hipError_t launch_crt(const Geometry &g, const Tables *dt, const Work &w, double alpha,
-                      double beta, double *C, int64_t ldc, int limbs, hipStream_t st) {
-  dim3 grid((unsigned)((g.m + 255) / 256), (unsigned)g.n);
-#define OZ2_CRT_CASE(LL)                                                                      \
-  case LL:                                                                                    \
-    hipLaunchKernelGGL(k_crt<LL>, grid, dim3(256), 0, st, w.planes, w.shift, w.flags, dt, g.N, \
-                       g.m, g.n, g.mp, g.np, alpha, beta, C, ldc);                            \
+hipError_t launch_crt_family(const Problem *P, const Group *G, int limbs, hipStream_t st) {
+  const bool grouped = G != nullptr;
+  Problem p1;
+  Group g1;
+  memset(&p1, 0, sizeof(p1));
+  memset(&g1, 0, sizeof(g1));
+  if (grouped)
+    g1 = *G;
+  else
+    p1 = *P;
+  const int64_t blocks = grouped ? G->total : family_blocks(kFamCrt, *P, 0);
+  if (blocks <= 0) return hipSuccess;
+  if (blocks > 0x7FFFFFFFll) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)blocks), blk(256);
+#define OZ2_CRT_CASE(LL)                                            \
+  case LL:                                                          \
+    if (grouped)                                                    \
+      hipLaunchKernelGGL((k_crt<LL, true>), grid, blk, 0, st, p1, g1);  \
+    else                                                            \
+      hipLaunchKernelGGL((k_crt<LL, false>), grid, blk, 0, st, p1, g1); \
     break;
   switch (limbs) {
     OZ2_CRT_CASE(1)
@@ -218,8 +243,9 @@ hipError_t launch_crt(const Geometry &g, const Tables *dt, const Work &w, double
 
 hipError_t launch_scal(int64_t m, int64_t n, double beta, double *C, int64_t ldc, hipStream_t st) {
   if (m == 0 || n == 0) return hipSuccess;
-  dim3 grid((unsigned)((m + 255) / 256), (unsigned)n);
-  hipLaunchKernelGGL(k_scal, grid, dim3(256), 0, st, m, n, beta, C, ldc);
+  const int64_t blocks = (m + 255) / 256 * n;
+  if (blocks > 0x7FFFFFFFll) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_scal, dim3((unsigned)blocks), dim3(256), 0, st, m, beta, C, ldc);
   return hipGetLastError();
 }
 

@@ -22,6 +22,8 @@
 // are 64 B with the four 16 B chunks of row r XOR-swizzled by
 // ((r >> 1) ^ (r >> 3)) & 3, which keeps the fragment reads (ds_read_b128)
 // free of bank conflicts.
+#include <string.h>
+
 #include "oz2_internal.h"
 
 namespace oz2 {
@@ -39,6 +41,7 @@ constexpr int ROWB = 64;                 // LDS bytes per tile row
 constexpr int BSZ = TJ * ROWB;           // bytes of one B-side slice tile
 constexpr int ASZ = TI * ROWB;           // bytes of one A-side slice tile
 constexpr int LDS_RING = 147456;         // 144 KB: 3 stages of 2 slices or 6 of 1
+static_assert(TI == kGemmTI && TJ == kGemmTJ && BK == kGemmBK, "tile shape");
 
 __device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
 
@@ -75,14 +78,34 @@ __device__ __forceinline__ v8i lds_frag(const uint8_t *tile, int row0) {
   return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
 }
 
+// Values read from a problem descriptor or the tables through a generic
+// pointer are wave-uniform but may sit in vector registers (a flat load could
+// address per-lane private memory, so the compiler treats its result as
+// divergent); the load issue below needs them in scalar registers.
+__device__ __forceinline__ int64_t uni(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <class T>
+__device__ __forceinline__ T *uni(T *p) {
+  return (T *)(uintptr_t)uni((int64_t)(uintptr_t)p);
+}
+
 // One direct-to-LDS load: each lane fetches 16 B at `base` + `voff`; the
 // wave's 64 chunks land contiguously at LDS byte address `lds_off` (held in
 // M0).  It is issued from inline asm so that the compiler's wait-count
 // analysis does not see an LDS write in flight (which would turn every
 // LDS-read wait in the K-loop into a full drain); the K-loop waits for these
-// loads itself with explicit vmcnt counts.
+// loads itself with explicit vmcnt counts.  The compiler's hazard checks do
+// not look inside inline asm, so the asm carries its own wait states: a VMEM
+// instruction reading an SGPR that a VALU instruction wrote (for instance a
+// v_readfirstlane the compiler places to move `base` into scalar registers,
+// or an SGPR reload from a VGPR lane) needs 5, and the write of M0 before an
+// LDS-DMA load needs 1.
 __device__ __forceinline__ void dma16(const uint8_t *base, uint32_t voff, uint32_t lds_off) {
-  asm volatile("global_load_lds_dwordx4 %0, %1" ::"v"(voff), "s"(base), "{m0}"(lds_off)
+  asm volatile("s_nop 4\n\tglobal_load_lds_dwordx4 %0, %1" ::"v"(voff), "s"(base),
+               "{m0}"(lds_off)
                : "memory");
 }
 
@@ -343,25 +366,21 @@ __device__ __forceinline__ int smod_i32(int v, int p, float inv_p) {
   return r;
 }
 
-// KIND 0: square moduli (blockIdx.z = l), KIND 1: Karatsuba moduli
-// (blockIdx.z = l - l0).
-template <int KIND>
+// One 256 x 128 output tile (j0.., i0..) of modulus l over k in
+// [kbeg, kbeg + 64 nk).  KIND 0: square modulus, 1: Karatsuba modulus.
 // (operand pointers carry no __restrict__: the prefetch fence in kloop must be
 // able to order their loads)
-__global__ __launch_bounds__(256, 1) void k_residue_gemm(const uint8_t *Asl, const uint8_t *Bsl,
-                                                         int16_t *__restrict__ planes,
-                                                         const Tables *__restrict__ tab,
-                                                         int64_t mp, int64_t np, int64_t kp,
-                                                         int64_t kbeg, int nk, int accumulate,
-                                                         int l0) {
-  __shared__ __attribute__((aligned(1024))) uint8_t lds[LDS_RING];
-  const int l = l0 + blockIdx.z;
-  const int64_t i0 = (int64_t)blockIdx.x * TI;
-  const int64_t j0 = (int64_t)blockIdx.y * TJ;
-  const int sl0 = tab->slice0[l];
-  const int p = tab->p[l];
-  const float inv = tab->inv_p[l];
-  const int sv = KIND == 0 ? tab->s[l] : tab->kinit[l];
+template <int KIND>
+__device__ __forceinline__ void residue_tile(const uint8_t *Asl, const uint8_t *Bsl,
+                                             int16_t *__restrict__ planes,
+                                             const Tables *__restrict__ tab, int64_t mp,
+                                             int64_t np, int64_t kp, int64_t kbeg, int nk,
+                                             int accumulate, int l, int64_t i0, int64_t j0,
+                                             uint8_t *lds) {
+  const int sl0 = (int)uni(tab->slice0[l]);
+  const int p = (int)uni(tab->p[l]);
+  const float inv = __int_as_float((int)uni(__float_as_int(tab->inv_p[l])));
+  const int sv = (int)uni(KIND == 0 ? tab->s[l] : tab->kinit[l]);
   resident(sl0, p, __float_as_int(inv), sv);
   resident_ptr(planes, planes);
   resident(accumulate, accumulate, accumulate, accumulate);
@@ -437,13 +456,34 @@ __global__ __launch_bounds__(256, 1) void k_residue_gemm(const uint8_t *Asl, con
   }
 }
 
-__global__ __launch_bounds__(256, 1) void k_bound_gemm(const uint8_t *Abar, const uint8_t *Bbar,
-                                                       int64_t kp, int nk,
-                                                       uint32_t *__restrict__ rmaxA,
-                                                       uint32_t *__restrict__ rmaxB) {
+// Residue products of k chunk `chunk`: KIND 0 over the square moduli (tile
+// index z = l), 1 over the Karatsuba moduli (l = 6 + z).
+// A grouped launch may run fewer workgroups than tiles; each then loops.
+template <int KIND, bool GROUPED>
+__global__ __launch_bounds__(256, 1) void k_residue_gemm(Problem P1, Group G, int chunk) {
   __shared__ __attribute__((aligned(1024))) uint8_t lds[LDS_RING];
-  const int64_t i0 = (int64_t)blockIdx.x * TI;
-  const int64_t j0 = (int64_t)blockIdx.y * TJ;
+  const int64_t total = GROUPED ? G.total : (int64_t)gridDim.x;
+  for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+    int64_t local;
+    const Problem &P = *locate<GROUPED>(P1, G, b, local);
+    const Geometry &g = P.g;
+    const Dims d = family_dims(KIND == 0 ? kFamGemmSq : kFamGemmKa, P, chunk);
+    const Dims c = decode_block(d, local);
+    const int64_t mp = uni(g.mp), np = uni(g.np), kp = uni(g.kp);
+    const int64_t kbeg = (int64_t)chunk * kChunkK;
+    const int64_t len = kp - kbeg < kChunkK ? kp - kbeg : kChunkK;
+    const int l = (int)uni((KIND == 0 ? 0 : num_square(g.N)) + c.z);
+    residue_tile<KIND>(uni(P.w.Asl), uni(P.w.Bsl), uni(P.w.planes), uni(P.tab), mp, np, kp,
+                       kbeg, (int)(len / BK), chunk > 0 ? 1 : 0, l, uni(c.x * TI),
+                       uni(c.y * TJ), lds);
+  }
+}
+
+// Line maxima of one 256 x 128 tile of the bound product Abar Bbar.
+__device__ __forceinline__ void bound_tile(const uint8_t *Abar, const uint8_t *Bbar, int64_t kp,
+                                           int nk, uint32_t *__restrict__ rmaxA,
+                                           uint32_t *__restrict__ rmaxB, int64_t i0, int64_t j0,
+                                           uint8_t *lds) {
   v16f acc0[4][2], acc1[4][2];
   zero_acc(acc0);
   const uint8_t *gB[1] = {Bbar + j0 * kp};
@@ -480,38 +520,65 @@ __global__ __launch_bounds__(256, 1) void k_bound_gemm(const uint8_t *Abar, cons
     }
 }
 
-}  // namespace
-
-hipError_t launch_bound_gemm(const Geometry &g, const uint8_t *Abar, const uint8_t *Bbar,
-                             uint32_t *rmaxA, uint32_t *rmaxB, hipStream_t st) {
-  dim3 grid((unsigned)(g.mp / TI), (unsigned)(g.np / TJ));
-  hipLaunchKernelGGL(k_bound_gemm, grid, dim3(256), 0, st, Abar, Bbar, g.kp, (int)(g.kp / BK),
-                     rmaxA, rmaxB);
-  return hipGetLastError();
+template <bool GROUPED>
+__global__ __launch_bounds__(256, 1) void k_bound_gemm(Problem P1, Group G) {
+  __shared__ __attribute__((aligned(1024))) uint8_t lds[LDS_RING];
+  const int64_t total = GROUPED ? G.total : (int64_t)gridDim.x;
+  for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+    int64_t local;
+    const Problem &P = *locate<GROUPED>(P1, G, b, local);
+    const Geometry &g = P.g;
+    const Dims d = family_dims(kFamBgemm, P, 0);
+    const Dims c = decode_block(d, local);
+    const int64_t mp = uni(g.mp), kp = uni(g.kp);
+    uint32_t *rmax = uni(P.w.rmax);
+    bound_tile(uni(P.w.Abar), uni(P.w.Bbar), kp, (int)(kp / BK), rmax, rmax + mp,
+               uni(c.x * TI), uni(c.y * TJ), lds);
+  }
 }
 
-hipError_t launch_residue_gemm(const Geometry &g, const Tables *dt, const uint8_t *Asl,
-                               const uint8_t *Bsl, int16_t *planes, hipStream_t st) {
-  // the hybrid list puts its squares first: moduli 0..nsq-1 are squares
-  const int nsq = g.N < 6 ? g.N : 6;
-  for (int64_t k0 = 0; k0 < g.kp; k0 += kChunkK) {
-    const int64_t len = g.kp - k0 < kChunkK ? g.kp - k0 : kChunkK;
-    const int acc = k0 > 0 ? 1 : 0;
-    hipLaunchKernelGGL(k_residue_gemm<0>, dim3((unsigned)(g.mp / TI), (unsigned)(g.np / TJ), nsq),
-                       dim3(256), 0, st, Asl, Bsl, planes, dt, g.mp, g.np, g.kp, k0,
-                       (int)(len / BK), acc, 0);
-    hipError_t err = hipGetLastError();
-    if (err != hipSuccess) return err;
-    if (g.N > nsq) {
-      hipLaunchKernelGGL(k_residue_gemm<1>,
-                         dim3((unsigned)(g.mp / TI), (unsigned)(g.np / TJ), g.N - nsq),
-                         dim3(256), 0, st, Asl, Bsl, planes, dt, g.mp, g.np, g.kp, k0,
-                         (int)(len / BK), acc, nsq);
-      err = hipGetLastError();
-      if (err != hipSuccess) return err;
-    }
+}  // namespace
+
+hipError_t launch_gemm_family(int fam, const Problem *P, const Group *G, int chunk, int64_t grid,
+                              hipStream_t st) {
+  const bool grouped = G != nullptr;
+  Problem p1;
+  Group g1;
+  memset(&p1, 0, sizeof(p1));
+  memset(&g1, 0, sizeof(g1));
+  if (grouped)
+    g1 = *G;
+  else
+    p1 = *P;
+  const int64_t tiles = grouped ? G->total : family_blocks(fam, *P, chunk);
+  if (tiles <= 0) return hipSuccess;
+  int64_t blocks = tiles;
+  if (grouped && grid > 0 && grid < tiles) blocks = grid;
+  if (blocks > 0x7FFFFFFFll) return hipErrorInvalidValue;
+  const dim3 gr((unsigned)blocks), blk(256);
+  switch (fam) {
+    case kFamBgemm:
+      if (grouped)
+        hipLaunchKernelGGL((k_bound_gemm<true>), gr, blk, 0, st, p1, g1);
+      else
+        hipLaunchKernelGGL((k_bound_gemm<false>), gr, blk, 0, st, p1, g1);
+      break;
+    case kFamGemmSq:
+      if (grouped)
+        hipLaunchKernelGGL((k_residue_gemm<0, true>), gr, blk, 0, st, p1, g1, chunk);
+      else
+        hipLaunchKernelGGL((k_residue_gemm<0, false>), gr, blk, 0, st, p1, g1, chunk);
+      break;
+    case kFamGemmKa:
+      if (grouped)
+        hipLaunchKernelGGL((k_residue_gemm<1, true>), gr, blk, 0, st, p1, g1, chunk);
+      else
+        hipLaunchKernelGGL((k_residue_gemm<1, false>), gr, blk, 0, st, p1, g1, chunk);
+      break;
+    default:
+      return hipErrorInvalidValue;
   }
-  return hipSuccess;
+  return hipGetLastError();
 }
 
 }  // namespace oz2

@@ -61,6 +61,8 @@ struct Work {
   uint8_t *Abar, *Bbar;
   uint8_t *Asl, *Bsl;
   int16_t *planes;
+  uint32_t *zero;     // the buffers that start at zero (amax .. amb), contiguous
+  int64_t zero_words;
 };
 
 enum LineFlag : uint32_t { kNonFinite = 1u, kZeroLine = 2u, kFixup = 4u };
@@ -72,22 +74,187 @@ struct Operand {
   int64_t lines, k, sr, sh;
 };
 
+// Everything the kernels need about one emulated GEMM.
+struct Problem {
+  Operand A, B;        // op(A): lines are its m rows; op(B): its n columns
+  Geometry g;
+  Work w;
+  const Tables *tab;   // device copy of the tables for g.N
+  double alpha, beta;
+  double *C;
+  int64_t ldc;
+  int32_t limbs;       // 32-bit limbs of P (host tables), selects the CRT kernel
+};
+
+// Tile shapes of the kernels (the block grids below depend on them).
+constexpr int kGemmTI = 128;  // residue / bound products: output rows i per tile
+constexpr int kGemmTJ = 256;  // output columns j per tile
+constexpr int kGemmBK = 64;   // k per pipeline stage
+constexpr int kQTile = 64;    // quantization passes: 64 lines x 64 k per block
+
+// Kernel families of the emulation, in launch order.  One launch of a family
+// covers one problem or a whole group of problems (a batch).
+enum Family : int {
+  kFamFill = 0,   // zero the per-line accumulators
+  kFamLmaxA,      // line maxima of op(A) / op(B)
+  kFamLmaxB,
+  kFamBarA,       // FP8 bound operands
+  kFamBarB,
+  kFamBgemm,      // FP8 bound product (line maxima)
+  kFamDecide,     // scale exponents from the FP8 bound
+  kFamFixup,      // exact bound product for undecided lines
+  kFamFinal,      // shifts
+  kFamResA,       // residues and FP8 digits
+  kFamResB,
+  kFamGemmSq,     // residue products, square moduli (one launch per k chunk)
+  kFamGemmKa,     // residue products, Karatsuba moduli
+  kFamCrt,        // CRT, inverse scaling, alpha / beta
+  kNumFamilies
+};
+
+// k-split of the line-maxima pass.
+struct LmaxShape {
+  int64_t gx, splits, hchunk;
+};
+
+__host__ __device__ inline LmaxShape lmax_shape(const Operand &op) {
+  LmaxShape s;
+  if (op.sh == 1) {  // k contiguous: a wave per line and k chunk, ~2048 waves
+    s.gx = (op.lines + 3) / 4;
+    const int64_t splits = (2048 + s.gx - 1) / s.gx;
+    int64_t h = (op.k + splits - 1) / splits;
+    h = (h + 63) / 64 * 64;
+    s.hchunk = h;
+    s.splits = (op.k + h - 1) / h;
+  } else {  // lines contiguous: a thread per line and k chunk
+    s.gx = (op.lines + 255) / 256;
+    int64_t splits = (4096 + s.gx - 1) / s.gx;
+    if (splits > op.k) splits = op.k;
+    s.hchunk = (op.k + splits - 1) / splits;
+    s.splits = (op.k + s.hchunk - 1) / s.hchunk;
+  }
+  return s;
+}
+
+__host__ __device__ inline int num_square(int N) { return N < 6 ? N : 6; }
+
+struct Dims {
+  int64_t x, y, z;
+};
+
+// Block grid of family `fam` for one problem (k chunk `chunk` for the residue
+// products).  Blocks are numbered x fastest, then y, then z.
+__host__ __device__ inline Dims family_dims(int fam, const Problem &P, int chunk) {
+  const Geometry &g = P.g;
+  switch (fam) {
+    case kFamFill: {
+      int64_t b = (P.w.zero_words + 255) / 256;
+      return {b < 64 ? b : 64, 1, 1};
+    }
+    case kFamLmaxA: {
+      const LmaxShape s = lmax_shape(P.A);
+      return {s.gx, s.splits, 1};
+    }
+    case kFamLmaxB: {
+      const LmaxShape s = lmax_shape(P.B);
+      return {s.gx, s.splits, 1};
+    }
+    case kFamBarA:
+    case kFamResA:
+      return {g.mp / kQTile, g.kp / kQTile, 1};
+    case kFamBarB:
+    case kFamResB:
+      return {g.np / kQTile, g.kp / kQTile, 1};
+    case kFamBgemm:
+      return {g.mp / kGemmTI, g.np / kGemmTJ, 1};
+    case kFamDecide:
+    case kFamFinal:
+      return {(g.mp + g.np + 255) / 256, 1, 1};
+    case kFamFixup: {
+      int64_t b = (g.mp + g.np) / 64;
+      return {b < 8 ? 8 : (b > 512 ? 512 : b), 1, 1};
+    }
+    case kFamGemmSq:
+    case kFamGemmKa: {
+      if ((int64_t)chunk * kChunkK >= g.kp) return {0, 1, 1};
+      const int nsq = num_square(g.N);
+      const int nm = fam == kFamGemmSq ? nsq : g.N - nsq;
+      return {g.mp / kGemmTI, g.np / kGemmTJ, nm};
+    }
+    case kFamCrt:
+      return {(g.m + 255) / 256, g.n, 1};
+    default:
+      return {0, 1, 1};
+  }
+}
+
+__host__ __device__ inline int64_t family_blocks(int fam, const Problem &P, int chunk) {
+  const Dims d = family_dims(fam, P, chunk);
+  return d.x * d.y * d.z;
+}
+
+// A grouped launch: segment q covers problem order[q] and owns the blocks
+// [start[q], start[q + 1]) of the launch (start[nseg] = total).  A launch of
+// a single problem passes it by value instead and numbers its blocks from 0.
+struct Group {
+  const Problem *probs;
+  const int32_t *order;
+  const int64_t *start;
+  int nseg;
+  int64_t total;
+};
+
+#if defined(__HIPCC__)
+// Segment holding block b: the last q with start[q] <= b (start is sorted;
+// empty segments repeat a value).
+__device__ __forceinline__ int find_segment(const Group &G, int64_t b) {
+  int lo = 0, hi = G.nseg;  // start[lo] <= b < start[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (G.start[mid] <= b)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// The problem and local block number of block b: a single-problem launch
+// passes its problem by value (P1), a grouped one a Group.
+template <bool GROUPED>
+__device__ __forceinline__ const Problem *locate(const Problem &P1, const Group &G, int64_t b,
+                                                 int64_t &local) {
+  if constexpr (GROUPED) {
+    const int q = find_segment(G, b);
+    local = b - G.start[q];
+    return &G.probs[G.order[q]];
+  } else {
+    local = b;
+    return &P1;
+  }
+}
+
+// Local block coordinates of block `local` of a family grid.
+__device__ __forceinline__ Dims decode_block(const Dims &d, int64_t local) {
+  Dims c;
+  c.x = local % d.x;
+  const int64_t r = local / d.x;
+  c.y = r % d.y;
+  c.z = r / d.y;
+  return c;
+}
+#endif
+
 // ---- launchers (all asynchronous on `st`) ----
-hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t st);
-hipError_t launch_line_max(const Operand &op, uint64_t *amax, uint32_t *flags, hipStream_t st);
-hipError_t launch_bound_operand(const Operand &op, int64_t lines_pad, int64_t kp,
-                                const uint64_t *amax, int32_t *E, uint32_t *flags,
-                                uint8_t *bar, hipStream_t st);
-hipError_t launch_bound_gemm(const Geometry &g, const uint8_t *Abar, const uint8_t *Bbar,
-                             uint32_t *rmaxA, uint32_t *rmaxB, hipStream_t st);
-hipError_t launch_scale(const Geometry &g, const Tables *dt, const Work &w, hipStream_t st);
-hipError_t launch_residues(const Operand &op, int64_t lines_pad, int64_t kp,
-                           const int32_t *shift, const Tables *dt, int N, uint8_t *slices,
-                           hipStream_t st);
-hipError_t launch_residue_gemm(const Geometry &g, const Tables *dt, const uint8_t *Asl,
-                               const uint8_t *Bsl, int16_t *planes, hipStream_t st);
-hipError_t launch_crt(const Geometry &g, const Tables *dt, const Work &w, double alpha,
-                      double beta, double *C, int64_t ldc, int limbs, hipStream_t st);
+// Exactly one of P (a single problem, passed to the kernel by value) and G
+// (a grouped launch over device-resident problems) is non-null.  `chunk` is
+// the k chunk of the residue products; `grid` caps the number of workgroups
+// of a grouped product launch (0: one per tile), which then loop over tiles.
+hipError_t launch_quant_family(int fam, const Problem *P, const Group *G, hipStream_t st);
+hipError_t launch_scale_family(int fam, const Problem *P, const Group *G, hipStream_t st);
+hipError_t launch_gemm_family(int fam, const Problem *P, const Group *G, int chunk, int64_t grid,
+                              hipStream_t st);
+hipError_t launch_crt_family(const Problem *P, const Group *G, int limbs, hipStream_t st);
 hipError_t launch_scal(int64_t m, int64_t n, double beta, double *C, int64_t ldc,
                        hipStream_t st);
 

@@ -4,6 +4,8 @@
 //  - the residues of A', B' for every modulus, split into FP8 digits
 //    (eqs. def:A', def:B', CRTmatmul; digit splits of Sections III-B..III-D).
 // Outputs are K-contiguous: line r's k values at r * kp, zero padded.
+#include <string.h>
+
 #include "oz2_device.h"
 #include "oz2_internal.h"
 
@@ -14,25 +16,22 @@ namespace {
 constexpr uint64_t kAbsMask = 0x7FFFFFFFFFFFFFFFull;
 constexpr uint64_t kInfBits = 0x7FF0000000000000ull;
 
-__global__ void k_fill_u32(uint32_t *__restrict__ p, uint32_t v, int64_t count) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; i < count; i += stride) p[i] = v;
+__device__ __forceinline__ void fill_zero(uint32_t *p, int64_t count, int64_t blk,
+                                          int64_t nblk) {
+  for (int64_t i = blk * 256 + threadIdx.x; i < count; i += nblk * 256) p[i] = 0u;
 }
 
 // Maxima of |x| over finite entries, per line; non-finite entries flag the line.
 // Lines with contiguous k: one wave per line and k-chunk.
-__global__ __launch_bounds__(256) void k_line_max_kcontig(const double *__restrict__ x,
-                                                          int64_t lines, int64_t k,
-                                                          int64_t sr, int64_t hchunk,
-                                                          uint64_t *__restrict__ amax,
-                                                          uint32_t *__restrict__ flags) {
+__device__ __forceinline__ void line_max_kcontig(const Operand &op, const LmaxShape &sh,
+                                                 int64_t bx, int64_t by, uint64_t *amax,
+                                                 uint32_t *flags) {
   const int lane = threadIdx.x & 63;
-  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (r >= lines) return;
-  const int64_t h0 = (int64_t)blockIdx.y * hchunk;
-  const int64_t h1 = min(k, h0 + hchunk);
-  const double *row = x + r * sr;
+  const int64_t r = bx * 4 + (threadIdx.x >> 6);
+  if (r >= op.lines) return;
+  const int64_t h0 = by * sh.hchunk;
+  const int64_t h1 = min(op.k, h0 + sh.hchunk);
+  const double *row = op.ptr + r * op.sr;
   uint64_t m = 0;
   int bad = 0;
   for (int64_t h = h0 + lane; h < h1; h += 64) {
@@ -53,20 +52,18 @@ __global__ __launch_bounds__(256) void k_line_max_kcontig(const double *__restri
   }
 }
 
-// Lines contiguous in memory: one thread per line, k split over blockIdx.y.
-__global__ __launch_bounds__(256) void k_line_max_lcontig(const double *__restrict__ x,
-                                                          int64_t lines, int64_t k,
-                                                          int64_t sh, int64_t hchunk,
-                                                          uint64_t *__restrict__ amax,
-                                                          uint32_t *__restrict__ flags) {
-  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (r >= lines) return;
-  const int64_t h0 = (int64_t)blockIdx.y * hchunk;
-  const int64_t h1 = min(k, h0 + hchunk);
+// Lines contiguous in memory: one thread per line, k split over blocks.
+__device__ __forceinline__ void line_max_lcontig(const Operand &op, const LmaxShape &sh,
+                                                 int64_t bx, int64_t by, uint64_t *amax,
+                                                 uint32_t *flags) {
+  const int64_t r = bx * 256 + threadIdx.x;
+  if (r >= op.lines) return;
+  const int64_t h0 = by * sh.hchunk;
+  const int64_t h1 = min(op.k, h0 + sh.hchunk);
   uint64_t m = 0;
   int bad = 0;
   for (int64_t h = h0; h < h1; ++h) {
-    uint64_t b = (uint64_t)__double_as_longlong(x[r + h * sh]) & kAbsMask;
+    uint64_t b = (uint64_t)__double_as_longlong(op.ptr[r + h * op.sh]) & kAbsMask;
     if (b >= kInfBits)
       bad = 1;
     else
@@ -76,8 +73,32 @@ __global__ __launch_bounds__(256) void k_line_max_lcontig(const double *__restri
   if (bad) atomicOr(&flags[r], kNonFinite);
 }
 
+template <bool GROUPED>
+__global__ __launch_bounds__(256) void k_fill(Problem P1, Group G) {
+  int64_t local;
+  const Problem &P = *locate<GROUPED>(P1, G, blockIdx.x, local);
+  const Dims d = family_dims(kFamFill, P, 0);
+  fill_zero(P.w.zero, P.w.zero_words, local, d.x);
+}
+
+// SIDE 0: rows of op(A) (lines 0..mp-1), 1: columns of op(B) (lines mp..)
+template <bool GROUPED, int SIDE>
+__global__ __launch_bounds__(256) void k_line_max(Problem P1, Group G) {
+  int64_t local;
+  const Problem &P = *locate<GROUPED>(P1, G, blockIdx.x, local);
+  const Operand &op = SIDE == 0 ? P.A : P.B;
+  const int64_t base = SIDE == 0 ? 0 : P.g.mp;
+  const LmaxShape sh = lmax_shape(op);
+  const int64_t bx = local % sh.gx, by = local / sh.gx;
+  if (op.sh == 1)
+    line_max_kcontig(op, sh, bx, by, P.w.amax + base, P.w.flags + base);
+  else
+    line_max_lcontig(op, sh, bx, by, P.w.amax + base, P.w.flags + base);
+}
+
 constexpr int kTile = 64;        // lines x k per tile
 constexpr int kTileLd = 65;      // LDS row stride (doubles)
+static_assert(kTile == kQTile, "quantization tile");
 
 // Stage a 64 x 64 tile of the operand (zero outside lines x k) in LDS as
 // tile[line][h], loading along whichever dimension is contiguous.
@@ -98,23 +119,20 @@ __device__ __forceinline__ void load_tile(const double *__restrict__ x, int64_t 
   }
 }
 
-template <bool LCONTIG>
-__global__ __launch_bounds__(256) void k_bound_operand(const double *__restrict__ x, int64_t lines,
-                                                       int64_t k, int64_t sr, int64_t sh,
-                                                       int64_t kp, const uint64_t *__restrict__ amax,
-                                                       int32_t *__restrict__ E,
-                                                       uint32_t *__restrict__ flags,
-                                                       uint8_t *__restrict__ bar) {
-  __shared__ double tile[kTile * kTileLd];
-  const int64_t r0 = (int64_t)blockIdx.x * kTile;
-  const int64_t h0 = (int64_t)blockIdx.y * kTile;
-  load_tile<LCONTIG>(x, lines, k, sr, sh, r0, h0, tile);
+// FP8 round-up bound operand of one 64 x 64 tile (rows r0.., k h0..).
+__device__ __forceinline__ void bound_operand_tile(const Operand &op, int64_t kp, int64_t r0,
+                                                   int64_t h0, const uint64_t *amax, int32_t *E,
+                                                   uint32_t *flags, uint8_t *bar, double *tile) {
+  if (op.sr == 1)
+    load_tile<true>(op.ptr, op.lines, op.k, op.sr, op.sh, r0, h0, tile);
+  else
+    load_tile<false>(op.ptr, op.lines, op.k, op.sr, op.sh, r0, h0, tile);
   __syncthreads();
   const int rl = threadIdx.x >> 2, b = threadIdx.x & 3;
   const int64_t r = r0 + rl;
-  const uint64_t am = r < lines ? amax[r] : 0ull;
+  const uint64_t am = r < op.lines ? amax[r] : 0ull;
   const int Er = am ? ufp_exponent(am) : 0;
-  if (blockIdx.y == 0 && b == 0) {
+  if (h0 == 0 && b == 0) {
     E[r] = Er;
     if (am == 0) flags[r] |= kZeroLine;
   }
@@ -135,6 +153,19 @@ __global__ __launch_bounds__(256) void k_bound_operand(const double *__restrict_
   }
   uint4 out = make_uint4(packed[0], packed[1], packed[2], packed[3]);
   *(uint4 *)(bar + r * kp + h0 + b * 16) = out;
+}
+
+template <bool GROUPED, int SIDE>
+__global__ __launch_bounds__(256) void k_bound_operand(Problem P1, Group G) {
+  __shared__ double tile[kTile * kTileLd];
+  int64_t local;
+  const Problem &P = *locate<GROUPED>(P1, G, blockIdx.x, local);
+  const Operand &op = SIDE == 0 ? P.A : P.B;
+  const int64_t base = SIDE == 0 ? 0 : P.g.mp;
+  const Dims d = family_dims(SIDE == 0 ? kFamBarA : kFamBarB, P, 0);
+  const int64_t bx = local % d.x, by = local / d.x;
+  bound_operand_tile(op, P.g.kp, bx * kTile, by * kTile, P.w.amax + base, P.w.E + base,
+                     P.w.flags + base, SIDE == 0 ? P.w.Abar : P.w.Bbar, tile);
 }
 
 // Residues of a' = sign * mf * 2^t (mf < 2^53 an integer held exactly in a
@@ -160,17 +191,16 @@ __device__ __forceinline__ int residue_of(double mf, int t, const Tables *__rest
   return r;
 }
 
-template <bool LCONTIG>
-__global__ __launch_bounds__(256) void k_residues(const double *__restrict__ x, int64_t lines,
-                                                  int64_t k, int64_t sr, int64_t sh, int64_t kp,
-                                                  int64_t lines_pad,
-                                                  const int32_t *__restrict__ shift,
-                                                  const Tables *__restrict__ tab, int N,
-                                                  uint8_t *__restrict__ slices) {
-  __shared__ double tile[kTile * kTileLd];
-  const int64_t r0 = (int64_t)blockIdx.x * kTile;
-  const int64_t h0 = (int64_t)blockIdx.y * kTile;
-  load_tile<LCONTIG>(x, lines, k, sr, sh, r0, h0, tile);
+// Residues and FP8 digits of one 64 x 64 tile (rows r0.., k h0..).
+__device__ __forceinline__ void residues_tile(const Operand &op, int64_t kp, int64_t lines_pad,
+                                              int64_t r0, int64_t h0,
+                                              const int32_t *__restrict__ shift,
+                                              const Tables *__restrict__ tab, int N,
+                                              uint8_t *__restrict__ slices, double *tile) {
+  if (op.sr == 1)
+    load_tile<true>(op.ptr, op.lines, op.k, op.sr, op.sh, r0, h0, tile);
+  else
+    load_tile<false>(op.ptr, op.lines, op.k, op.sr, op.sh, r0, h0, tile);
   __syncthreads();
   const int rl = threadIdx.x >> 2, b = threadIdx.x & 3;
   const int64_t r = r0 + rl;
@@ -242,61 +272,57 @@ __global__ __launch_bounds__(256) void k_residues(const double *__restrict__ x, 
   }
 }
 
+template <bool GROUPED, int SIDE>
+__global__ __launch_bounds__(256) void k_residues(Problem P1, Group G) {
+  __shared__ double tile[kTile * kTileLd];
+  int64_t local;
+  const Problem &P = *locate<GROUPED>(P1, G, blockIdx.x, local);
+  const Operand &op = SIDE == 0 ? P.A : P.B;
+  const int64_t base = SIDE == 0 ? 0 : P.g.mp;
+  const Dims d = family_dims(SIDE == 0 ? kFamResA : kFamResB, P, 0);
+  const int64_t bx = local % d.x, by = local / d.x;
+  residues_tile(op, P.g.kp, SIDE == 0 ? P.g.mp : P.g.np, bx * kTile, by * kTile,
+                P.w.shift + base, P.tab, P.g.N, SIDE == 0 ? P.w.Asl : P.w.Bsl, tile);
+}
+
 }  // namespace
 
-hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t st) {
-  if (count <= 0) return hipSuccess;
-  int64_t blocks = (count + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, v, count);
-  return hipGetLastError();
-}
-
-hipError_t launch_line_max(const Operand &op, uint64_t *amax, uint32_t *flags, hipStream_t st) {
-  if (op.lines == 0 || op.k == 0) return hipSuccess;
-  if (op.sh == 1) {
-    // aim for >= 2048 waves in flight
-    int64_t gx = (op.lines + 3) / 4;
-    int64_t splits = (2048 + gx - 1) / gx;
-    int64_t hchunk = (op.k + splits - 1) / splits;
-    hchunk = ((hchunk + 63) / 64) * 64;
-    splits = (op.k + hchunk - 1) / hchunk;
-    hipLaunchKernelGGL(k_line_max_kcontig, dim3((unsigned)gx, (unsigned)splits), dim3(256), 0, st,
-                       op.ptr, op.lines, op.k, op.sr, hchunk, amax, flags);
-  } else {
-    int64_t gx = (op.lines + 255) / 256;
-    int64_t splits = (4096 + gx - 1) / gx;
-    if (splits > op.k) splits = op.k;
-    int64_t hchunk = (op.k + splits - 1) / splits;
-    splits = (op.k + hchunk - 1) / hchunk;
-    hipLaunchKernelGGL(k_line_max_lcontig, dim3((unsigned)gx, (unsigned)splits), dim3(256), 0, st,
-                       op.ptr, op.lines, op.k, op.sh, hchunk, amax, flags);
+hipError_t launch_quant_family(int fam, const Problem *P, const Group *G, hipStream_t st) {
+  const bool grouped = G != nullptr;
+  Problem p1;
+  Group g1;
+  memset(&p1, 0, sizeof(p1));
+  memset(&g1, 0, sizeof(g1));
+  if (grouped)
+    g1 = *G;
+  else
+    p1 = *P;
+  const int64_t blocks = grouped ? G->total : family_blocks(fam, *P, 0);
+  if (blocks <= 0) return hipSuccess;
+  if (blocks > 0x7FFFFFFFll) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)blocks), blk(256);
+#define OZ2_Q(KER)                                                          \
+  if (grouped)                                                              \
+    hipLaunchKernelGGL((KER<true>), grid, blk, 0, st, p1, g1);              \
+  else                                                                      \
+    hipLaunchKernelGGL((KER<false>), grid, blk, 0, st, p1, g1);
+#define OZ2_Q2(KER, SIDE)                                                   \
+  if (grouped)                                                              \
+    hipLaunchKernelGGL((KER<true, SIDE>), grid, blk, 0, st, p1, g1);        \
+  else                                                                      \
+    hipLaunchKernelGGL((KER<false, SIDE>), grid, blk, 0, st, p1, g1);
+  switch (fam) {
+    case kFamFill: OZ2_Q(k_fill) break;
+    case kFamLmaxA: OZ2_Q2(k_line_max, 0) break;
+    case kFamLmaxB: OZ2_Q2(k_line_max, 1) break;
+    case kFamBarA: OZ2_Q2(k_bound_operand, 0) break;
+    case kFamBarB: OZ2_Q2(k_bound_operand, 1) break;
+    case kFamResA: OZ2_Q2(k_residues, 0) break;
+    case kFamResB: OZ2_Q2(k_residues, 1) break;
+    default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_bound_operand(const Operand &op, int64_t lines_pad, int64_t kp,
-                                const uint64_t *amax, int32_t *E, uint32_t *flags, uint8_t *bar,
-                                hipStream_t st) {
-  dim3 grid((unsigned)(lines_pad / kTile), (unsigned)(kp / kTile));
-  if (op.sr == 1)
-    hipLaunchKernelGGL(k_bound_operand<true>, grid, dim3(256), 0, st, op.ptr, op.lines, op.k,
-                       op.sr, op.sh, kp, amax, E, flags, bar);
-  else
-    hipLaunchKernelGGL(k_bound_operand<false>, grid, dim3(256), 0, st, op.ptr, op.lines, op.k,
-                       op.sr, op.sh, kp, amax, E, flags, bar);
-  return hipGetLastError();
-}
-
-hipError_t launch_residues(const Operand &op, int64_t lines_pad, int64_t kp, const int32_t *shift,
-                           const Tables *dt, int N, uint8_t *slices, hipStream_t st) {
-  dim3 grid((unsigned)(lines_pad / kTile), (unsigned)(kp / kTile));
-  if (op.sr == 1)
-    hipLaunchKernelGGL(k_residues<true>, grid, dim3(256), 0, st, op.ptr, op.lines, op.k, op.sr,
-                       op.sh, kp, lines_pad, shift, dt, N, slices);
-  else
-    hipLaunchKernelGGL(k_residues<false>, grid, dim3(256), 0, st, op.ptr, op.lines, op.k, op.sr,
-                       op.sh, kp, lines_pad, shift, dt, N, slices);
+#undef OZ2_Q
+#undef OZ2_Q2
   return hipGetLastError();
 }
 

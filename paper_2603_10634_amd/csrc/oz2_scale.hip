@@ -24,6 +24,8 @@
 // summation order.  (Integer digit products stay exact: every product is an
 // integer of magnitude <= 256, far inside the 2^-13 window, and every partial
 // sum is at most 2^24.)
+#include <string.h>
+
 #include "oz2_internal.h"
 
 namespace oz2 {
@@ -40,16 +42,27 @@ __device__ __forceinline__ int exponent_rule(double x, double D) {
   return d >= 0 ? d / 2 : -((-d + 1) / 2);  // floor(d / 2)
 }
 
-__global__ void k_scale_decide(const uint32_t *__restrict__ rmax, uint32_t *__restrict__ flags,
-                               int32_t *__restrict__ e, uint32_t *__restrict__ amb,
-                               int64_t lines, double g_lo, double g_hi,
-                               const Tables *__restrict__ tab) {
-  const int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Decision window of the FP8 bound for a k extent of kp (see above).
+__device__ __forceinline__ void bound_window(int64_t kp, double &g_lo, double &g_hi) {
+  const double kd = (double)kp;
+  g_lo = (kd / 64.0 + 2.0) * 0x1p-23;
+  g_hi = 2.0 * (7.0 * 0x1p-13 + (kd / 7.0) * 0x1p-23);
+}
+
+template <bool GROUPED>
+__global__ __launch_bounds__(256) void k_scale_decide(Problem P1, Group G) {
+  int64_t local;
+  const Problem &P = *locate<GROUPED>(P1, G, blockIdx.x, local);
+  const int64_t L = local * 256 + threadIdx.x;
+  const int64_t lines = P.g.mp + P.g.np;
   if (L >= lines) return;
-  const float r = __uint_as_float(rmax[L]);
+  const Work &w = P.w;
+  double g_lo, g_hi;
+  bound_window(P.g.kp, g_lo, g_hi);
+  const float r = __uint_as_float(w.rmax[L]);
   int ev = 0;
-  if (r > 0.0f && !(flags[L] & kZeroLine)) {
-    const double D = tab->D;
+  if (r > 0.0f && !(w.flags[L] & kZeroLine)) {
+    const double D = P.tab->D;
     const double rd = (double)r;
     const double lo = rd * (1.0 - g_lo) * (1.0 - 0x1p-50);
     const double hi = rd * (1.0 + 2.0 * g_hi) * (1.0 + 0x1p-50);  // >= r' / (1 - g_hi)
@@ -57,35 +70,36 @@ __global__ void k_scale_decide(const uint32_t *__restrict__ rmax, uint32_t *__re
     const int e_large = exponent_rule(lo, D);
     ev = e_small;
     if (e_small != e_large) {
-      const uint32_t slot = atomicAdd(&amb[0], 1u);
-      amb[1 + slot] = (uint32_t)L;
-      flags[L] |= kFixup;
+      const uint32_t slot = atomicAdd(&w.amb[0], 1u);
+      w.amb[1 + slot] = (uint32_t)L;
+      w.flags[L] |= kFixup;
     }
   }
-  e[L] = ev;
+  w.e[L] = ev;
 }
 
-// Exact maxima of the bound product over the flagged lines.  Persistent: each
-// workgroup walks (line, block of 32 partner lines) items until all are done.
-__global__ __launch_bounds__(256) void k_scale_fixup(const uint8_t *__restrict__ Abar,
-                                                     const uint8_t *__restrict__ Bbar,
-                                                     int64_t mp, int64_t np, int64_t kp,
-                                                     const uint32_t *__restrict__ amb,
-                                                     uint64_t *__restrict__ rfix) {
+// Exact maxima of the bound product over the flagged lines.  Each of the
+// problem's nblk workgroups walks (line, block of 32 partner lines) items.
+__device__ __forceinline__ void scale_fixup(const uint8_t *__restrict__ Abar,
+                                            const uint8_t *__restrict__ Bbar, int64_t mp,
+                                            int64_t np, int64_t kp,
+                                            const uint32_t *__restrict__ amb,
+                                            uint64_t *__restrict__ rfix, int64_t blk,
+                                            int64_t nblk) {
   const uint32_t count = amb[0];
-  const int64_t nblk = ((mp > np ? mp : np) + 31) / 32;
-  const int64_t items = (int64_t)count * nblk;
+  const int64_t npb = ((mp > np ? mp : np) + 31) / 32;
+  const int64_t items = (int64_t)count * npb;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
-    const int64_t L = amb[1 + it / nblk];
-    const int64_t blk = it % nblk;
+  for (int64_t it = blk; it < items; it += nblk) {
+    const int64_t L = amb[1 + it / npb];
+    const int64_t pb = it % npb;
     const bool rowA = L < mp;
     const uint8_t *own = rowA ? Abar + L * kp : Bbar + (L - mp) * kp;
     const uint8_t *part = rowA ? Bbar : Abar;
     const int64_t npart = rowA ? np : mp;
     uint64_t best = 0;
     for (int z = 0; z < 8; ++z) {
-      const int64_t j = blk * 32 + wave * 8 + z;
+      const int64_t j = pb * 32 + wave * 8 + z;
       if (j >= npart) break;
       const uint8_t *other = part + j * kp;
       uint64_t sum = 0;
@@ -109,39 +123,58 @@ __global__ __launch_bounds__(256) void k_scale_fixup(const uint8_t *__restrict__
   }
 }
 
-__global__ void k_scale_finalize(const uint32_t *__restrict__ flags,
-                                 const uint64_t *__restrict__ rfix, const int32_t *__restrict__ E,
-                                 int32_t *__restrict__ e, int32_t *__restrict__ shift,
-                                 int64_t lines, const Tables *__restrict__ tab) {
-  const int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (L >= lines) return;
-  int ev = e[L];
-  if (flags[L] & kFixup) {
-    const uint64_t r18 = rfix[L];  // 2^18 x the exact line maximum, < 2^53
-    ev = r18 ? exponent_rule(ldexp((double)r18, -18), tab->D) : 0;
-    e[L] = ev;
+template <bool GROUPED>
+__global__ __launch_bounds__(256) void k_scale_fixup(Problem P1, Group G) {
+  int64_t local;
+  const Problem &P = *locate<GROUPED>(P1, G, blockIdx.x, local);
+  const Dims d = family_dims(kFamFixup, P, 0);
+  scale_fixup(P.w.Abar, P.w.Bbar, P.g.mp, P.g.np, P.g.kp, P.w.amb, P.w.rfix, local, d.x);
+}
+
+template <bool GROUPED>
+__global__ __launch_bounds__(256) void k_scale_finalize(Problem P1, Group G) {
+  int64_t local;
+  const Problem &P = *locate<GROUPED>(P1, G, blockIdx.x, local);
+  const int64_t L = local * 256 + threadIdx.x;
+  if (L >= P.g.mp + P.g.np) return;
+  const Work &w = P.w;
+  int ev = w.e[L];
+  if (w.flags[L] & kFixup) {
+    const uint64_t r18 = w.rfix[L];  // 2^18 x the exact line maximum, < 2^53
+    ev = r18 ? exponent_rule(ldexp((double)r18, -18), P.tab->D) : 0;
+    w.e[L] = ev;
   }
-  shift[L] = 7 - E[L] + ev;
+  w.shift[L] = 7 - w.E[L] + ev;
 }
 
 }  // namespace
 
-hipError_t launch_scale(const Geometry &g, const Tables *dt, const Work &w, hipStream_t st) {
-  const int64_t lines = g.mp + g.np;
-  const unsigned blocks = (unsigned)((lines + 255) / 256);
-  const double kp = (double)g.kp;
-  const double g_lo = (kp / 64.0 + 2.0) * 0x1p-23;
-  const double g_hi = 2.0 * (7.0 * 0x1p-13 + (kp / 7.0) * 0x1p-23);
-  hipLaunchKernelGGL(k_scale_decide, dim3(blocks), dim3(256), 0, st, w.rmax, w.flags, w.e, w.amb,
-                     lines, g_lo, g_hi, dt);
-  hipError_t err = hipGetLastError();
-  if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(k_scale_fixup, dim3(512), dim3(256), 0, st, w.Abar, w.Bbar, g.mp, g.np, g.kp,
-                     w.amb, w.rfix);
-  err = hipGetLastError();
-  if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(k_scale_finalize, dim3(blocks), dim3(256), 0, st, w.flags, w.rfix, w.E, w.e,
-                     w.shift, lines, dt);
+hipError_t launch_scale_family(int fam, const Problem *P, const Group *G, hipStream_t st) {
+  const bool grouped = G != nullptr;
+  Problem p1;
+  Group g1;
+  memset(&p1, 0, sizeof(p1));
+  memset(&g1, 0, sizeof(g1));
+  if (grouped)
+    g1 = *G;
+  else
+    p1 = *P;
+  const int64_t blocks = grouped ? G->total : family_blocks(fam, *P, 0);
+  if (blocks <= 0) return hipSuccess;
+  if (blocks > 0x7FFFFFFFll) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)blocks), blk(256);
+#define OZ2_S(KER)                                             \
+  if (grouped)                                                 \
+    hipLaunchKernelGGL((KER<true>), grid, blk, 0, st, p1, g1); \
+  else                                                         \
+    hipLaunchKernelGGL((KER<false>), grid, blk, 0, st, p1, g1);
+  switch (fam) {
+    case kFamDecide: OZ2_S(k_scale_decide) break;
+    case kFamFixup: OZ2_S(k_scale_fixup) break;
+    case kFamFinal: OZ2_S(k_scale_finalize) break;
+    default: return hipErrorInvalidValue;
+  }
+#undef OZ2_S
   return hipGetLastError();
 }
 

@@ -97,6 +97,21 @@ def test_alpha_beta(alpha, beta):
     assert _same(r.C, want)
 
 
+def test_alpha_beta_cancellation_rounds_twice():
+    """alpha Chat + beta C_in with heavy cancellation: the result must be
+    RN(RN(alpha Chat) + RN(beta C_in)), two roundings, not one fused
+    multiply-add (which differs exactly when the two terms cancel)."""
+    A, B = _inputs(130, 70, 200, 1.0, 4200)
+    Chat = ref.emulate(A, B, 12)
+    noise = phi_matrix(130, 70, 1.0, 4201) * 1e-9
+    alpha, beta = 2.0, -1.5
+    Cin = (alpha / -beta) * Chat * (1.0 + noise)        # beta C_in ~ -alpha Chat
+    r = run(A, B, 12, alpha=alpha, beta=beta, Cin=Cin, pad=(0, 0, 3))
+    assert r.status == 0
+    want = ref.combine_alpha_beta(Chat, alpha, beta, Cin)
+    assert _same(r.C, want)
+
+
 def test_beta_zero_does_not_read_C():
     A, B = _inputs(70, 50, 40, 1.0, 4100)
     Cin = np.full((70, 50), np.nan)

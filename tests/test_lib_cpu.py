@@ -103,3 +103,52 @@ def test_library_fails_loudly_when_missing(monkeypatch):
     monkeypatch.setattr(oz, "LIB_PATH", "/nonexistent/liboz2.so")
     with pytest.raises(ImportError):
         oz.lib()
+
+
+def test_batched_argument_errors_and_workspace():
+    d = 0
+    call = oz.ozaki2_dgemm_batched
+    one = lambda **kw: dict(dict(transA=["N"], transB=["N"], m=[4], n=[4], k=[4], alpha=[1.0],
+                                 A=[d], lda=[4], B=[d], ldb=[4], beta=[0.0], C=[d], ldc=[4],
+                                 num_moduli=12), **kw)
+    assert call(**one(transA=["X"])) == -2
+    assert call(**one(transB=["q"])) == -3
+    assert call(**one(m=[-1])) == -4
+    assert call(**one(n=[-1])) == -5
+    assert call(**one(k=[-1])) == -6
+    assert call(**one(lda=[3])) == -9
+    assert call(**one(ldb=[3])) == -11
+    assert call(**one(ldc=[3])) == -14
+    assert call(**one(num_moduli=0)) == -15
+    assert call(**one(num_moduli=21)) == -15
+    # the second problem is the invalid one
+    two = dict(transA=["N", "T"], transB=["N", "N"], m=[4, 4], n=[4, 4], k=[4, 5],
+               alpha=[1.0, 1.0], A=[d, d], lda=[4, 4], B=[d, d], ldb=[4, 5], beta=[0.0, 0.0],
+               C=[d, d], ldc=[4, 4], num_moduli=12)
+    assert call(**two) == -9
+    L = oz.lib()
+    assert L.ozaki2_dgemm_batched(-1, None, None, None, None, None, None, None, None, None,
+                                  None, None, None, None, 12) == -1
+    assert L.ozaki2_dgemm_batched(0, None, None, None, None, None, None, None, None, None,
+                                  None, None, None, None, 12) == 0
+    assert L.ozaki2_dgemm_batched(1, None, None, None, None, None, None, None, None, None,
+                                  None, None, None, None, 12) == -2
+    # empty outputs only: nothing to do, success without a device
+    assert call(**one(m=[0], lda=[1], ldc=[1])) == 0
+    # workspace of a batch = sum over problems with a nonempty product
+    ms, ns, ks = [300, 0, 64, 1000], [200, 5, 64, 17], [700, 9, 0, 4096]
+    want = sum(oz.ozaki2_workspace_bytes(a, b, c, 12) for a, b, c in zip(ms, ns, ks)
+               if a and b and c)
+    assert oz.ozaki2_workspace_bytes_batched(ms, ns, ks, 12) == want
+    assert oz.ozaki2_workspace_bytes_batched([1], [-1], [1], 12) == 0
+
+
+def test_batched_no_device_on_cpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    assert oz.ozaki2_dgemm_batched(["N"], ["N"], [4], [4], [4], [1.0], [0], [4], [0], [4],
+                                   [0.0], [0], [4], 12) == 5
+    assert oz.ozaki2_set_graph(True) == 0 and oz.ozaki2_set_graph(False) == 0
+    assert oz.ozaki2_set_autotune(True) == 0 and oz.ozaki2_set_autotune(False) == 0
+    assert oz.ozaki2_get_schedule() == -1

@@ -95,3 +95,13 @@ def from_colmajor(buf: np.ndarray, rows: int, cols: int, ld: int) -> np.ndarray:
     buf = np.ascontiguousarray(buf, dtype=np.float64)
     return np.lib.stride_tricks.as_strided(
         buf, shape=(rows, cols), strides=(8, 8 * ld)).copy()
+
+
+def batch_shapes(count: int, lo: int, hi: int, seed: int) -> list[tuple[int, int, int]]:
+    """`count` problem shapes (m, n, k), each dimension drawn independently and
+    log-uniformly from [lo, hi] and rounded to an integer (the uneven batch of
+    many small and mid-size products)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = np.exp(rng.uniform(np.log(lo), np.log(hi), size=(count, 3)))
+    x = np.clip(np.rint(x), lo, hi).astype(np.int64)
+    return [tuple(int(v) for v in row) for row in x]

@@ -67,12 +67,14 @@ __device__ __forceinline__ v16f mfma_f8(v8i a, v8i b, v16f c) {
 // Operand fragment of a 32-row sub-tile: lane l holds row (l % 32) and the 32
 // k bytes of logical chunks 2 (l / 32) and 2 (l / 32) + 1.  Both MFMA operands
 // are read with the same k assignment, so the dot products pair matching k.
+// row0 is always a multiple of 32, so the swizzle of row row0 + (l % 32) is
+// that of l % 32: the per-lane byte offsets do not depend on row0, and every
+// read is one per-lane address plus a constant (the ds_read immediate).
 __device__ __forceinline__ v8i lds_frag(const uint8_t *tile, int row0) {
   const int lane = threadIdx.x & 63;
-  const int r = row0 + (lane & 31);
-  const int g = lane >> 5;
-  const int f = swz(r);
-  const uint8_t *row = tile + r * ROWB;
+  const int x = lane & 31, g = lane >> 5;
+  const int f = swz(x);
+  const uint8_t *row = tile + (row0 + x) * ROWB;
   const v4i lo = *(const v4i *)(row + 16 * ((2 * g) ^ f));
   const v4i hi = *(const v4i *)(row + 16 * ((2 * g + 1) ^ f));
   return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
@@ -322,13 +324,12 @@ __device__ __forceinline__ void kloop(const uint8_t *const *gB, const uint8_t *c
     for (int ti = 0; ti < 2; ++ti) fa0[s][ti] = lds_frag(lds + NS * BSZ + s * ASZ, wi * 64 + ti * 32);
     fb[s][0] = lds_frag(lds + s * BSZ, wj * 128);
   }
-  // two stages per trip so that the A-side fragment buffers alternate by name
-  int j = 0;
-  for (; j + 1 < nk; j += 2) {
+  // two stages per trip so that the A-side fragment buffers alternate by
+  // name; nk is a multiple of 4 (k is padded to 256), so there is no tail
+  for (int j = 0; j < nk; j += 2) {
     stage_iter<NS, PAT>(j, nk, gB, gA, d, kbeg, lds, ring, fa0, fa1, fb, acc0, acc1);
     stage_iter<NS, PAT>(j + 1, nk, gB, gA, d, kbeg, lds, ring, fa1, fa0, fb, acc0, acc1);
   }
-  if (j < nk) stage_iter<NS, PAT>(j, nk, gB, gA, d, kbeg, lds, ring, fa0, fa1, fb, acc0, acc1);
   // the ring is free for the next use only when every wave is done with it
   __builtin_amdgcn_s_barrier();
 }
@@ -456,8 +457,226 @@ __device__ __forceinline__ void residue_tile(const uint8_t *Asl, const uint8_t *
   }
 }
 
-// Residue products of k chunk `chunk`: KIND 0 over the square moduli (tile
-// index z = l), 1 over the Karatsuba moduli (l = 6 + z).
+// ---------------------------------------------------------------------------
+// Wide single-product tiles: 256 (j) x 256 (i) per workgroup, each wave a
+// 128 x 128 block as 4 x 4 MFMA tiles in one accumulator (256 AGPRs).  Per
+// 64-k stage a wave issues 16 MFMAs against 16 KB of LDS fragment reads and
+// the workgroup moves 32 KB into LDS, so LDS traffic stays below the MFMA
+// time; the 256 x 128 two-accumulator tile above is kept for the square
+// moduli, whose three products share two operand slices per side.
+// ---------------------------------------------------------------------------
+constexpr int TIW = 256;                 // wide tile: i extent
+constexpr int ASZW = TIW * ROWB;         // bytes of one A-side tile
+constexpr int STAGEW = BSZ + ASZW;       // 32 KB per stage
+constexpr int SW = 4;                    // ring slots
+static_assert(SW * STAGEW <= LDS_RING, "wide ring");
+
+// Load number idx (0..7) of a wide stage: 0..3 B side, 4..7 A side, each 1 KB
+// = 16 rows; both sides have 256 rows, so one set of lane offsets serves both.
+__device__ __forceinline__ void dma_one_w(int idx, const uint8_t *gB, const uint8_t *gA,
+                                          const DmaOffsets &d, int64_t kofs, uint32_t slot) {
+  const uint32_t w = slot + d.lds_wave;
+  if (idx < 4)
+    dma16(gB + kofs, d.ob[idx], w + idx * 4096);
+  else
+    dma16(gA + kofs, d.ob[idx - 4], w + BSZ + (idx - 4) * 4096);
+}
+
+template <int Q>
+__device__ __forceinline__ void dma_part_w(const uint8_t *gB, const uint8_t *gA,
+                                           const DmaOffsets &d, int64_t kofs, uint32_t slot) {
+#pragma unroll
+  for (int idx = 2 * Q; idx < 2 * Q + 2; ++idx) {
+    dma_one_w(idx, gB, gA, d, kofs, slot);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// One stage of the wide loop, scheduled as stage_iter (blocks rows tj of 4
+// MFMAs; barrier B_j before the last block row; loads in four parts of 2).
+__device__ __forceinline__ void stage_iter_w(int j, int nk, const uint8_t *gB, const uint8_t *gA,
+                                             const DmaOffsets &d, int64_t kbeg,
+                                             const uint8_t *lds, uint32_t ring,
+                                             const v8i (&fa)[4], v8i (&fan)[4], v8i (&fb)[4],
+                                             v16f (&acc)[4][4]) {
+  constexpr int L = 8;
+  const int wave = threadIdx.x >> 6;
+  const int wj = wave >> 1, wi = wave & 1;
+  const uint8_t *cur = lds + (j % SW) * STAGEW;
+  const bool ld_prev = j + SW - 1 < nk;
+  const bool ld_next = j + SW < nk;
+  const bool rd_next = j + 1 < nk;
+  const int64_t kofs_prev = kbeg + (int64_t)(j + SW - 1) * BK;
+  const uint32_t slot_prev = ring + ((j + SW - 1) % SW) * STAGEW;
+#pragma unroll
+  for (int tj = 0; tj < 3; ++tj) {
+    fb[tj + 1] = lds_frag(cur, wj * 128 + (tj + 1) * 32);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti) {
+      acc[tj][ti] = mfma_f8(fb[tj], fa[ti], acc[tj][ti]);
+      __builtin_amdgcn_sched_barrier(0);
+      if (ti == 0 && ld_prev) {
+        if (tj == 0) dma_part_w<1>(gB, gA, d, kofs_prev, slot_prev);
+        if (tj == 1) dma_part_w<2>(gB, gA, d, kofs_prev, slot_prev);
+        if (tj == 2) dma_part_w<3>(gB, gA, d, kofs_prev, slot_prev);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  wait_lgkm0();
+  if (rd_next) wait_stages<L, SW - 2>(nk - 2 - j);
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_sched_barrier(0);
+  const uint8_t *nxt = lds + ((j + 1) % SW) * STAGEW;
+#pragma unroll
+  for (int ti = 0; ti < 4; ++ti) {
+    acc[3][ti] = mfma_f8(fb[3], fa[ti], acc[3][ti]);
+    __builtin_amdgcn_sched_barrier(0);
+    if (ti == 0 && ld_next)
+      dma_part_w<0>(gB, gA, d, kbeg + (int64_t)(j + SW) * BK, ring + (j % SW) * STAGEW);
+    if (rd_next) {
+      // five fragment reads after MFMAs 0, 0, 1, 1, 2
+      if (ti == 0) {
+        fan[0] = lds_frag(nxt + BSZ, wi * 128);
+        fan[1] = lds_frag(nxt + BSZ, wi * 128 + 32);
+      } else if (ti == 1) {
+        fan[2] = lds_frag(nxt + BSZ, wi * 128 + 64);
+        fan[3] = lds_frag(nxt + BSZ, wi * 128 + 96);
+      } else if (ti == 2) {
+        fb[0] = lds_frag(nxt, wj * 128);
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// acc += A B over nk stages of 64 k for one wide tile; gB / gA point at row
+// j0 / i0 of one B-side / A-side slice.
+__device__ __forceinline__ void kloop_w(const uint8_t *gB, const uint8_t *gA, int64_t kp,
+                                        int64_t kbeg, int nk, uint8_t *lds, v16f (&acc)[4][4]) {
+  constexpr int L = 8;
+  const int wave = threadIdx.x >> 6;
+  const int wj = wave >> 1, wi = wave & 1;
+  const DmaOffsets d = dma_offsets(kp);
+  const uint32_t ring = lds_offset(lds);
+#pragma unroll
+  for (int t = 0; t < SW - 1; ++t)
+    if (t < nk) {
+#pragma unroll
+      for (int idx = 0; idx < L; ++idx) dma_one_w(idx, gB, gA, d, kbeg + (int64_t)t * BK, ring + t * STAGEW);
+    }
+  if (SW - 1 < nk) dma_part_w<0>(gB, gA, d, kbeg + (int64_t)(SW - 1) * BK, ring + (SW - 1) * STAGEW);
+  if (SW - 1 < nk)
+    wait_vm<(SW - 2) * L + 2>();
+  else
+    wait_stages<L, SW - 2>(nk - 1);
+  __builtin_amdgcn_s_barrier();
+  v8i fa0[4], fa1[4], fb[4];
+#pragma unroll
+  for (int ti = 0; ti < 4; ++ti) fa0[ti] = lds_frag(lds + BSZ, wi * 128 + ti * 32);
+  fb[0] = lds_frag(lds, wj * 128);
+  // nk is a multiple of 4 (k is padded to 256): two stages per trip, no tail
+  for (int j = 0; j < nk; j += 2) {
+    stage_iter_w(j, nk, gB, gA, d, kbeg, lds, ring, fa0, fa1, fb, acc);
+    stage_iter_w(j + 1, nk, gB, gA, d, kbeg, lds, ring, fa1, fa0, fb, acc);
+  }
+  __builtin_amdgcn_s_barrier();
+}
+
+// Keeps the accumulator tiles in AGPRs at this point (an empty asm with
+// AGPR in/out operands), so the register allocator does not move the whole
+// accumulator to VGPRs around the folds between passes.
+__device__ __forceinline__ void pin_agpr(v16f (&acc)[4][4]) {
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti) asm volatile("" : "+a"(acc[tj][ti]));
+}
+
+// acc = smod(mul smod(acc)), one 16-value MFMA tile at a time.
+__device__ __forceinline__ void fold_w(v16f (&acc)[4][4], int mul, int p, float inv) {
+  pin_agpr(acc);
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti) {
+      v16f t16;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int t = smod_i32((int)acc[tj][ti][v], p, inv);
+        t16[v] = (float)smod_i32(mul * t, p, inv);
+      }
+      acc[tj][ti] = t16;
+      asm volatile("" : "+a"(acc[tj][ti]));
+      __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// One 256 x 256 tile (j0.., i0..) of Karatsuba modulus l (s = 16) over k in
+// [kbeg, kbeg + 64 nk), three single-product passes in one accumulator.
+// The digit products C1 = A1 B1, C2 = A2 B2, C3 = A3 B3 combine to
+// 240 C1 - 15 C2 + 16 C3 (eq. C'-Karatsuba) = 16 (C3 + 15 C1) - 15 C2:
+//   pass 1: acc = C1;        fold: acc = smod(15 smod(acc))
+//   pass 2: acc += C3;       fold: acc = smod(kinit smod(acc)),  kinit = -16/15 mod p
+//   pass 3: acc += C2;       result smod(-15 acc)
+// Every fold leaves |acc| < p/2 <= 256, so the FP32 accumulation of each pass
+// stays an exact integer below 2^24.
+__device__ __forceinline__ void karatsuba_tile_w(const uint8_t *Asl, const uint8_t *Bsl,
+                                                 int16_t *__restrict__ planes,
+                                                 const Tables *__restrict__ tab, int64_t mp,
+                                                 int64_t np, int64_t kp, int64_t kbeg, int nk,
+                                                 int accumulate, int l, int64_t i0, int64_t j0,
+                                                 uint8_t *lds) {
+  const int sl0 = (int)uni(tab->slice0[l]);
+  const int p = (int)uni(tab->p[l]);
+  const float inv = __int_as_float((int)uni(__float_as_int(tab->inv_p[l])));
+  const int kinit = (int)uni(tab->kinit[l]);
+  resident(sl0, p, __float_as_int(inv), kinit);
+  resident_ptr(planes, planes);
+  resident(accumulate, accumulate, accumulate, accumulate);
+  const int64_t sA = mp * kp, sB = np * kp;
+  const uint8_t *A0 = Asl + (int64_t)sl0 * sA + i0 * kp;
+  const uint8_t *B0 = Bsl + (int64_t)sl0 * sB + j0 * kp;
+
+  v16f acc[4][4];
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[tj][ti][v] = 0.0f;
+
+  pin_agpr(acc);
+  kloop_w(B0, A0, kp, kbeg, nk, lds, acc);                    // C1 (x1 slices)
+  fold_w(acc, 15, p, inv);
+  kloop_w(B0 + 2 * sB, A0 + 2 * sA, kp, kbeg, nk, lds, acc);  // + C3 (x3 slices)
+  fold_w(acc, kinit, p, inv);
+  kloop_w(B0 + sB, A0 + sA, kp, kbeg, nk, lds, acc);          // + C2 (x2 slices)
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wj = wave >> 1, wi = wave & 1;
+  int16_t *out = planes + (int64_t)l * np * mp;
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        int r = smod_i32(-15 * (int)acc[tj][ti][v], p, inv);
+        const int64_t i = i0 + wi * 128 + ti * 32 + (lane & 31);
+        const int64_t j = j0 + wj * 128 + tj * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+        int16_t *dst = out + j * mp + i;
+        if (accumulate) r = smod_i32(r + (int)*dst, p, inv);
+        *dst = (int16_t)r;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// Residue products of k chunk `chunk`: KIND 0 over the square moduli (256 x
+// 128 tiles, tile index z = l), 1 over the Karatsuba moduli (256 x 256
+// tiles, l = 6 + z).
 // A grouped launch may run fewer workgroups than tiles; each then loops.
 template <int KIND, bool GROUPED>
 __global__ __launch_bounds__(256, 1) void k_residue_gemm(Problem P1, Group G, int chunk) {
@@ -473,8 +692,12 @@ __global__ __launch_bounds__(256, 1) void k_residue_gemm(Problem P1, Group G, in
     const int64_t kbeg = (int64_t)chunk * kChunkK;
     const int64_t len = kp - kbeg < kChunkK ? kp - kbeg : kChunkK;
     const int l = (int)uni((KIND == 0 ? 0 : num_square(g.N)) + c.z);
-    residue_tile<KIND>(uni(P.w.Asl), uni(P.w.Bsl), uni(P.w.planes), uni(P.tab), mp, np, kp,
-                       kbeg, (int)(len / BK), chunk > 0 ? 1 : 0, l, uni(c.x * TI),
+    if (KIND == 0)
+      residue_tile<0>(uni(P.w.Asl), uni(P.w.Bsl), uni(P.w.planes), uni(P.tab), mp, np, kp, kbeg,
+                      (int)(len / BK), chunk > 0 ? 1 : 0, l, uni(c.x * TI), uni(c.y * TJ), lds);
+    else
+      karatsuba_tile_w(uni(P.w.Asl), uni(P.w.Bsl), uni(P.w.planes), uni(P.tab), mp, np, kp,
+                       kbeg, (int)(len / BK), chunk > 0 ? 1 : 0, l, uni(c.x * TIW),
                        uni(c.y * TJ), lds);
   }
 }

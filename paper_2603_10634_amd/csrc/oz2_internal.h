@@ -89,6 +89,7 @@ struct Problem {
 // Tile shapes of the kernels (the block grids below depend on them).
 constexpr int kGemmTI = 128;  // residue / bound products: output rows i per tile
 constexpr int kGemmTJ = 256;  // output columns j per tile
+constexpr int kGemmTIW = 256; // output rows i per tile of the Karatsuba products
 constexpr int kGemmBK = 64;   // k per pipeline stage
 constexpr int kQTile = 64;    // quantization passes: 64 lines x 64 k per block
 
@@ -178,8 +179,8 @@ __host__ __device__ inline Dims family_dims(int fam, const Problem &P, int chunk
     case kFamGemmKa: {
       if ((int64_t)chunk * kChunkK >= g.kp) return {0, 1, 1};
       const int nsq = num_square(g.N);
-      const int nm = fam == kFamGemmSq ? nsq : g.N - nsq;
-      return {g.mp / kGemmTI, g.np / kGemmTJ, nm};
+      if (fam == kFamGemmSq) return {g.mp / kGemmTI, g.np / kGemmTJ, nsq};
+      return {g.mp / kGemmTIW, g.np / kGemmTJ, g.N - nsq};
     }
     case kFamCrt:
       return {(g.m + 255) / 256, g.n, 1};

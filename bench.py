@@ -45,6 +45,10 @@ def _parse():
     ap.add_argument("--no-native", action="store_true")
     ap.add_argument("--traffic", type=str, default=None,
                     help="JSON file with measured HBM bytes per residue-product call")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="before the timed steps, run a plain device copy of 1 GiB "
+                         "(torch copy_) three times, as the reference kernel for "
+                         "scaling hardware byte counters")
     return ap.parse_args()
 
 
@@ -115,6 +119,13 @@ def main():
     for _ in range(args.warmup):
         call()
     torch.cuda.synchronize(dev)
+    if args.copy_calibration:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize(dev)
+        del src, dst
 
     # timed region: K calls; the library records HIP events between its kernel
     # groups on `stream`, read back after each call

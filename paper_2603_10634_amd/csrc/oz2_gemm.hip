@@ -56,7 +56,6 @@ __device__ __forceinline__ void wait_lgkm0() {
   __builtin_amdgcn_s_waitcnt(0xF | (0x7 << 4) | (0x0 << 8) | (0x3 << 14));
 }
 
-enum Pattern { kSquare = 0, kKara1 = 1, kOne = 2 };
 
 __device__ __forceinline__ v16f mfma_f8(v8i a, v8i b, v16f c) {
   // cbsz = blgp = 0 selects E4M3 for both operands; zero scale operands give
@@ -183,31 +182,16 @@ __device__ __forceinline__ void wait_stages(int a) {
   }
 }
 
-// Register fragments: fa[s][ti] is A-side slice s, 32-row block ti of this
-// wave's 64 rows; fb[s][tj] is B-side slice s, block tj of its 128 rows.
-// The i-th MFMA of block row tj (G per block row: 6 square, 4 Karatsuba
-// first pass, 2 single product).  Two products into one accumulator sit at
-// least 4 MFMAs apart.
-//   kSquare: slices 0 = x1, 1 = x2; acc0 += A2 B2, acc1 += A1 B2 + A2 B1
-//   kKara1:  slices 0 = x1, 1 = x3; acc0 += A3 B3, acc1 += A1 B1
-//   kOne:    acc0 += A B
-template <int PAT>
-constexpr int group_size() { return PAT == kSquare ? 6 : PAT == kKara1 ? 4 : 2; }
-
-template <int PAT, int NS>
-__device__ __forceinline__ void mfma_i(int i, int tj, const v8i (&fa)[NS][2],
-                                       const v8i (&fb)[NS][4], v16f (&acc0)[4][2],
+// Register fragments: fa[s][ti] is A-side slice s (0 = x1, 1 = x2), 32-row
+// block ti of this wave's 64 rows; fb[s][tj] is B-side slice s, block tj of
+// its 128 rows.  The i-th of the 6 MFMAs of block row tj: acc0 += A2 B2,
+// acc1 += A1 B2 + A2 B1; two products into one accumulator sit 4 MFMAs apart.
+__device__ __forceinline__ void mfma_i(int i, int tj, const v8i (&fa)[2][2],
+                                       const v8i (&fb)[2][4], v16f (&acc0)[4][2],
                                        v16f (&acc1)[4][2]) {
-  if (PAT == kSquare) {
-    if (i < 2) acc1[tj][i] = mfma_f8(fb[1][tj], fa[0][i], acc1[tj][i]);
-    else if (i < 4) acc0[tj][i - 2] = mfma_f8(fb[1][tj], fa[1][i - 2], acc0[tj][i - 2]);
-    else acc1[tj][i - 4] = mfma_f8(fb[0][tj], fa[1][i - 4], acc1[tj][i - 4]);
-  } else if (PAT == kKara1) {
-    if (i < 2) acc1[tj][i] = mfma_f8(fb[0][tj], fa[0][i], acc1[tj][i]);
-    else acc0[tj][i - 2] = mfma_f8(fb[NS - 1][tj], fa[NS - 1][i - 2], acc0[tj][i - 2]);
-  } else {
-    acc0[tj][i] = mfma_f8(fb[0][tj], fa[0][i], acc0[tj][i]);
-  }
+  if (i < 2) acc1[tj][i] = mfma_f8(fb[1][tj], fa[0][i], acc1[tj][i]);
+  else if (i < 4) acc0[tj][i - 2] = mfma_f8(fb[1][tj], fa[1][i - 2], acc0[tj][i - 2]);
+  else acc1[tj][i - 4] = mfma_f8(fb[0][tj], fa[1][i - 4], acc1[tj][i - 4]);
 }
 
 // Accumulate over nk stages of 64 k.  gB[s] / gA[s] point at row j0 / i0 of
@@ -226,7 +210,7 @@ __device__ __forceinline__ void mfma_i(int i, int tj, const v8i (&fa)[NS][2],
 //     behind MFMAs already in registers.
 // Loads are issued S - 2 to S - 1 stages before their barrier; at B_j the
 // loads of stages j + 2 .. j + S - 1 may still be in flight.
-template <int NS, int PAT>
+template <int NS>
 __device__ __forceinline__ void stage_iter(int j, int nk, const uint8_t *const *gB,
                                            const uint8_t *const *gA, const DmaOffsets &d,
                                            int64_t kbeg, const uint8_t *lds, uint32_t ring,
@@ -236,7 +220,8 @@ __device__ __forceinline__ void stage_iter(int j, int nk, const uint8_t *const *
   constexpr int STAGE = NS * (BSZ + ASZ);
   constexpr int S = NS == 2 ? 3 : 6;
   constexpr int L = 6 * NS;
-  constexpr int G = group_size<PAT>();
+  constexpr int G = 6;
+  static_assert(NS == 2, "square tile: two slices per side");
   const int wave = threadIdx.x >> 6;
   const int wj = wave >> 1, wi = wave & 1;
   const uint8_t *cur = lds + (j % S) * STAGE;
@@ -252,7 +237,7 @@ __device__ __forceinline__ void stage_iter(int j, int nk, const uint8_t *const *
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int i = 0; i < G; ++i) {
-      mfma_i<PAT, NS>(i, tj, fa, fb, acc0, acc1);
+      mfma_i(i, tj, fa, fb, acc0, acc1);
       __builtin_amdgcn_sched_barrier(0);
       if (i == 0 && ld_prev) {
         if (tj == 0) dma_part<NS, 1>(gB, gA, d, kofs_prev, slot_prev);
@@ -272,7 +257,7 @@ __device__ __forceinline__ void stage_iter(int j, int nk, const uint8_t *const *
   const uint8_t *nxt = lds + ((j + 1) % S) * STAGE;
 #pragma unroll
   for (int i = 0; i < G; ++i) {
-    mfma_i<PAT, NS>(i, 3, fa, fb, acc0, acc1);
+    mfma_i(i, 3, fa, fb, acc0, acc1);
     __builtin_amdgcn_sched_barrier(0);
     if (i == 0 && ld_next)
       dma_part<NS, 0>(gB, gA, d, kbeg + (int64_t)(j + S) * BK, ring + (j % S) * STAGE);
@@ -291,7 +276,7 @@ __device__ __forceinline__ void stage_iter(int j, int nk, const uint8_t *const *
   }
 }
 
-template <int NS, int PAT>
+template <int NS = 2>
 __device__ __forceinline__ void kloop(const uint8_t *const *gB, const uint8_t *const *gA,
                                       int64_t kp, int64_t kbeg, int nk, uint8_t *lds,
                                       v16f (&acc0)[4][2], v16f (&acc1)[4][2]) {
@@ -327,8 +312,8 @@ __device__ __forceinline__ void kloop(const uint8_t *const *gB, const uint8_t *c
   // two stages per trip so that the A-side fragment buffers alternate by
   // name; nk is a multiple of 4 (k is padded to 256), so there is no tail
   for (int j = 0; j < nk; j += 2) {
-    stage_iter<NS, PAT>(j, nk, gB, gA, d, kbeg, lds, ring, fa0, fa1, fb, acc0, acc1);
-    stage_iter<NS, PAT>(j + 1, nk, gB, gA, d, kbeg, lds, ring, fa1, fa0, fb, acc0, acc1);
+    stage_iter<NS>(j, nk, gB, gA, d, kbeg, lds, ring, fa0, fa1, fb, acc0, acc1);
+    stage_iter<NS>(j + 1, nk, gB, gA, d, kbeg, lds, ring, fa1, fa0, fb, acc0, acc1);
   }
   // the ring is free for the next use only when every wave is done with it
   __builtin_amdgcn_s_barrier();
@@ -367,22 +352,23 @@ __device__ __forceinline__ int smod_i32(int v, int p, float inv_p) {
   return r;
 }
 
-// One 256 x 128 output tile (j0.., i0..) of modulus l over k in
-// [kbeg, kbeg + 64 nk).  KIND 0: square modulus, 1: Karatsuba modulus.
+// One 256 x 128 output tile (j0.., i0..) of square modulus l (p = s^2) over
+// k in [kbeg, kbeg + 64 nk): the three digit products in two accumulators,
+// acc0 = A2 B2 and acc1 = A1 B2 + A2 B1, then s acc1 + acc0 reduced modulo p
+// (eq. 3matmult-notKaratsuba; s^2 A1 B1 vanishes modulo s^2).
 // (operand pointers carry no __restrict__: the prefetch fence in kloop must be
 // able to order their loads)
-template <int KIND>
-__device__ __forceinline__ void residue_tile(const uint8_t *Asl, const uint8_t *Bsl,
-                                             int16_t *__restrict__ planes,
-                                             const Tables *__restrict__ tab, int64_t mp,
-                                             int64_t np, int64_t kp, int64_t kbeg, int nk,
-                                             int accumulate, int l, int64_t i0, int64_t j0,
-                                             uint8_t *lds) {
+__device__ __forceinline__ void square_tile(const uint8_t *Asl, const uint8_t *Bsl,
+                                            int16_t *__restrict__ planes,
+                                            const Tables *__restrict__ tab, int64_t mp,
+                                            int64_t np, int64_t kp, int64_t kbeg, int nk,
+                                            int accumulate, int l, int64_t i0, int64_t j0,
+                                            uint8_t *lds) {
   const int sl0 = (int)uni(tab->slice0[l]);
   const int p = (int)uni(tab->p[l]);
   const float inv = __int_as_float((int)uni(__float_as_int(tab->inv_p[l])));
-  const int sv = (int)uni(KIND == 0 ? tab->s[l] : tab->kinit[l]);
-  resident(sl0, p, __float_as_int(inv), sv);
+  const int s = (int)uni(tab->s[l]);
+  resident(sl0, p, __float_as_int(inv), s);
   resident_ptr(planes, planes);
   resident(accumulate, accumulate, accumulate, accumulate);
   const int64_t sA = mp * kp, sB = np * kp;
@@ -392,69 +378,27 @@ __device__ __forceinline__ void residue_tile(const uint8_t *Asl, const uint8_t *
   v16f acc0[4][2], acc1[4][2];
   zero_acc(acc0);
   zero_acc(acc1);
+  const uint8_t *gB[2] = {B0, B0 + sB};
+  const uint8_t *gA[2] = {A0, A0 + sA};
+  kloop(gB, gA, kp, kbeg, nk, lds, acc0, acc1);
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wj = wave >> 1, wi = wave & 1;
   int16_t *out = planes + (int64_t)l * np * mp;
   // accumulator element (tj, ti, v) of this lane is entry (i, j) of C'_l
-  auto store = [&](int tj, int ti, int v, int r) {
-    const int64_t i = i0 + wi * 64 + ti * 32 + (lane & 31);
-    const int64_t j = j0 + wj * 128 + tj * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-    int16_t *dst = out + j * mp + i;
-    if (accumulate) r = smod_i32(r + (int)*dst, p, inv);
-    *dst = (int16_t)r;
-  };
-
-  if (KIND == 0) {
-    const uint8_t *gB[2] = {B0, B0 + sB};
-    const uint8_t *gA[2] = {A0, A0 + sA};
-    kloop<2, kSquare>(gB, gA, kp, kbeg, nk, lds, acc0, acc1);
-    const int s = sv;
-    // eq. 3matmult-notKaratsuba: s (A1 B2 + A2 B1) + A2 B2 (mod s^2)
 #pragma unroll
-    for (int tj = 0; tj < 4; ++tj)
+  for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
-      for (int ti = 0; ti < 2; ++ti)
+    for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-        for (int v = 0; v < 16; ++v)
-          store(tj, ti, v, smod_i32(s * (int)acc1[tj][ti][v] + (int)acc0[tj][ti][v], p, inv));
-  } else {
-    {
-      const uint8_t *gB[2] = {B0, B0 + 2 * sB};
-      const uint8_t *gA[2] = {A0, A0 + 2 * sA};
-      kloop<2, kKara1>(gB, gA, kp, kbeg, nk, lds, acc0, acc1);
-    }
-    // eq. C'-Karatsuba with s = 16: 240 C1 - 15 C2 + 16 C3 = 16 t - 15 C2 with
-    // t = 15 C1 + C3.  Modulo p this is -15 (C2 + t'), t' = kinit t: the
-    // second pass starts its accumulator at t' (|t'| < 256, so the sum stays
-    // an exact FP32 integer) and adds C2 on top.
-    const int kinit = sv;
-#pragma unroll
-    for (int tj = 0; tj < 4; ++tj)
-#pragma unroll
-      for (int ti = 0; ti < 2; ++ti)
-      {
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const int t = smod_i32(15 * (int)acc1[tj][ti][v] + (int)acc0[tj][ti][v], p, inv);
-          acc0[tj][ti][v] = (float)smod_i32(kinit * t, p, inv);
-        }
-        // one 16-value tile at a time keeps the compare masks few
-        __builtin_amdgcn_sched_barrier(0);
+      for (int v = 0; v < 16; ++v) {
+        int r = smod_i32(s * (int)acc1[tj][ti][v] + (int)acc0[tj][ti][v], p, inv);
+        const int64_t i = i0 + wi * 64 + ti * 32 + (lane & 31);
+        const int64_t j = j0 + wj * 128 + tj * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+        int16_t *dst = out + j * mp + i;
+        if (accumulate) r = smod_i32(r + (int)*dst, p, inv);
+        *dst = (int16_t)r;
       }
-    {
-      const uint8_t *gB[1] = {B0 + sB};
-      const uint8_t *gA[1] = {A0 + sA};
-      kloop<1, kOne>(gB, gA, kp, kbeg, nk, lds, acc0, acc1);
-    }
-#pragma unroll
-    for (int tj = 0; tj < 4; ++tj)
-#pragma unroll
-      for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-        for (int v = 0; v < 16; ++v)
-          store(tj, ti, v, smod_i32(-15 * (int)acc0[tj][ti][v], p, inv));
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -693,8 +637,8 @@ __global__ __launch_bounds__(256, 1) void k_residue_gemm(Problem P1, Group G, in
     const int64_t len = kp - kbeg < kChunkK ? kp - kbeg : kChunkK;
     const int l = (int)uni((KIND == 0 ? 0 : num_square(g.N)) + c.z);
     if (KIND == 0)
-      residue_tile<0>(uni(P.w.Asl), uni(P.w.Bsl), uni(P.w.planes), uni(P.tab), mp, np, kp, kbeg,
-                      (int)(len / BK), chunk > 0 ? 1 : 0, l, uni(c.x * TI), uni(c.y * TJ), lds);
+      square_tile(uni(P.w.Asl), uni(P.w.Bsl), uni(P.w.planes), uni(P.tab), mp, np, kp, kbeg,
+                  (int)(len / BK), chunk > 0 ? 1 : 0, l, uni(c.x * TI), uni(c.y * TJ), lds);
     else
       karatsuba_tile_w(uni(P.w.Asl), uni(P.w.Bsl), uni(P.w.planes), uni(P.tab), mp, np, kp,
                        kbeg, (int)(len / BK), chunk > 0 ? 1 : 0, l, uni(c.x * TIW),
@@ -702,38 +646,45 @@ __global__ __launch_bounds__(256, 1) void k_residue_gemm(Problem P1, Group G, in
   }
 }
 
-// Line maxima of one 256 x 128 tile of the bound product Abar Bbar.
+// Line maxima of one 256 x 256 tile of the bound product Abar Bbar (wide
+// single-product loop; FP32 accumulation in one fixed k order, so the result
+// does not depend on the tiling).
 __device__ __forceinline__ void bound_tile(const uint8_t *Abar, const uint8_t *Bbar, int64_t kp,
                                            int nk, uint32_t *__restrict__ rmaxA,
                                            uint32_t *__restrict__ rmaxB, int64_t i0, int64_t j0,
                                            uint8_t *lds) {
-  v16f acc0[4][2], acc1[4][2];
-  zero_acc(acc0);
-  const uint8_t *gB[1] = {Bbar + j0 * kp};
-  const uint8_t *gA[1] = {Abar + i0 * kp};
+  v16f acc[4][4];
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[tj][ti][v] = 0.0f;
   resident_ptr(rmaxA, rmaxB);
-  kloop<1, kOne>(gB, gA, kp, 0, nk, lds, acc0, acc1);
+  pin_agpr(acc);
+  kloop_w(Bbar + j0 * kp, Abar + i0 * kp, kp, 0, nk, lds, acc);
+  pin_agpr(acc);
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wj = wave >> 1, wi = wave & 1;
   // maxima over j of each column i (row maxima of Abar Bbar, for mu)
 #pragma unroll
-  for (int ti = 0; ti < 2; ++ti) {
+  for (int ti = 0; ti < 4; ++ti) {
     float m = 0.0f;
 #pragma unroll
     for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) m = fmaxf(m, acc0[tj][ti][v]);
+      for (int v = 0; v < 16; ++v) m = fmaxf(m, acc[tj][ti][v]);
     m = fmaxf(m, __shfl_xor(m, 32, 64));
     if (lane < 32)
-      atomicMax(&rmaxA[i0 + wi * 64 + ti * 32 + lane], __float_as_uint(m));
+      atomicMax(&rmaxA[i0 + wi * 128 + ti * 32 + lane], __float_as_uint(m));
   }
   // maxima over i of each row j (column maxima of Abar Bbar, for nu)
 #pragma unroll
   for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-      float m = fmaxf(acc0[tj][0][v], acc0[tj][1][v]);
+      float m = fmaxf(fmaxf(acc[tj][0][v], acc[tj][1][v]), fmaxf(acc[tj][2][v], acc[tj][3][v]));
 #pragma unroll
       for (int off = 16; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
       if ((lane & 31) == 0) {
@@ -756,7 +707,7 @@ __global__ __launch_bounds__(256, 1) void k_bound_gemm(Problem P1, Group G) {
     const int64_t mp = uni(g.mp), kp = uni(g.kp);
     uint32_t *rmax = uni(P.w.rmax);
     bound_tile(uni(P.w.Abar), uni(P.w.Bbar), kp, (int)(kp / BK), rmax, rmax + mp,
-               uni(c.x * TI), uni(c.y * TJ), lds);
+               uni(c.x * TIW), uni(c.y * TJ), lds);
   }
 }
 

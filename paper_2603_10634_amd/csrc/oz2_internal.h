@@ -89,7 +89,8 @@ struct Problem {
 // Tile shapes of the kernels (the block grids below depend on them).
 constexpr int kGemmTI = 128;  // residue / bound products: output rows i per tile
 constexpr int kGemmTJ = 256;  // output columns j per tile
-constexpr int kGemmTIW = 256; // output rows i per tile of the Karatsuba products
+constexpr int kGemmTIW = 256; // output rows i per tile of the single-product kernels
+                              // (Karatsuba products, bound product)
 constexpr int kGemmBK = 64;   // k per pipeline stage
 constexpr int kQTile = 64;    // quantization passes: 64 lines x 64 k per block
 
@@ -167,7 +168,7 @@ __host__ __device__ inline Dims family_dims(int fam, const Problem &P, int chunk
     case kFamResB:
       return {g.np / kQTile, g.kp / kQTile, 1};
     case kFamBgemm:
-      return {g.mp / kGemmTI, g.np / kGemmTJ, 1};
+      return {g.mp / kGemmTIW, g.np / kGemmTJ, 1};
     case kFamDecide:
     case kFamFinal:
       return {(g.mp + g.np + 255) / 256, 1, 1};

@@ -12,6 +12,9 @@ constexpr int kMaxN = OZ2_MAX_MODULI;
 constexpr int kLimbs = 8;        // 32-bit limbs for S = sum_l w_l u_l (< 2^256)
 constexpr int kPad = 256;        // every dimension is padded to this multiple
 constexpr int kChunkK = 1 << 15; // k handled by one residue-product launch
+constexpr int kPowT = 192;       // 2^t mod p is tabulated for t < kPowT; the integer
+                                 // a' = mant 2^t of an input never has t >= e + 8, and the
+                                 // scale exponent e stays below 110 for N <= 20
 
 // Moduli and CRT constants for one N, built on the host (oz2_tables.cpp) and
 // copied to device memory once per device and N.
@@ -24,13 +27,13 @@ struct Tables {
   int32_t s[kMaxN];           // digit radix: sqrt(p) for squares, 16 otherwise
   int32_t kind[kMaxN];        // 0 square (Section III-C), 1 Karatsuba (III-B)
   int32_t slice0[kMaxN];      // index of the modulus' first digit slice
-  int32_t smag[kMaxN];        // ceil(2^16 / s): floor(v / s) = (v * smag) >> 16 for v <= 560
   int32_t kinit[kMaxN];       // Karatsuba: -16 / 15 mod p (symmetric), see the residue products
-  int32_t pow2_32[kMaxN];     // 2^32 mod p
-  int32_t pow2lo[kMaxN][64];  // 2^t mod p, t < 64
-  int32_t pow2hi[kMaxN][4];   // 2^(64 t) mod p, t < 4
+  int32_t k16[kMaxN];         // 2^16 mod p
+  int32_t k32[kMaxN];         // 2^32 mod p
+  int32_t k48[kMaxN];         // 2^48 mod p
   float inv_p[kMaxN];         // 1/p, float
-  double inv_pd[kMaxN];       // 1/p, double
+  float inv_s[kMaxN];         // 1/s, float
+  uint16_t pw[kMaxN][kPowT];  // 2^t mod p, t < kPowT
   uint32_t w[kMaxN][kLimbs];  // CRT weights q_l P / p_l, little-endian limbs
   uint32_t P[kLimbs];         // product of the moduli
   uint32_t half[kLimbs];      // floor(P / 2)
@@ -92,7 +95,8 @@ constexpr int kGemmTJ = 256;  // output columns j per tile
 constexpr int kGemmTIW = 256; // output rows i per tile of the single-product kernels
                               // (Karatsuba products, bound product)
 constexpr int kGemmBK = 64;   // k per pipeline stage
-constexpr int kQTile = 64;    // quantization passes: 64 lines x 64 k per block
+constexpr int kQL = 32;       // quantization passes: 32 lines x 128 k per block
+constexpr int kQK = 128;
 
 // Kernel families of the emulation, in launch order.  One launch of a family
 // covers one problem or a whole group of problems (a batch).
@@ -163,10 +167,10 @@ __host__ __device__ inline Dims family_dims(int fam, const Problem &P, int chunk
     }
     case kFamBarA:
     case kFamResA:
-      return {g.mp / kQTile, g.kp / kQTile, 1};
+      return {g.mp / kQL, g.kp / kQK, 1};
     case kFamBarB:
     case kFamResB:
-      return {g.np / kQTile, g.kp / kQTile, 1};
+      return {g.np / kQL, g.kp / kQK, 1};
     case kFamBgemm:
       return {g.mp / kGemmTIW, g.np / kGemmTJ, 1};
     case kFamDecide:

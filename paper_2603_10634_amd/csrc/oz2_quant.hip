@@ -96,12 +96,16 @@ __global__ __launch_bounds__(256) void k_line_max(Problem P1, Group G) {
     line_max_lcontig(op, sh, bx, by, P.w.amax + base, P.w.flags + base);
 }
 
-constexpr int kTile = 64;        // lines x k per tile
-constexpr int kTileLd = 65;      // LDS row stride (doubles)
-static_assert(kTile == kQTile, "quantization tile");
+// Quantization tiles: 32 lines x 128 k per workgroup of 256 threads; thread t
+// owns line t / 8 and the 16 consecutive k (t % 8) * 16 .. + 15, so a line's
+// bytes of a tile leave as one 128-byte segment per output slice.  The FP64
+// tile is staged in LDS to read along whichever dimension is contiguous;
+// element h of a row sits at h + h / 16 (one pad double per 16) so that the
+// threads of one read (same q, consecutive t) fall into different banks.
+constexpr int kRowLd = kQK + kQK / 16 + 1;   // 137 doubles per staged row
 
-// Stage a 64 x 64 tile of the operand (zero outside lines x k) in LDS as
-// tile[line][h], loading along whichever dimension is contiguous.
+__device__ __forceinline__ int tile_at(int rr, int hh) { return rr * kRowLd + hh + (hh >> 4); }
+
 template <bool LCONTIG>
 __device__ __forceinline__ void load_tile(const double *__restrict__ x, int64_t lines, int64_t k,
                                           int64_t sr, int64_t sh, int64_t r0, int64_t h0,
@@ -109,26 +113,30 @@ __device__ __forceinline__ void load_tile(const double *__restrict__ x, int64_t 
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int idx = threadIdx.x + 256 * q;
-    const int a = idx >> 6, c = idx & 63;
-    const int rr = LCONTIG ? c : a;
-    const int hh = LCONTIG ? a : c;
+    const int rr = LCONTIG ? (idx & 31) : (idx >> 7);
+    const int hh = LCONTIG ? (idx >> 5) : (idx & 127);
     const int64_t r = r0 + rr, h = h0 + hh;
     double v = 0.0;
     if (r < lines && h < k) v = x[r * sr + h * sh];
-    tile[rr * kTileLd + hh] = v;
+    tile[tile_at(rr, hh)] = v;
   }
 }
 
-// FP8 round-up bound operand of one 64 x 64 tile (rows r0.., k h0..).
-__device__ __forceinline__ void bound_operand_tile(const Operand &op, int64_t kp, int64_t r0,
-                                                   int64_t h0, const uint64_t *amax, int32_t *E,
-                                                   uint32_t *flags, uint8_t *bar, double *tile) {
+__device__ __forceinline__ void stage_tile(const Operand &op, int64_t r0, int64_t h0,
+                                           double *tile) {
   if (op.sr == 1)
     load_tile<true>(op.ptr, op.lines, op.k, op.sr, op.sh, r0, h0, tile);
   else
     load_tile<false>(op.ptr, op.lines, op.k, op.sr, op.sh, r0, h0, tile);
+}
+
+// FP8 round-up bound operand of one tile (lines r0.., k h0..).
+__device__ __forceinline__ void bound_operand_tile(const Operand &op, int64_t kp, int64_t r0,
+                                                   int64_t h0, const uint64_t *amax, int32_t *E,
+                                                   uint32_t *flags, uint8_t *bar, double *tile) {
+  stage_tile(op, r0, h0, tile);
   __syncthreads();
-  const int rl = threadIdx.x >> 2, b = threadIdx.x & 3;
+  const int rl = threadIdx.x >> 3, b = threadIdx.x & 7;
   const int64_t r = r0 + rl;
   const uint64_t am = r < op.lines ? amax[r] : 0ull;
   const int Er = am ? ufp_exponent(am) : 0;
@@ -143,7 +151,7 @@ __device__ __forceinline__ void bound_operand_tile(const Operand &op, int64_t kp
     uint32_t word = 0;
 #pragma unroll
     for (int z = 0; z < 4; ++z) {
-      const double v = tile[rl * kTileLd + b * 16 + w * 4 + z];
+      const double v = tile[tile_at(rl, b * 16 + w * 4 + z)];
       const uint64_t bits = (uint64_t)__double_as_longlong(v);
       uint32_t code = 0;
       if ((bits & kAbsMask) < kInfBits) code = e4m3_round_up(bits, sh7);
@@ -151,119 +159,141 @@ __device__ __forceinline__ void bound_operand_tile(const Operand &op, int64_t kp
     }
     packed[w] = word;
   }
-  uint4 out = make_uint4(packed[0], packed[1], packed[2], packed[3]);
-  *(uint4 *)(bar + r * kp + h0 + b * 16) = out;
+  *(uint4 *)(bar + r * kp + h0 + b * 16) = make_uint4(packed[0], packed[1], packed[2], packed[3]);
 }
 
 template <bool GROUPED, int SIDE>
 __global__ __launch_bounds__(256) void k_bound_operand(Problem P1, Group G) {
-  __shared__ double tile[kTile * kTileLd];
+  __shared__ double tile[kQL * kRowLd];
   int64_t local;
   const Problem &P = *locate<GROUPED>(P1, G, blockIdx.x, local);
   const Operand &op = SIDE == 0 ? P.A : P.B;
   const int64_t base = SIDE == 0 ? 0 : P.g.mp;
   const Dims d = family_dims(SIDE == 0 ? kFamBarA : kFamBarB, P, 0);
   const int64_t bx = local % d.x, by = local / d.x;
-  bound_operand_tile(op, P.g.kp, bx * kTile, by * kTile, P.w.amax + base, P.w.E + base,
+  bound_operand_tile(op, P.g.kp, bx * kQL, by * kQK, P.w.amax + base, P.w.E + base,
                      P.w.flags + base, SIDE == 0 ? P.w.Abar : P.w.Bbar, tile);
 }
 
-// Residues of a' = sign * mf * 2^t (mf < 2^53 an integer held exactly in a
-// double) modulo p, as an integer in [0, p).
-__device__ __forceinline__ int residue_of(double mf, int t, const Tables *__restrict__ tab,
-                                          int l, double pd, double inv) {
-  double qd = floor(mf * inv);
-  double rd = fma(-qd, pd, mf);  // exact: the result is an integer below 2p in magnitude
-  if (rd < 0.0) rd += pd;
-  if (rd >= pd) rd -= pd;
-  int r = (int)rd;
-  if (t > 0) {
-    const int p = tab->p[l];
-    int f;
-    if (t < 256) {
-      f = (tab->pow2hi[l][t >> 6] * tab->pow2lo[l][t & 63]) % p;
-    } else {
-      f = 1;
-      for (int z = 0; z < t; ++z) f = (f * 2) % p;
-    }
-    r = (r * f) % p;
-  }
+// Symmetric remainder of |x| < 2^29 modulo p, in [lo, hi] = [-floor(p/2),
+// ceil(p/2) - 1].  The float quotient estimate is within 1 of the rounded
+// quotient (|x| p^-1 carries a relative error below 2^-22), so one correction
+// in either direction suffices; both products fit the 24-bit multiplier.
+__device__ __forceinline__ int mod_sym(int x, int p, float invp, int lo, int hi) {
+  const int q = (int)rintf((float)x * invp);
+  int r = x - __mul24(q, p);
+  r = r > hi ? r - p : r;
+  r = r < lo ? r + p : r;
   return r;
 }
 
-// Residues and FP8 digits of one 64 x 64 tile (rows r0.., k h0..).
+// Residues of a' (eq. def:A') for every modulus, split into FP8 digits, for
+// one tile (lines r0.., k h0..).
+//
+// Each finite input is |a| = mant 2^qe with mant < 2^53; with s = log2 mu_r
+// the integer is a' = sign (mant 2^t) for t = qe + s > 0, else
+// sign floor(mant 2^t) (eq. def:A': truncation toward zero).  The magnitude
+// m (mant or mant 2^t) is split into four 16-bit chunks carrying the sign,
+// so a' = c0 + c1 2^16 + c2 2^32 + c3 2^48 and
+//   a' = c0 + c1 (2^16 mod p) + c2 (2^32 mod p) + c3 (2^48 mod p)  (mod p)
+// is a sum below 2^29 in 24-bit multiply-adds; for t > 0 it is multiplied by
+// 2^t mod p afterwards.  Digits (Sections III-B, III-C) are formed in FP32,
+// exact for these small integers, and packed to E4M3 two at a time by the
+// hardware conversion (exact: every digit has |d| <= 16).
 __device__ __forceinline__ void residues_tile(const Operand &op, int64_t kp, int64_t lines_pad,
                                               int64_t r0, int64_t h0,
                                               const int32_t *__restrict__ shift,
                                               const Tables *__restrict__ tab, int N,
-                                              uint8_t *__restrict__ slices, double *tile) {
-  if (op.sr == 1)
-    load_tile<true>(op.ptr, op.lines, op.k, op.sr, op.sh, r0, h0, tile);
-  else
-    load_tile<false>(op.ptr, op.lines, op.k, op.sr, op.sh, r0, h0, tile);
+                                              uint8_t *__restrict__ slices, double *tile,
+                                              uint16_t *wtab) {
+  stage_tile(op, r0, h0, tile);
+  {
+    const uint16_t *src = &tab->pw[0][0];
+    for (int i = threadIdx.x; i < N * kPowT; i += 256) wtab[i] = src[i];
+  }
   __syncthreads();
-  const int rl = threadIdx.x >> 2, b = threadIdx.x & 3;
+  const int rl = threadIdx.x >> 3, b = threadIdx.x & 7;
   const int64_t r = r0 + rl;
   const int s = shift[r];  // log2(mu_r)
 
-  // a' = trunc(a 2^s) = sign * mf * 2^t, exactly
-  double mf[16];
-  int tt[16];
-  uint32_t neg = 0;
+  int c0[16], c1[16], c2[16], c3[16], tt[16];
+  bool big = false;
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
-    const uint64_t bits = (uint64_t)__double_as_longlong(tile[rl * kTileLd + b * 16 + q]);
-    mf[q] = 0.0;
-    tt[q] = 0;
+    const uint64_t bits = (uint64_t)__double_as_longlong(tile[tile_at(rl, b * 16 + q)]);
+    uint64_t m = 0;
+    int t = 0;
     if ((bits & kAbsMask) < kInfBits) {
       uint64_t mant;
       int qe;
       split_double(bits, mant, qe);
       const int e2 = qe + s;
-      if (e2 >= 0) {
-        mf[q] = (double)mant;
-        tt[q] = e2;
+      if (e2 > 0) {
+        m = mant;
+        t = e2 < kPowT ? e2 : kPowT - 1;
       } else if (e2 > -64) {
-        mf[q] = (double)(mant >> (-e2));
+        m = mant >> (-e2);
       }
-      if (bits >> 63) neg |= 1u << q;
     }
+    const int lo32 = (int)(uint32_t)m, hi32 = (int)(uint32_t)(m >> 32);
+    const int neg = (int)(bits >> 63);
+    // chunks with the sign of a
+    const int a0 = lo32 & 0xFFFF, a1 = (int)((uint32_t)lo32 >> 16);
+    const int a2 = hi32 & 0xFFFF, a3 = (int)((uint32_t)hi32 >> 16);
+    c0[q] = neg ? -a0 : a0;
+    c1[q] = neg ? -a1 : a1;
+    c2[q] = neg ? -a2 : a2;
+    c3[q] = neg ? -a3 : a3;
+    tt[q] = t;
+    big |= t > 0;
   }
+  const bool wave_big = __any(big);
 
   const int64_t slice_stride = lines_pad * kp;
   uint8_t *base = slices + r * kp + h0 + b * 16;
   for (int l = 0; l < N; ++l) {
     const int p = tab->p[l];
-    const int hlf = p >> 1;
+    const int lo = -(p >> 1), hi = p - 1 - (p >> 1);
+    const int K1 = tab->k16[l], K2 = tab->k32[l], K3 = tab->k48[l];
+    const float invp = tab->inv_p[l];
     const int kind = tab->kind[l];
-    const int srad = tab->s[l];
-    const int smag = tab->smag[l];
-    const double pd = (double)p, inv = tab->inv_pd[l];
-    uint32_t w1[4] = {0, 0, 0, 0}, w2[4] = {0, 0, 0, 0}, w3[4] = {0, 0, 0, 0};
+    const float sf = (float)tab->s[l], invs = tab->inv_s[l];
+    const uint16_t *wl = wtab + l * kPowT;
+    int w1[4] = {0, 0, 0, 0}, w2[4] = {0, 0, 0, 0}, w3[4] = {0, 0, 0, 0};
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      int u = residue_of(mf[q], tt[q], tab, l, pd, inv);
-      if ((neg >> q) & 1u) u = -u;
-      if (u > p - 1 - hlf) u -= p;  // symmetric range [-floor(p/2), ceil(p/2) - 1]
-      if (u < -hlf) u += p;
-      const int au = u < 0 ? -u : u;
-      int x1, x2, x3 = 0;
-      if (kind == 0) {
-        // p = s^2: x1 = round(u / s) (ties away from zero), x2 = u - s x1
-        int a1 = ((au + (srad >> 1)) * smag) >> 16;
-        x1 = u < 0 ? -a1 : a1;
-        x2 = u - srad * x1;
-      } else {
-        // s = 16: x1 = sign(u) ceil(|u| / 16), x2 = u - 16 x1, x3 = x1 + x2
-        int a1 = (au + 15) >> 4;
-        x1 = u < 0 ? -a1 : a1;
-        x2 = u - 16 * x1;
-        x3 = x1 + x2;
+    for (int g = 0; g < 4; ++g) {
+      float x1[4], x2[4], x3[4];
+#pragma unroll
+      for (int z = 0; z < 4; ++z) {
+        const int q = 4 * g + z;
+        const int x = c0[q] + __mul24(c1[q], K1) + __mul24(c2[q], K2) + __mul24(c3[q], K3);
+        int u = mod_sym(x, p, invp, lo, hi);
+        if (wave_big) {
+          const int w = tt[q] > 0 ? (int)wl[tt[q]] : 1;
+          u = mod_sym(__mul24(u, w), p, invp, lo, hi);
+        }
+        const float fu = (float)u;
+        if (kind == 0) {
+          // p = s^2: x1 = round(u / s) (ties away from zero), x2 = u - s x1
+          const float tq = fu * invs;
+          x1[z] = truncf(tq + copysignf(0.5f, tq)) + 0.0f;  // + 0 turns -0 into +0
+          x2[z] = fmaf(-sf, x1[z], fu);
+          x3[z] = 0.0f;
+        } else {
+          // s = 16: x1 = sign(u) ceil(|u| / 16), x2 = u - 16 x1, x3 = x1 + x2
+          x1[z] = copysignf(ceilf(fabsf(fu) * 0.0625f), fu);
+          x2[z] = fmaf(-16.0f, x1[z], fu);
+          x3[z] = x1[z] + x2[z];
+        }
       }
-      const int sh8 = 8 * (q & 3);
-      w1[q >> 2] |= e4m3_of_small_int(x1) << sh8;
-      w2[q >> 2] |= e4m3_of_small_int(x2) << sh8;
-      w3[q >> 2] |= e4m3_of_small_int(x3) << sh8;
+      w1[g] = __builtin_amdgcn_cvt_pk_fp8_f32(x1[0], x1[1], 0, false);
+      w1[g] = __builtin_amdgcn_cvt_pk_fp8_f32(x1[2], x1[3], w1[g], true);
+      w2[g] = __builtin_amdgcn_cvt_pk_fp8_f32(x2[0], x2[1], 0, false);
+      w2[g] = __builtin_amdgcn_cvt_pk_fp8_f32(x2[2], x2[3], w2[g], true);
+      if (kind != 0) {
+        w3[g] = __builtin_amdgcn_cvt_pk_fp8_f32(x3[0], x3[1], 0, false);
+        w3[g] = __builtin_amdgcn_cvt_pk_fp8_f32(x3[2], x3[3], w3[g], true);
+      }
     }
     uint8_t *dst = base + (int64_t)tab->slice0[l] * slice_stride;
     *(uint4 *)dst = make_uint4(w1[0], w1[1], w1[2], w1[3]);
@@ -274,15 +304,16 @@ __device__ __forceinline__ void residues_tile(const Operand &op, int64_t kp, int
 
 template <bool GROUPED, int SIDE>
 __global__ __launch_bounds__(256) void k_residues(Problem P1, Group G) {
-  __shared__ double tile[kTile * kTileLd];
+  __shared__ double tile[kQL * kRowLd];
+  __shared__ uint16_t wtab[kMaxN * kPowT];
   int64_t local;
   const Problem &P = *locate<GROUPED>(P1, G, blockIdx.x, local);
   const Operand &op = SIDE == 0 ? P.A : P.B;
   const int64_t base = SIDE == 0 ? 0 : P.g.mp;
   const Dims d = family_dims(SIDE == 0 ? kFamResA : kFamResB, P, 0);
   const int64_t bx = local % d.x, by = local / d.x;
-  residues_tile(op, P.g.kp, SIDE == 0 ? P.g.mp : P.g.np, bx * kTile, by * kTile,
-                P.w.shift + base, P.tab, P.g.N, SIDE == 0 ? P.w.Asl : P.w.Bsl, tile);
+  residues_tile(op, P.g.kp, SIDE == 0 ? P.g.mp : P.g.np, bx * kQL, by * kQK, P.w.shift + base,
+                P.tab, P.g.N, SIDE == 0 ? P.w.Asl : P.w.Bsl, tile, wtab);
 }
 
 }  // namespace

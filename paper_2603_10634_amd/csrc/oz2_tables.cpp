@@ -136,8 +136,7 @@ bool build_tables(int N, Tables *t) {
     t->slice0[l] = slice;
     slice += square ? 2 : 3;
     t->inv_p[l] = 1.0f / (float)p[l];
-    t->inv_pd[l] = 1.0 / (double)p[l];
-    t->smag[l] = (65536 + t->s[l] - 1) / t->s[l];
+    t->inv_s[l] = 1.0f / (float)t->s[l];
     if (!square) {
       // 16 t - 15 G2 = -15 (G2 + t') with t' = -16 t / 15 (mod p); p is coprime
       // to 15 because 1089 = 3^2 11^2 and 625 = 5^4 precede every Karatsuba modulus
@@ -146,17 +145,13 @@ bool build_tables(int N, Tables *t) {
       t->kinit[l] = c;
     }
     uint64_t v = 1;
-    for (int e = 0; e < 64; ++e) {
-      t->pow2lo[l][e] = (int32_t)v;
+    for (int e = 0; e < kPowT; ++e) {
+      t->pw[l][e] = (uint16_t)v;
+      if (e == 16) t->k16[l] = (int32_t)v;
+      if (e == 32) t->k32[l] = (int32_t)v;
+      if (e == 48) t->k48[l] = (int32_t)v;
       v = (v * 2) % p[l];
     }
-    uint64_t v64 = v;  // 2^64 mod p
-    uint64_t acc = 1;
-    for (int e = 0; e < 4; ++e) {
-      t->pow2hi[l][e] = (int32_t)acc;
-      acc = (acc * v64) % p[l];
-    }
-    t->pow2_32[l] = t->pow2lo[l][32];
   }
   t->M = slice;
 

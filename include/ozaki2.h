@@ -52,7 +52,7 @@ extern "C" {
 
 /* Largest number of moduli (the hybrid list keeps its six squares first for
  * N < 34, Section IV-B) and largest k handled in one call. */
-#define OZ2_MAX_MODULI 20
+#define OZ2_MAX_MODULI 33
 #define OZ2_MAX_K      (1 << 18)
 
 /*

@@ -92,12 +92,18 @@ __device__ __forceinline__ void crt_entry(const int16_t *__restrict__ planes,
     acc[L] = 0;
     const int16_t *pl = planes + j * mp + i;
     const int64_t pstride = mp * np;
-    for (int l = 0; l < N; ++l) {
-      int u = pl[l * pstride];
-      const int p = tab->p[l];
-      if (u < 0) u += p;
+    // all N residues are requested before the first is used
+    int uu[kMaxN];
 #pragma unroll
-      for (int q = 0; q < L; ++q) acc[q] += (uint64_t)tab->w[l][q] * (uint32_t)u;
+    for (int l = 0; l < kMaxN; ++l)
+      if (l < N) uu[l] = pl[l * pstride];
+#pragma unroll
+    for (int l = 0; l < kMaxN; ++l) {
+      if (l < N) {
+        const int u = uu[l] + (tab->p[l] & (uu[l] >> 31));  // C'_l mod p_l in [0, p_l)
+#pragma unroll
+        for (int q = 0; q < L; ++q) acc[q] += (uint64_t)tab->w[l][q] * (uint32_t)u;
+      }
     }
     uint32_t S[L + 1];
     uint64_t carry = 0;
@@ -111,7 +117,7 @@ __device__ __forceinline__ void crt_entry(const int16_t *__restrict__ planes,
     double sd = 0.0;
 #pragma unroll
     for (int q = 0; q <= L; ++q) sd += ldexp((double)S[q], 32 * q);
-    int64_t tq = (int64_t)floor(sd / tab->P_d);
+    int64_t tq = (int64_t)floor(sd * tab->inv_P_d);
     if (tq < 0) tq = 0;
     uint32_t R[L + 1];
     int64_t borrow = 0;
@@ -234,6 +240,9 @@ hipError_t launch_crt_family(const Problem *P, const Group *G, int limbs, hipStr
     OZ2_CRT_CASE(5)
     OZ2_CRT_CASE(6)
     OZ2_CRT_CASE(7)
+    OZ2_CRT_CASE(8)
+    OZ2_CRT_CASE(9)
+    OZ2_CRT_CASE(10)
     default:
       return hipErrorInvalidValue;
   }

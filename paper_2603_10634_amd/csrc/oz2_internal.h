@@ -9,12 +9,12 @@
 namespace oz2 {
 
 constexpr int kMaxN = OZ2_MAX_MODULI;
-constexpr int kLimbs = 8;        // 32-bit limbs for S = sum_l w_l u_l (< 2^256)
+constexpr int kLimbs = 11;       // 32-bit limbs for S = sum_l w_l u_l (P < 2^296 for N = 33)
 constexpr int kPad = 256;        // every dimension is padded to this multiple
 constexpr int kChunkK = 1 << 15; // k handled by one residue-product launch
 constexpr int kPowT = 192;       // 2^t mod p is tabulated for t < kPowT; the integer
                                  // a' = mant 2^t of an input never has t >= e + 8, and the
-                                 // scale exponent e stays below 110 for N <= 20
+                                 // scale exponent e stays below 160 for N <= 33
 
 // Moduli and CRT constants for one N, built on the host (oz2_tables.cpp) and
 // copied to device memory once per device and N.
@@ -37,7 +37,8 @@ struct Tables {
   uint32_t w[kMaxN][kLimbs];  // CRT weights q_l P / p_l, little-endian limbs
   uint32_t P[kLimbs];         // product of the moduli
   uint32_t half[kLimbs];      // floor(P / 2)
-  double P_d;                 // P rounded to double (estimate of quotients)
+  double P_d;                 // P rounded to double
+  double inv_P_d;             // 1 / P_d (estimate of quotients S / P)
   double D;                   // largest double <= P - 1 (scale rule)
 };
 

@@ -174,6 +174,7 @@ bool build_tables(int N, Tables *t) {
     for (size_t i = 0; i < others.size(); ++i) t->w[l][i] = others[i];
   }
   t->P_d = big_to_double(P, true);
+  t->inv_P_d = 1.0 / t->P_d;
   Big Pm1 = P;
   big_sub_one(Pm1);
   t->D = big_to_double(Pm1, false);

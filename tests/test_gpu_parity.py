@@ -32,7 +32,7 @@ def _same(a, b):
     return bool(np.all(both_nan | (a.view(np.int64) == b.view(np.int64))))
 
 
-@pytest.mark.parametrize("N", [1, 2, 3, 6, 7, 12, 13, 20])
+@pytest.mark.parametrize("N", [1, 2, 3, 6, 7, 12, 13, 20, 26, 33])
 def test_stage_parity_ragged(N):
     print(f"stage parity N={N} shape=(300, 200, 700)", flush=True)
     A, B = _inputs(300, 200, 700, 1.0, 1000 + N)

@@ -28,7 +28,7 @@ def test_every_header_function_is_exported(L):
 
 
 def test_moduli_match_oracle(L):
-    for N in range(1, 21):
+    for N in range(1, 34):
         p, kinds = oz.ozaki2_moduli(N)
         want = ref.hybrid_moduli(N)
         assert p == [q for q, _, _ in want]
@@ -36,12 +36,12 @@ def test_moduli_match_oracle(L):
     with pytest.raises(ValueError):
         oz.ozaki2_moduli(0)
     with pytest.raises(ValueError):
-        oz.ozaki2_moduli(21)
+        oz.ozaki2_moduli(34)
 
 
 @pytest.mark.parametrize("shape", [(1, 1, 1), (300, 200, 700), (8192, 8192, 8192),
                                    (1024, 1024, 65536), (16384, 16384, 1024)])
-@pytest.mark.parametrize("N", [1, 6, 7, 12, 20])
+@pytest.mark.parametrize("N", [1, 6, 7, 12, 20, 33])
 def test_workspace_layout(shape, N):
     m, n, k = shape
     off, pads = oz.ozaki2_workspace_layout(m, n, k, N)
@@ -75,7 +75,7 @@ def test_argument_errors(L):
     assert call("N", "T", 4, 5, 4, 1.0, d, 4, d, 4, 0.0, d, 4, 12) == -10
     assert call("N", "N", 4, 4, 4, 1.0, d, 4, d, 4, 0.0, d, 3, 12) == -13
     assert call("N", "N", 4, 4, 4, 1.0, d, 4, d, 4, 0.0, d, 4, 0) == -14
-    assert call("N", "N", 4, 4, 4, 1.0, d, 4, d, 4, 0.0, d, 4, 21) == -14
+    assert call("N", "N", 4, 4, 4, 1.0, d, 4, d, 4, 0.0, d, 4, 34) == -14
     # empty output: nothing to do, success without a device
     assert call("N", "N", 0, 4, 4, 1.0, d, 1, d, 4, 0.0, d, 1, 12) == 0
     assert call("n", "t", 4, 0, 4, 1.0, d, 4, d, 1, 0.0, d, 4, 12) == 0
@@ -120,7 +120,7 @@ def test_batched_argument_errors_and_workspace():
     assert call(**one(ldb=[3])) == -11
     assert call(**one(ldc=[3])) == -14
     assert call(**one(num_moduli=0)) == -15
-    assert call(**one(num_moduli=21)) == -15
+    assert call(**one(num_moduli=34)) == -15
     # the second problem is the invalid one
     two = dict(transA=["N", "T"], transB=["N", "N"], m=[4, 4], n=[4, 4], k=[4, 5],
                alpha=[1.0, 1.0], A=[d, d], lda=[4, 4], B=[d, d], ldb=[4, 5], beta=[0.0, 0.0],

@@ -43,8 +43,11 @@ def _parse():
                     help="rows of op(A) in the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-native", action="store_true")
-    ap.add_argument("--traffic", type=str, default=None,
-                    help="JSON file with measured HBM bytes per residue-product call")
+    ap.add_argument("--traffic", type=str,
+                    default=os.path.join(ROOT, "profiles", "residue_gemm_8192_n12_traffic.json"),
+                    help="JSON file with measured HBM bytes per residue-product call (used "
+                         "only for the workload it was measured on and while the GEMM "
+                         "source is unchanged)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="before the timed steps, run a plain device copy of 1 GiB "
                          "(torch copy_) three times, as the reference kernel for "
@@ -154,9 +157,12 @@ def main():
     res_flops = 3 * N * flops
     achieved = res_flops / (gemm_ms * 1e-3) / 1e12
     traffic = None
-    if args.traffic and os.path.exists(args.traffic):
+    if args.traffic and os.path.exists(args.traffic) and (m, n, k, N) == (8192, 8192, 8192, 12):
+        from paper_2603_10634_amd.profile_summary import gemm_source_sha
         with open(args.traffic) as f:
-            traffic = json.load(f).get("bytes_per_call")
+            rec = json.load(f)
+        if rec.get("gemm_source_sha256") == gemm_source_sha():
+            traffic = rec.get("bytes_per_call")
     roofline = {"bound": "mfma", "achieved": round(achieved, 1), "peak": FP8_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP8_PEAK_TFLOPS, 4),
                 "traffic": traffic,

@@ -41,6 +41,14 @@ R10 final rounding: one round-to-nearest-even of the exact rational C' 2^-t
 R11 FP8 is OCP E4M3FN (max 448): the bound operands reach 256.
 R12 k > 2^16: the residue products are summed in chunks of 2^16 and reduced
     modulo p (the modulo is linear), which is exact.
+R13 fast mode (Section III-E names it and says only that it bounds the sum of
+    |a'||b'| by the Cauchy-Schwarz inequality): r_i is the squared Euclidean
+    norm of row i of the round-up bound operand Abar (c_j: column j of Bbar),
+    and e_i follows the rule of R3.  Then
+    2 sum_h |a'_ih||b'_hj| <= 2^(e_i + f_j + 1) sum_h Abar_ih Bbar_hj
+                           <= 2^(e_i + f_j + 1) sqrt(r_i c_j) <= P - 1,
+    which is condition (3).  Squares of Abar are multiples of 2^-18, so r_i is
+    an exact integer multiple of 2^-18 (below 2^34 for k <= 2^18).
 """
 from __future__ import annotations
 
@@ -193,6 +201,20 @@ def exact_bound_product(Abar: np.ndarray, Bbar: np.ndarray) -> np.ndarray:
     return np.ldexp(Abar, 9) @ np.ldexp(Bbar, 9)
 
 
+def cauchy_schwarz_norms(Abar: np.ndarray, Bbar: np.ndarray):
+    """Squared Euclidean norms, scaled by 2^18, of the rows of Abar and the
+    columns of Bbar (fast mode, R13), as exact integers in float64.
+
+    2^9 Abar is an integer of at most 2^17, its square at most 2^34, and a sum
+    of k <= 2^18 such squares at most 2^52, so every partial sum is an exact
+    integer whatever order numpy sums in."""
+    if Abar.shape[1] > 2 ** 18:
+        raise ValueError("k too large for exact float64 norms")
+    r18 = (np.ldexp(Abar, 9) ** 2).sum(axis=1)
+    c18 = (np.ldexp(Bbar, 9) ** 2).sum(axis=0)
+    return r18, c18
+
+
 def scale_exponent(r18: int, P: int) -> int:
     """Largest integer e with 2^(2e+1) r <= P - 1, where r = r18 / 2^18 (R3, R5).
 
@@ -337,11 +359,14 @@ def inverse_scale(Cp: np.ndarray, sA: np.ndarray, sB: np.ndarray) -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 
-def scaling(opA: np.ndarray, opB: np.ndarray, num_moduli: int) -> dict:
+def scaling(opA: np.ndarray, opB: np.ndarray, num_moduli: int, mode: str = "accurate") -> dict:
     """Workflow steps 1-3 of Section IV-B: mu', nu', the round-up FP8 bound
-    operands, the bound product's line maxima and the scale exponents.
+    operands, the bound product's line maxima (accurate mode) or the bound
+    operands' line norms (fast mode, R13) and the scale exponents.
     Returns a dict with EA, EB, Abar, Bbar, r18, c18, e, f, sA = log2(mu),
     sB = log2(nu), the zeroed operands A, B and the non-finite flags."""
+    if mode not in ("accurate", "fast"):
+        raise ValueError("mode must be 'accurate' or 'fast'")
     opA = np.asarray(opA, dtype=np.float64)
     opB = np.asarray(opB, dtype=np.float64)
     m, k = opA.shape
@@ -360,11 +385,15 @@ def scaling(opA: np.ndarray, opB: np.ndarray, num_moduli: int) -> dict:
     EB = ufp_exponents(B, axis=0)
     Abar, Bbar = bound_operands(A, B, EA, EB)
 
-    # workflow steps 2-3: bound product, row/column maxima, scale exponents
-    W18 = exact_bound_product(Abar, Bbar)
-    r18 = W18.max(axis=1) if n else np.zeros(m)
-    c18 = W18.max(axis=0) if m else np.zeros(n)
-    del W18
+    if mode == "fast":
+        # fast mode: Cauchy-Schwarz norms in place of the bound product (R13)
+        r18, c18 = cauchy_schwarz_norms(Abar, Bbar)
+    else:
+        # workflow steps 2-3: bound product, row/column maxima, scale exponents
+        W18 = exact_bound_product(Abar, Bbar)
+        r18 = W18.max(axis=1) if n else np.zeros(m)
+        c18 = W18.max(axis=0) if m else np.zeros(n)
+        del W18
     e = np.array([scale_exponent(v, P) for v in r18], dtype=np.int64)
     f = np.array([scale_exponent(v, P) for v in c18], dtype=np.int64)
     return dict(moduli=mods, P=P, A=A, B=B, badA=badA, badB=badB, EA=EA, EB=EB,
@@ -401,13 +430,13 @@ def products(sc: dict, rows, cols, keep_stages: bool = False):
 
 
 def emulate(opA: np.ndarray, opB: np.ndarray, num_moduli: int,
-            keep_stages: bool = False):
-    """Chat ~ op(A) op(B) by the FP8 Ozaki-II scheme, accurate mode.
+            keep_stages: bool = False, mode: str = "accurate"):
+    """Chat ~ op(A) op(B) by the FP8 Ozaki-II scheme, accurate or fast mode.
 
     Returns Chat (m x n float64) and, with keep_stages, a dict of every
     intermediate quantity.  Implements Sections II and III-B..III-E in the
     order of the workflow of Section IV-B."""
-    sc = scaling(opA, opB, num_moduli)
+    sc = scaling(opA, opB, num_moduli, mode)
     m, n = sc["A"].shape[0], sc["B"].shape[1]
     Chat, st = products(sc, slice(0, m), slice(0, n), keep_stages)
     if not keep_stages:
@@ -417,12 +446,13 @@ def emulate(opA: np.ndarray, opB: np.ndarray, num_moduli: int,
     return Chat, st
 
 
-def emulate_sampled(opA: np.ndarray, opB: np.ndarray, num_moduli: int, rows, cols):
+def emulate_sampled(opA: np.ndarray, opB: np.ndarray, num_moduli: int, rows, cols,
+                    mode: str = "accurate"):
     """The entries Chat[rows][:, cols] of emulate(opA, opB, num_moduli), with
     the scale exponents of every line (they depend on the whole product) but
     the residue products, CRT and inverse scaling only for the sample.
     Returns (Chat_sample, scaling dict)."""
-    sc = scaling(opA, opB, num_moduli)
+    sc = scaling(opA, opB, num_moduli, mode)
     Chat, _ = products(sc, np.asarray(rows), np.asarray(cols), False)
     return Chat, sc
 
@@ -454,7 +484,7 @@ def _op_view(buf, trans, rows, cols, ld):
 
 def dgemm(transA: str, transB: str, m: int, n: int, k: int, alpha: float,
           A: np.ndarray, lda: int, B: np.ndarray, ldb: int, beta: float,
-          C: np.ndarray, ldc: int, num_moduli: int) -> np.ndarray:
+          C: np.ndarray, ldc: int, num_moduli: int, mode: str = "accurate") -> np.ndarray:
     """Column-major C <- alpha op(A) op(B) + beta C, emulated; returns a new
     flat C buffer (entries outside the m x n view are copied unchanged)."""
     Cout = np.array(C, dtype=np.float64, copy=True)
@@ -467,6 +497,6 @@ def dgemm(transA: str, transB: str, m: int, n: int, k: int, alpha: float,
         return Cout
     opA = _op_view(A, transA, m, k, lda)
     opB = _op_view(B, transB, k, n, ldb)
-    Chat = emulate(opA, opB, num_moduli)
+    Chat = emulate(opA, opB, num_moduli, mode=mode)
     view[...] = combine_alpha_beta(Chat, alpha, beta, Cin)
     return Cout

@@ -36,9 +36,9 @@ def check_scale_exponent_brute(P, r18_values):
         assert r * Fraction(2) ** (2 * e + 3) > P - 1
 
 
-def check_condition3(A, B, N):
+def check_condition3(A, B, N, mode="accurate"):
     """2 sum_h |a'_ih||b'_hj| < P for all i, j, in exact integers (eq. condition)."""
-    _, st = ref.emulate(A, B, N, keep_stages=True)
+    _, st = ref.emulate(A, B, N, keep_stages=True, mode=mode)
     Ai = [[int(x) for x in row] for row in st["Aint"]]
     Bi = [[int(x) for x in row] for row in st["Bint"]]
     m, k = len(Ai), len(Bi)
@@ -96,21 +96,21 @@ def check_crt_is_exact_product(A, B, N):
             assert int(st["Cp"][i, j]) == sum(Ai[i][h] * Bi[h][j] for h in range(k))
 
 
-def check_integer_inputs_exact(N=12):
+def check_integer_inputs_exact(N=12, mode="accurate"):
     """Integer inputs with small products: truncation is exact and C equals the
     exact product (a closed-form special case)."""
     A = integer_matrix(9, 33, 1000, 11)
     B = integer_matrix(33, 7, 1000, 12)
-    C = ref.emulate(A, B, N)
+    C = ref.emulate(A, B, N, mode=mode)
     exact = np.array([[sum(int(A[i, h]) * int(B[h, j]) for h in range(33))
                        for j in range(7)] for i in range(9)], dtype=np.float64)
     assert np.array_equal(C, exact)
 
 
-def check_error_bound(A, B, N):
+def check_error_bound(A, B, N, mode="accurate"):
     """|C - AB| <= sum_h(|da||b| + |a||db| + |da||db|) + half an ulp of C, with
     |da_ih| < 2^-log2(mu_i) from truncation (exact rationals)."""
-    C, st = ref.emulate(A, B, N, keep_stages=True)
+    C, st = ref.emulate(A, B, N, keep_stages=True, mode=mode)
     m, k = A.shape
     n = B.shape[1]
     for i in range(m):
@@ -123,6 +123,54 @@ def check_error_bound(A, B, N):
             c = float(C[i, j])
             ulp = Fraction(math.ulp(c)) if c != 0 else Fraction(2) ** -1074
             assert abs(Fraction(c) - exact) <= bound + ulp / 2
+
+
+def _e4m3_positive_values():
+    """Every positive finite E4M3FN value, decoded from its bit fields: 1 sign,
+    4 exponent (bias 7), 3 mantissa bits; exponent field 0 is subnormal and
+    the all-ones pattern S.1111.111 is NaN."""
+    vals = []
+    for code in range(1, 0x7F):
+        ex, man = code >> 3, code & 7
+        vals.append(Fraction(man, 8) * Fraction(2) ** -6 if ex == 0
+                    else (1 + Fraction(man, 8)) * Fraction(2) ** (ex - 7))
+    return sorted(vals)
+
+
+def check_fast_norms(A, B, N):
+    """Fast mode (Section III-E, Cauchy-Schwarz): r_i is the squared norm of
+    row i of the round-up bound operand, found here by brute force over the
+    E4M3 value set with exact rationals; the Cauchy-Schwarz inequality then
+    bounds every entry of the bound product, and the exponents follow the
+    scale rule."""
+    _, st = ref.emulate(A, B, N, keep_stages=True, mode="fast")
+    grid = _e4m3_positive_values()
+
+    def round_up(x):
+        return Fraction(0) if x == 0 else next(v for v in grid if v >= x)
+
+    def bars(X, E):
+        mu = Fraction(2) ** (7 - int(E))
+        return [round_up(mu * abs(Fraction(float(x)))) for x in X]
+
+    m, k = A.shape
+    n = B.shape[1]
+    rows = [bars(A[i, :], st["EA"][i]) for i in range(m)]
+    cols = [bars(B[:, j], st["EB"][j]) for j in range(n)]
+    r = [sum(v * v for v in row) for row in rows]
+    c = [sum(v * v for v in col) for col in cols]
+    for i in range(m):
+        assert Fraction(int(st["r18"][i]), 2 ** 18) == r[i]
+    for j in range(n):
+        assert Fraction(int(st["c18"][j]), 2 ** 18) == c[j]
+    for i in range(m):
+        for j in range(n):
+            w = sum(a * b for a, b in zip(rows[i], cols[j]))
+            assert w * w <= r[i] * c[j]
+    P = st["P"]
+    for x18, e in list(zip(st["r18"], st["e"])) + list(zip(st["c18"], st["f"])):
+        check_scale_exponent_brute(P, [x18])
+        assert ref.scale_exponent(x18, P) == e
 
 
 def check_integer_conversion(A, B, N):
@@ -156,15 +204,34 @@ def check_smod():
         assert np.all((xs - v) % p == 0)
 
 
-def check_invariants(A, B, N):
-    C = ref.emulate(A, B, N)
-    assert np.array_equal(ref.emulate(-A, B, N), -C)
-    assert np.array_equal(ref.emulate(A, -B, N), -C)
-    assert np.array_equal(ref.emulate(np.ldexp(A, 5), B, N), np.ldexp(C, 5))
-    assert np.array_equal(ref.emulate(A, np.ldexp(B, -3), N), np.ldexp(C, -3))
-    assert np.array_equal(ref.emulate(B.T.copy(), A.T.copy(), N), C.T)
+def check_invariants(A, B, N, mode="accurate"):
+    def em(X, Y):
+        return ref.emulate(X, Y, N, mode=mode)
+
+    C = em(A, B)
+    assert np.array_equal(em(-A, B), -C)
+    assert np.array_equal(em(A, -B), -C)
+    assert np.array_equal(em(np.ldexp(A, 5), B), np.ldexp(C, 5))
+    assert np.array_equal(em(A, np.ldexp(B, -3)), np.ldexp(C, -3))
+    assert np.array_equal(em(B.T.copy(), A.T.copy()), C.T)
     perm = np.random.default_rng(5).permutation(A.shape[0])
-    assert np.array_equal(ref.emulate(A[perm], B, N), C[perm])
+    assert np.array_equal(em(A[perm], B), C[perm])
+
+
+def check_fast_matches_accurate_when_tight(N):
+    """Where every row of Abar and every column of Bbar is one constant vector,
+    the Cauchy-Schwarz bound is attained (sum_h Abar Bbar = sqrt(r c)), so the
+    two modes must pick the same exponents and give the same result.  Inputs:
+    random signs times a power of two per row / column (Abar = Bbar = 128)."""
+    rng = np.random.default_rng(31)
+    m, k, n = 6, 40, 5
+    A = rng.choice([-1.0, 1.0], (m, k)) * np.ldexp(1.0, rng.integers(-20, 20, (m, 1)))
+    B = rng.choice([-1.0, 1.0], (k, n)) * np.ldexp(1.0, rng.integers(-20, 20, (1, n)))
+    Cf, sf = ref.emulate(A, B, N, keep_stages=True, mode="fast")
+    Ca, sa = ref.emulate(A, B, N, keep_stages=True)
+    assert np.array_equal(sf["e"], sa["e"]) and np.array_equal(sf["f"], sa["f"])
+    assert np.array_equal(sf["r18"], sa["r18"]) and np.array_equal(sf["c18"], sa["c18"])
+    assert np.array_equal(Cf, Ca)
 
 
 # ---- tests ----------------------------------------------------------------
@@ -181,6 +248,25 @@ def test_scale_exponent():
 def test_condition3(N):
     A, B = _small_problem(6, 5, 17, 2.0, 100 + N)
     check_condition3(A, B, N)
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 6, 7, 12, 13])
+def test_condition3_fast(N):
+    A, B = _small_problem(6, 5, 17, 2.0, 150 + N)
+    check_condition3(A, B, N, mode="fast")
+
+
+@pytest.mark.parametrize("N,phi", [(13, 1.0), (6, 4.0)])
+def test_fast_norms(N, phi):
+    A, B = _small_problem(5, 4, 14, phi, 160 + N)
+    A[1, :] = 0.0
+    A[2, 3] = 5e-324
+    check_fast_norms(A, B, N)
+
+
+@pytest.mark.parametrize("N", [1, 7, 12, 13])
+def test_fast_matches_accurate_when_tight(N):
+    check_fast_matches_accurate_when_tight(N)
 
 
 def test_bound_dominates():
@@ -203,12 +289,19 @@ def test_crt_exact_product(N):
 
 def test_integer_inputs_exact():
     check_integer_inputs_exact(12)
+    check_integer_inputs_exact(12, mode="fast")
 
 
 @pytest.mark.parametrize("N,phi", [(12, 0.5), (6, 1.0), (3, 4.0), (12, 4.0)])
 def test_error_bound(N, phi):
     A, B = _small_problem(4, 4, 21, phi, 400 + N)
     check_error_bound(A, B, N)
+
+
+@pytest.mark.parametrize("N,phi", [(13, 0.5), (6, 1.0), (13, 4.0)])
+def test_error_bound_fast(N, phi):
+    A, B = _small_problem(4, 4, 21, phi, 450 + N)
+    check_error_bound(A, B, N, mode="fast")
 
 
 @pytest.mark.parametrize("phi", [0.5, 4.0])
@@ -234,6 +327,7 @@ def test_ufp():
 def test_invariants():
     A, B = _small_problem(11, 9, 37, 1.0, 17)
     check_invariants(A, B, 12)
+    check_invariants(A, B, 13, mode="fast")
 
 
 def test_residue_product_chunked_k():
@@ -281,6 +375,23 @@ def test_accuracy_full_moduli():
     for N in (6, 8, 10, 12):
         errs.append(normalised_error(ref.emulate(A, B, N), hi, lo, np.abs(A), np.abs(B)))
     assert errs[0] > errs[1] > errs[2] > errs[3]
+
+
+def test_accuracy_fast_mode():
+    # Fast mode's Cauchy-Schwarz bound is looser than the bound product, so it
+    # may need one more modulus for the same accuracy (Section V-A uses 13 for
+    # fast mode against 12 for accurate mode).  Measured on these inputs:
+    # phi = 0.5 -> equal errors at N = 12, phi = 2 -> fast needs N = 13.
+    A, B = _small_problem(24, 20, 1500, 0.5, 500)
+    hi, lo = dd_dot_rows(A, B)
+    err = normalised_error(ref.emulate(A, B, 12, mode="fast"), hi, lo, np.abs(A), np.abs(B))
+    assert err <= 1e-15, err
+    A, B = _small_problem(24, 20, 1500, 2.0, 500)
+    hi, lo = dd_dot_rows(A, B)
+    acc12 = normalised_error(ref.emulate(A, B, 12), hi, lo, np.abs(A), np.abs(B))
+    fast12 = normalised_error(ref.emulate(A, B, 12, mode="fast"), hi, lo, np.abs(A), np.abs(B))
+    fast13 = normalised_error(ref.emulate(A, B, 13, mode="fast"), hi, lo, np.abs(A), np.abs(B))
+    assert fast12 > 1e-15 >= fast13 and fast12 >= acc12, (acc12, fast12, fast13)
 
 
 def test_dd_reference_against_rationals():

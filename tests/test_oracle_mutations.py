@@ -30,6 +30,9 @@ def _run_checks():
         ("intexact", lambda: core.check_integer_inputs_exact(12)),
         ("errbound", lambda: core.check_error_bound(A, B, 12)),
         ("invariants", lambda: core.check_invariants(A, B, 12)),
+        ("cond3_fast", lambda: core.check_condition3(A, B, 12, mode="fast")),
+        ("fastnorm", lambda: core.check_fast_norms(A, B, 13)),
+        ("fast_tight", lambda: core.check_fast_matches_accurate_when_tight(12)),
     ]
     for name, fn in checks:
         try:
@@ -107,6 +110,25 @@ def _fp8_route_sign(dA, dB, p, kind, s, chunk=2 ** 16):
     return ref.smod(s * s * c1 + c2 + s * (c3 + c1 - c2), p)
 
 
+def _norms_unsquared(Abar, Bbar):
+    return np.ldexp(Abar, 18).sum(axis=1), np.ldexp(Bbar, 18).sum(axis=0)
+
+
+def _norms_unscaled(Abar, Bbar):
+    return (Abar ** 2).sum(axis=1), (Bbar ** 2).sum(axis=0)
+
+
+def _norms_unrounded(Abar, Bbar):
+    # squares of the bound operand rounded down to a multiple of 2^-6 instead
+    # of taken exactly
+    return (np.ldexp(np.floor(np.ldexp(Abar, 6)), 3) ** 2).sum(axis=1), \
+        (np.ldexp(np.floor(np.ldexp(Bbar, 6)), 3) ** 2).sum(axis=0)
+
+
+def _norms_max_not_sum(Abar, Bbar):
+    return (np.ldexp(Abar, 9) ** 2).max(axis=1), (np.ldexp(Bbar, 9) ** 2).max(axis=0)
+
+
 def _smod_shifted(x, p):
     h = (p + 1) // 2
     return ((x + h) % p) - h
@@ -116,7 +138,7 @@ _orig = {name: getattr(ref, name) for name in (
     "digits_karatsuba", "digits_square", "crt_weights", "crt_reconstruct",
     "scale_exponent", "round_up_e4m3", "residues", "to_integers",
     "ufp_exponents", "inverse_scale", "residue_product", "residue_product_fp8",
-    "smod")}
+    "smod", "cauchy_schwarz_norms")}
 
 MUTATIONS = {
     "karatsuba_x3": ("digits_karatsuba", _kara_wrong_x3),
@@ -132,6 +154,10 @@ MUTATIONS = {
     "residue_product_off": ("residue_product", _residue_product_transposed_chunk),
     "karatsuba_recombine_sign": ("residue_product_fp8", _fp8_route_sign),
     "smod_shifted": ("smod", _smod_shifted),
+    "fast_norm_unsquared": ("cauchy_schwarz_norms", _norms_unsquared),
+    "fast_norm_unscaled": ("cauchy_schwarz_norms", _norms_unscaled),
+    "fast_norm_truncated": ("cauchy_schwarz_norms", _norms_unrounded),
+    "fast_norm_max": ("cauchy_schwarz_norms", _norms_max_not_sum),
 }
 
 

@@ -2,7 +2,8 @@
 
 Default workload: m = n = k = 8192, column-major 'N','N', entries
 (U[0,1) - 0.5) exp(0.5 N(0,1)) from a seeded PCG64, alpha = 1, beta = 0,
-12 moduli (the paper's full-accuracy count), accurate mode.  Inputs are
+12 moduli (the paper's full-accuracy count), accurate mode (--mode fast for
+the Cauchy-Schwarz scaling, with --moduli 13 as in the paper).  Inputs are
 resident in HBM before the timed region.  One step = one ozaki2_dgemm call
 (every stage of the path).  Prints one JSON line.
 
@@ -39,6 +40,8 @@ def _parse():
     ap.add_argument("--k", type=int, default=None)
     ap.add_argument("--moduli", type=int, default=12)
     ap.add_argument("--phi", type=float, default=0.5)
+    ap.add_argument("--mode", choices=["accurate", "fast"], default="accurate",
+                    help="scaling mode (fast: Cauchy-Schwarz bound, no bound product)")
     ap.add_argument("--cpu-rows", type=int, default=48,
                     help="rows of op(A) in the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -55,7 +58,7 @@ def _parse():
     return ap.parse_args()
 
 
-def _cpu_baseline(A, B, N, rows):
+def _cpu_baseline(A, B, N, rows, mode):
     """The oracle, as it stands, on op(A)[:rows] x op(B): a bounded slab of the
     same workload (its own emulated GEMM of shape rows x n x k)."""
     import numpy as np
@@ -67,14 +70,14 @@ def _cpu_baseline(A, B, N, rows):
         threads = os.cpu_count() or 1
     Asub = np.ascontiguousarray(A[:rows])
     t0 = time.perf_counter()
-    ref.emulate(Asub, B, N)
+    ref.emulate(Asub, B, N, mode=mode)
     dt = time.perf_counter() - t0
     m, k = Asub.shape
     n = B.shape[1]
     return {"value": 2.0 * m * n * k / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads),
             "kind": "oracle",
             "sample": f"oracle emulate() on op(A)[:{rows}] x op(B) ({m}x{n}x{k}, "
-                      f"N={N}), {dt:.1f} s wall"}
+                      f"N={N}, {mode} mode), {dt:.1f} s wall"}
 
 
 def main():
@@ -107,6 +110,8 @@ def main():
 
     stream = torch.cuda.current_stream(dev)
     oz.ozaki2_set_stream(stream)
+    if oz.ozaki2_set_mode(args.mode) != 0:
+        raise RuntimeError("ozaki2_set_mode failed")
     # caller-owned workspace (so the fix-up count can be read back afterwards)
     wbytes = oz.ozaki2_workspace_bytes(m, n, k, N)
     ws = torch.empty(wbytes + 256, dtype=torch.uint8, device=dev)
@@ -198,7 +203,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = _cpu_baseline(A, B, N, min(args.cpu_rows, m))
+        cpu = _cpu_baseline(A, B, N, min(args.cpu_rows, m), args.mode)
 
     stage = dict(zip(["quant", "gemms", "requant", "dequant", "others"],
                      [float(k_med[0] + k_med[3]), float(k_med[1] + k_med[4]), 0.0,
@@ -217,8 +222,9 @@ def main():
         "dtype": "fp8e4m3-mfma->f64",
         "data": "synthetic",
         "config": {"workload": f"emulated dgemm {m}x{n}x{k} col-major NN, phi={args.phi}, "
-                               f"{N} moduli, accurate mode",
+                               f"{N} moduli, {args.mode} mode",
                    "m": m, "n": n, "k": k, "num_moduli": N, "phi": args.phi,
+                   "mode": args.mode,
                    "alpha": 1.0, "beta": 0.0},
         "error_normalised": err_emu,
         "native_fp64": native,

@@ -2,12 +2,13 @@
  * ozaki2.h - C ABI of the MI355X (gfx950) FP8 Ozaki-II DGEMM emulation.
  *
  * The library computes C <- alpha * op(A) op(B) + beta * C for FP64 matrices
- * by the Ozaki-II scheme with FP8 quantization, accurate mode (Uchino, Ozaki,
- * Imamura, "Double-Precision Matrix Multiplication Emulation via Ozaki-II
- * Scheme with FP8 Quantization", arXiv 2603.10634):
+ * by the Ozaki-II scheme with FP8 quantization, accurate or fast mode (Uchino,
+ * Ozaki, Imamura, "Double-Precision Matrix Multiplication Emulation via
+ * Ozaki-II Scheme with FP8 Quantization", arXiv 2603.10634):
  *   1. per-row / per-column power-of-two scaling of op(A), op(B) to integers
  *      A', B' (Section II eqs. def:A', def:B'), with the scale chosen from an
- *      FP8 bound product (Section III-E);
+ *      FP8 bound product (accurate mode) or from Cauchy-Schwarz norms (fast
+ *      mode, Section III-E);
  *   2. residues of A', B' modulo the hybrid moduli 1089, 1024, 961, 841, 625,
  *      529, 511, 509, ... (Section III-D), split into FP8 E4M3 digits;
  *   3. three exact FP8 products per modulus on e4m3 MFMA with FP32
@@ -25,7 +26,8 @@
  *   - Work is enqueued on the stream set by ozaki2_set_stream (default: the
  *     null stream) and runs asynchronously; inputs must stay valid and
  *     unmodified until the stream reaches the end of the call.
- *   - Stream, workspace and timing settings are per host thread.
+ *   - Stream, workspace, timing, graph, autotune and mode settings are per
+ *     host thread.
  *   - Results are deterministic: the same inputs give bit-identical C on every
  *     call and for all four transA/transB storage combinations.
  *
@@ -55,8 +57,13 @@ extern "C" {
 #define OZ2_MAX_MODULI 33
 #define OZ2_MAX_K      (1 << 18)
 
+/* Scaling modes (ozaki2_set_mode). */
+#define OZ2_MODE_ACCURATE 0
+#define OZ2_MODE_FAST     1
+
 /*
- * ozaki2_dgemm - emulated DGEMM, accurate mode.
+ * ozaki2_dgemm - emulated DGEMM in the calling thread's mode (ozaki2_set_mode,
+ * accurate by default).
  *
  *  transA, transB  'N'/'n' (op(X) = X) or 'T'/'t'/'C'/'c' (op(X) = X^T).
  *  m, n, k         op(A) is m x k, op(B) is k x n, C is m x n; each >= 0.
@@ -127,7 +134,8 @@ int ozaki2_get_stage_times(float ms[5]);
 /*
  * ozaki2_get_kernel_times - milliseconds of each kernel group of the last
  * timed call, in launch order: [0] scaling pass 1 (maxima and bound
- * operands), [1] bound product, [2] scale exponents and fix-up, [3] residue
+ * operands, or their norms in fast mode), [1] bound product (empty in fast
+ * mode), [2] scale exponents and fix-up, [3] residue
  * and digit pass, [4] residue products with modular reduction, [5] CRT and
  * inverse scaling.  `count` is the capacity of ms; returns the number of
  * entries written (6), or a negative value on error.
@@ -148,15 +156,19 @@ int ozaki2_moduli(int num_moduli, int32_t *p, int32_t *kinds);
  *   off[0] int32  [m_pad + n_pad]  log2 of mu_i / nu_j (shift applied to each line)
  *   off[1] int32  [m_pad + n_pad]  E with ufp(max|x|) = 2^E per line (0 for zero lines)
  *   off[2] int32  [m_pad + n_pad]  scale exponent e_i / f_j (log2(mu/mu'))
- *   off[3] uint8  [m_pad x k_pad]  Abar, row i at i*k_pad (E4M3 codes)
- *   off[4] uint8  [n_pad x k_pad]  Bbar, column j of op(B) at j*k_pad
+ *   off[3] uint8  [m_pad x k_pad]  Abar, row i at i*k_pad (E4M3 codes; accurate mode)
+ *   off[4] uint8  [n_pad x k_pad]  Bbar, column j of op(B) at j*k_pad (accurate mode)
  *   off[5] uint8  [M x m_pad x k_pad]  digit slices of A' (slice order below)
  *   off[6] uint8  [M x n_pad x k_pad]  digit slices of B'
  *   off[7] int16  [N x n_pad x m_pad]  C'_l, entry (i, j) at l*n_pad*m_pad + j*m_pad + i
  *   off[8] uint32 [m_pad + n_pad]  FP32 bits of the bound product's line maxima
- *   off[9] uint32 [m_pad + n_pad]  line flags: 1 non-finite, 2 all zero, 4 exact fix-up
+ *          (accurate mode)
+ *   off[9] uint32 [m_pad + n_pad]  line flags: 1 non-finite, 2 all zero, 4 exponent
+ *          from an exact bound (fixed-up lines; every line in fast mode)
  *   off[10] uint32 [1 + m_pad + n_pad]  number of lines whose scale exponent
- *          the FP8 bound could not settle (recomputed exactly), then their indices
+ *          the FP8 bound could not settle (recomputed exactly), then their
+ *          indices (accurate mode)
+ * The layout, and so the workspace size, is the same in both modes.
  * Lines 0..m_pad-1 are rows of op(A), m_pad..m_pad+n_pad-1 columns of op(B).
  * Slices: modulus l contributes 2 (square) or 3 (Karatsuba) consecutive
  * slices, digit x1 first.  Also writes pads[0..2] = m_pad, n_pad, k_pad and
@@ -238,6 +250,28 @@ int ozaki2_set_autotune(int on);
  * first, bit 1 one workgroup per CU) of the calling thread's last batched
  * call, or -1 if there was none. */
 int ozaki2_get_schedule(void);
+
+/*
+ * ozaki2_set_mode - scaling mode of the calling thread's subsequent
+ * ozaki2_dgemm and ozaki2_dgemm_batched calls (Section III-E).  Both modes
+ * take mu_i = mu'_i 2^e_i, nu_j = nu'_j 2^f_j with e_i the largest integer
+ * with 2^(2 e_i + 1) r_i <= P - 1 (f_j likewise from c_j), which gives
+ * 2 sum_h |a'_ih||b'_hj| < P (condition (3)) since the entries of the bound
+ * product Abar Bbar are at most sqrt(r_i c_j):
+ *   OZ2_MODE_ACCURATE (default)  r_i, c_j are the row / column maxima of the
+ *        FP8 bound product Abar Bbar: one more FP8 product (3N + 1 in all).
+ *   OZ2_MODE_FAST  r_i, c_j are the squared Euclidean norms of the rows of
+ *        Abar and columns of Bbar (the Cauchy-Schwarz bound), summed exactly:
+ *        no bound product (3N products), but a looser scale, so wide-range
+ *        inputs may need one more modulus for the same accuracy (the paper
+ *        runs fast mode with 13 moduli against 12 in accurate mode).
+ * Both modes are deterministic.  Returns 0, or -1 for an unknown mode (the
+ * setting is then unchanged).
+ */
+int ozaki2_set_mode(int mode);
+
+/* ozaki2_get_mode - the calling thread's scaling mode. */
+int ozaki2_get_mode(void);
 
 /* ozaki2_release - free the calling thread's library-owned workspace, timing
  * events, cached batch plans and graphs. */

@@ -17,13 +17,17 @@ __all__ = [
     "ozaki2_set_workspace", "ozaki2_set_timing", "ozaki2_get_stage_times",
     "ozaki2_get_kernel_times", "ozaki2_moduli", "ozaki2_workspace_layout", "ozaki2_release",
     "ozaki2_status_string", "ozaki2_dgemm_batched", "ozaki2_workspace_bytes_batched",
-    "ozaki2_set_graph", "ozaki2_set_autotune", "ozaki2_get_schedule", "dgemm", "dgemm_batched",
+    "ozaki2_set_graph", "ozaki2_set_autotune", "ozaki2_get_schedule", "ozaki2_set_mode",
+    "ozaki2_get_mode", "MODE_ACCURATE", "MODE_FAST", "dgemm", "dgemm_batched",
     "LIB_PATH", "HEADER_PATH", "header_functions",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboz2.so")
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "ozaki2.h")
+
+MODE_ACCURATE = 0   # OZ2_MODE_ACCURATE
+MODE_FAST = 1       # OZ2_MODE_FAST
 
 _i64 = ctypes.c_int64
 _vp = ctypes.c_void_p
@@ -76,6 +80,8 @@ def lib() -> ctypes.CDLL:
         "ozaki2_set_graph": (ctypes.c_int, [ctypes.c_int]),
         "ozaki2_set_autotune": (ctypes.c_int, [ctypes.c_int]),
         "ozaki2_get_schedule": (ctypes.c_int, []),
+        "ozaki2_set_mode": (ctypes.c_int, [ctypes.c_int]),
+        "ozaki2_get_mode": (ctypes.c_int, []),
         "ozaki2_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     }
     for name, (res, args) in sig.items():
@@ -218,9 +224,46 @@ def ozaki2_get_schedule() -> int:
     return lib().ozaki2_get_schedule()
 
 
-def dgemm_batched(As, Bs, num_moduli: int = 12):
+def _mode_code(mode) -> int:
+    if isinstance(mode, str):
+        codes = {"accurate": MODE_ACCURATE, "fast": MODE_FAST}
+        if mode not in codes:
+            raise ValueError("mode must be 'accurate' or 'fast'")
+        return codes[mode]
+    return int(mode)
+
+
+def ozaki2_set_mode(mode) -> int:
+    """mode: MODE_ACCURATE / MODE_FAST, or 'accurate' / 'fast'."""
+    return lib().ozaki2_set_mode(_mode_code(mode))
+
+
+def ozaki2_get_mode() -> int:
+    return lib().ozaki2_get_mode()
+
+
+class _ModeScope:
+    """Sets the calling thread's mode for one call and restores it after."""
+
+    def __init__(self, mode):
+        self.mode = mode
+
+    def __enter__(self):
+        self.prev = ozaki2_get_mode()
+        if self.mode is not None:
+            st = ozaki2_set_mode(self.mode)
+            if st != 0:
+                raise Ozaki2Error("ozaki2_set_mode", st)
+
+    def __exit__(self, *exc):
+        ozaki2_set_mode(self.prev)
+        return False
+
+
+def dgemm_batched(As, Bs, num_moduli: int = 12, mode=None):
     """Row-major C_q = A_q B_q for lists of 2-D float64 CUDA tensors, as one
-    batched call on torch's current stream; returns the list of C_q."""
+    batched call on torch's current stream; returns the list of C_q.  `mode`
+    ('accurate' / 'fast', default: the thread's setting) applies to this call."""
     import torch
 
     As = [a.contiguous() for a in As]
@@ -239,19 +282,23 @@ def dgemm_batched(As, Bs, num_moduli: int = 12):
     if not args:
         return Cs
     ozaki2_set_stream(torch.cuda.current_stream(As[0].device))
-    st = ozaki2_dgemm_batched(["N"] * len(args), ["N"] * len(args), [x[0] for x in args],
-                              [x[1] for x in args], [x[2] for x in args], [1.0] * len(args),
-                              [x[3] for x in args], [x[4] for x in args], [x[5] for x in args],
-                              [x[6] for x in args], [0.0] * len(args), [x[7] for x in args],
-                              [x[8] for x in args], num_moduli)
+    with _ModeScope(mode):
+        st = ozaki2_dgemm_batched(["N"] * len(args), ["N"] * len(args), [x[0] for x in args],
+                                  [x[1] for x in args], [x[2] for x in args], [1.0] * len(args),
+                                  [x[3] for x in args], [x[4] for x in args],
+                                  [x[5] for x in args], [x[6] for x in args], [0.0] * len(args),
+                                  [x[7] for x in args], [x[8] for x in args], num_moduli)
     if st != 0:
         raise Ozaki2Error("ozaki2_dgemm_batched", st)
     return Cs
 
 
-def dgemm(A, B, num_moduli: int = 12, alpha: float = 1.0, beta: float = 0.0, C=None):
+def dgemm(A, B, num_moduli: int = 12, alpha: float = 1.0, beta: float = 0.0, C=None,
+          mode=None):
     """Row-major C = alpha A B + beta C for 2-D float64 CUDA tensors (via the
-    column-major identity C^T = B^T A^T).  Runs on torch's current stream."""
+    column-major identity C^T = B^T A^T).  Runs on torch's current stream.
+    `mode` ('accurate' / 'fast', default: the thread's setting) applies to
+    this call."""
     import torch
 
     if A.dtype != torch.float64 or B.dtype != torch.float64:
@@ -266,8 +313,9 @@ def dgemm(A, B, num_moduli: int = 12, alpha: float = 1.0, beta: float = 0.0, C=N
         C = torch.empty((m, n), dtype=torch.float64, device=A.device)
         beta = 0.0
     ozaki2_set_stream(torch.cuda.current_stream(A.device))
-    st = ozaki2_dgemm("N", "N", n, m, k, alpha, B, max(1, n), A, max(1, k), beta, C,
-                      max(1, n), num_moduli)
+    with _ModeScope(mode):
+        st = ozaki2_dgemm("N", "N", n, m, k, alpha, B, max(1, n), A, max(1, k), beta, C,
+                          max(1, n), num_moduli)
     if st != 0:
         raise Ozaki2Error("ozaki2_dgemm", st)
     return C

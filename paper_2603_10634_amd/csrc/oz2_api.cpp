@@ -38,6 +38,7 @@ struct ThreadState {
   bool graph = false;                      // capture launch sequences in hipGraphs
   bool autotune = false;                   // tune the grouped residue-product schedule
   int last_schedule = -1;                  // schedule of the last batched call
+  int mode = OZ2_MODE_ACCURATE;            // scaling mode (Section III-E)
   hipStream_t cap_stream = nullptr;        // private stream used only for capture
   int cap_dev = -1;
   std::list<std::unique_ptr<Plan>> plans;  // cached plans, most recent first
@@ -201,6 +202,7 @@ Problem make_problem(char transA, char transB, int64_t m, int64_t n, int64_t k, 
   P.C = C;
   P.ldc = ldc;
   P.limbs = limbs;
+  P.mode = g_ts.mode;
   return P;
 }
 
@@ -226,17 +228,23 @@ struct Marks {
   } while (0)
 
 // The launch sequence of one problem (workflow steps 1-10 of Section IV-B).
+// Fast mode replaces the bound operands, bound product and its decision by
+// the exact line norms of the bound operands (Section III-E).
 int enqueue_single(const Problem &P, hipStream_t st, Marks &mark) {
+  const bool fast = P.mode == OZ2_MODE_FAST;
   mark();
-  // step 1: mu', nu' and the FP8 bound operands
-  for (int f : {kFamFill, kFamLmaxA, kFamLmaxB, kFamBarA, kFamBarB})
+  // step 1: mu', nu' and the FP8 bound operands (fast mode: their line norms)
+  for (int f : {kFamFill, kFamLmaxA, kFamLmaxB}) OZ2_TRY(launch_quant_family(f, &P, nullptr, st));
+  for (int f : {fast ? kFamNormA : kFamBarA, fast ? kFamNormB : kFamBarB})
     OZ2_TRY(launch_quant_family(f, &P, nullptr, st));
   mark();
-  // step 2: the FP8 bound product (its line maxima only)
-  OZ2_TRY(launch_gemm_family(kFamBgemm, &P, nullptr, 0, 0, st));
+  // step 2: the FP8 bound product (its line maxima only; none in fast mode)
+  if (!fast) OZ2_TRY(launch_gemm_family(kFamBgemm, &P, nullptr, 0, 0, st));
   mark();
   // step 3: scale exponents mu, nu
-  for (int f : {kFamDecide, kFamFixup, kFamFinal}) OZ2_TRY(launch_scale_family(f, &P, nullptr, st));
+  if (!fast)
+    for (int f : {kFamDecide, kFamFixup}) OZ2_TRY(launch_scale_family(f, &P, nullptr, st));
+  OZ2_TRY(launch_scale_family(kFamFinal, &P, nullptr, st));
   mark();
   // steps 4-6: integers, residues and FP8 digits
   OZ2_TRY(launch_quant_family(kFamResA, &P, nullptr, st));
@@ -436,9 +444,16 @@ void build_subbatch(const std::vector<Problem> &probs, ImageWriter &W, SubBatch 
     L.G.total = start[np];
     sb->launches.push_back(L);
   };
-  for (int f : {kFamFill, kFamLmaxA, kFamLmaxB, kFamBarA, kFamBarB, kFamBgemm, kFamDecide,
-                kFamFixup, kFamFinal, kFamResA, kFamResB})
-    add(f, 0, 0);
+  // every problem of a batch has the calling thread's mode
+  if (probs[0].mode == OZ2_MODE_FAST) {
+    for (int f : {kFamFill, kFamLmaxA, kFamLmaxB, kFamNormA, kFamNormB, kFamFinal, kFamResA,
+                  kFamResB})
+      add(f, 0, 0);
+  } else {
+    for (int f : {kFamFill, kFamLmaxA, kFamLmaxB, kFamBarA, kFamBarB, kFamBgemm, kFamDecide,
+                  kFamFixup, kFamFinal, kFamResA, kFamResB})
+      add(f, 0, 0);
+  }
   for (int order = 0; order < 2; ++order)
     for (int c = 0; c < chunks; ++c) {
       add(kFamGemmSq, c, order);
@@ -814,6 +829,7 @@ int ozaki2_dgemm_batched(int count, const char *transA, const char *transB, cons
 
   KeyBuilder kb;
   kb.add(dev);
+  kb.add(ts.mode);
   kb.add(num_moduli);
   kb.add(count);
   kb.add(ws);
@@ -966,5 +982,13 @@ int ozaki2_set_autotune(int on) {
 }
 
 int ozaki2_get_schedule(void) { return g_ts.last_schedule; }
+
+int ozaki2_set_mode(int mode) {
+  if (mode != OZ2_MODE_ACCURATE && mode != OZ2_MODE_FAST) return -1;
+  g_ts.mode = mode;
+  return OZ2_SUCCESS;
+}
+
+int ozaki2_get_mode(void) { return g_ts.mode; }
 
 }  // extern "C"

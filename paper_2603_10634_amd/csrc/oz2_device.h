@@ -86,4 +86,12 @@ __device__ __forceinline__ uint32_t e4m3_of_small_int(int d) {
   return d < 0 ? (code | 0x80u) : code;
 }
 
+// 2^9 x the value of a non-negative E4M3 code (sign bit clear): an integer
+// below 2^18.  Subnormals (exponent field 0) are m 2^-9, normals
+// (8 + m) 2^(e - 10).
+__device__ __forceinline__ uint32_t e4m3_q9(uint32_t code) {
+  const uint32_t ex = code >> 3, man = code & 7u;
+  return ex ? (8u + man) << (ex - 1u) : man;
+}
+
 }  // namespace oz2

@@ -60,7 +60,8 @@ struct Work {
   uint64_t *amax;     // [mp + np] bits of max |x| per line
   uint32_t *rmax;     // [mp + np] FP32 bits of the bound product's line maxima
   uint32_t *flags;    // [mp + np]
-  uint64_t *rfix;     // [mp + np] exact line maxima (FP64 bits) for fix-ups
+  uint64_t *rfix;     // [mp + np] 2^18 x the exact line bound: bound-product maxima of
+                      // fixed-up lines (accurate mode), squared norms (fast mode)
   uint32_t *amb;      // [1 + mp + np] count, then the lines needing a fix-up
   uint8_t *Abar, *Bbar;
   uint8_t *Asl, *Bsl;
@@ -69,6 +70,7 @@ struct Work {
   int64_t zero_words;
 };
 
+// kFixup: the line's exponent comes from the exact bound in rfix.
 enum LineFlag : uint32_t { kNonFinite = 1u, kZeroLine = 2u, kFixup = 4u };
 
 // Operand view: line r (row of op(A) or column of op(B)), k-index h at
@@ -88,6 +90,7 @@ struct Problem {
   double *C;
   int64_t ldc;
   int32_t limbs;       // 32-bit limbs of P (host tables), selects the CRT kernel
+  int32_t mode;        // OZ2_MODE_ACCURATE or OZ2_MODE_FAST (selects the launch sequence)
 };
 
 // Tile shapes of the kernels (the block grids below depend on them).
@@ -107,6 +110,8 @@ enum Family : int {
   kFamLmaxB,
   kFamBarA,       // FP8 bound operands
   kFamBarB,
+  kFamNormA,      // fast mode: squared norms of the bound operands' lines
+  kFamNormB,
   kFamBgemm,      // FP8 bound product (line maxima)
   kFamDecide,     // scale exponents from the FP8 bound
   kFamFixup,      // exact bound product for undecided lines
@@ -167,9 +172,11 @@ __host__ __device__ inline Dims family_dims(int fam, const Problem &P, int chunk
       return {s.gx, s.splits, 1};
     }
     case kFamBarA:
+    case kFamNormA:
     case kFamResA:
       return {g.mp / kQL, g.kp / kQK, 1};
     case kFamBarB:
+    case kFamNormB:
     case kFamResB:
       return {g.np / kQL, g.kp / kQK, 1};
     case kFamBgemm:

@@ -1,6 +1,7 @@
 // Quantization passes over the FP64 inputs (HBM-bound):
 //  - line maxima of op(A) rows / op(B) columns (for mu', nu', eq. def:mu'nu'),
-//  - the round-up FP8 bound operands Abar, Bbar (Section III-E),
+//  - the round-up FP8 bound operands Abar, Bbar (Section III-E), or in fast
+//    mode the squared norms of their lines (Cauchy-Schwarz bound),
 //  - the residues of A', B' for every modulus, split into FP8 digits
 //    (eqs. def:A', def:B', CRTmatmul; digit splits of Sections III-B..III-D).
 // Outputs are K-contiguous: line r's k values at r * kp, zero padded.
@@ -173,6 +174,55 @@ __global__ __launch_bounds__(256) void k_bound_operand(Problem P1, Group G) {
   const int64_t bx = local % d.x, by = local / d.x;
   bound_operand_tile(op, P.g.kp, bx * kQL, by * kQK, P.w.amax + base, P.w.E + base,
                      P.w.flags + base, SIDE == 0 ? P.w.Abar : P.w.Bbar, tile);
+}
+
+// Fast mode: 2^18 x the squared Euclidean norm of every line of the round-up
+// bound operand over one tile, added to norm[r] (Section III-E, the
+// Cauchy-Schwarz bound; with r_i, c_j these norms, the bound product obeys
+// (Abar Bbar)_ij <= sqrt(r_i c_j)).  Abar is not stored.  Each 2^9 Abar is an
+// integer of at most 2^17, so the sums are exact 64-bit integers (at most
+// 2^52 for k <= 2^18) and do not depend on the order of the additions.
+// Every line is flagged to take its exponent from this exact value.
+__device__ __forceinline__ void bound_norm_tile(const Operand &op, int64_t r0, int64_t h0,
+                                                const uint64_t *amax, int32_t *E,
+                                                uint32_t *flags, uint64_t *norm,
+                                                double *tile) {
+  stage_tile(op, r0, h0, tile);
+  __syncthreads();
+  const int rl = threadIdx.x >> 3, b = threadIdx.x & 7;
+  const int64_t r = r0 + rl;
+  const uint64_t am = r < op.lines ? amax[r] : 0ull;
+  const int Er = am ? ufp_exponent(am) : 0;
+  if (h0 == 0 && b == 0) {
+    E[r] = Er;
+    flags[r] |= am ? kFixup : (kFixup | kZeroLine);
+  }
+  const int sh7 = 7 - Er;  // mu' = 2^(7 - E)
+  uint64_t sum = 0;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const uint64_t bits = (uint64_t)__double_as_longlong(tile[tile_at(rl, b * 16 + q)]);
+    const uint32_t q9 = (bits & kAbsMask) < kInfBits ? e4m3_q9(e4m3_round_up(bits, sh7)) : 0u;
+    sum += (uint64_t)q9 * q9;
+  }
+  // the 8 threads of a line are 8 consecutive lanes
+  sum += __shfl_xor(sum, 1, 64);
+  sum += __shfl_xor(sum, 2, 64);
+  sum += __shfl_xor(sum, 4, 64);
+  if (b == 0 && sum) atomicAdd((unsigned long long *)&norm[r], (unsigned long long)sum);
+}
+
+template <bool GROUPED, int SIDE>
+__global__ __launch_bounds__(256) void k_bound_norm(Problem P1, Group G) {
+  __shared__ double tile[kQL * kRowLd];
+  int64_t local;
+  const Problem &P = *locate<GROUPED>(P1, G, blockIdx.x, local);
+  const Operand &op = SIDE == 0 ? P.A : P.B;
+  const int64_t base = SIDE == 0 ? 0 : P.g.mp;
+  const Dims d = family_dims(SIDE == 0 ? kFamNormA : kFamNormB, P, 0);
+  const int64_t bx = local % d.x, by = local / d.x;
+  bound_norm_tile(op, bx * kQL, by * kQK, P.w.amax + base, P.w.E + base, P.w.flags + base,
+                  P.w.rfix + base, tile);
 }
 
 // Symmetric remainder of |x| < 2^29 modulo p, in [lo, hi] = [-floor(p/2),
@@ -348,6 +398,8 @@ hipError_t launch_quant_family(int fam, const Problem *P, const Group *G, hipStr
     case kFamLmaxB: OZ2_Q2(k_line_max, 1) break;
     case kFamBarA: OZ2_Q2(k_bound_operand, 0) break;
     case kFamBarB: OZ2_Q2(k_bound_operand, 1) break;
+    case kFamNormA: OZ2_Q2(k_bound_norm, 0) break;
+    case kFamNormB: OZ2_Q2(k_bound_norm, 1) break;
     case kFamResA: OZ2_Q2(k_residues, 0) break;
     case kFamResB: OZ2_Q2(k_residues, 1) break;
     default: return hipErrorInvalidValue;

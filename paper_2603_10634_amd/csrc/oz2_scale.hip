@@ -1,5 +1,9 @@
 // Scale exponents (Section III-E).
 //
+// Fast mode takes r_i from the Cauchy-Schwarz inequality instead: the squared
+// norm of row i of Abar, summed exactly by the quantization pass; every line
+// is then finalized from that exact value.  The accurate mode follows.
+//
 // For each row i of op(A) let r_i be the maximum over j of the bound product
 // (Abar Bbar)_ij, and likewise c_j for the columns of op(B).  The scale
 // exponent is e_i = max{e : 2^(2e+1) r_i <= P - 1}, giving log2 mu_i =
@@ -26,6 +30,7 @@
 // sum is at most 2^24.)
 #include <string.h>
 
+#include "oz2_device.h"
 #include "oz2_internal.h"
 
 namespace oz2 {
@@ -108,11 +113,8 @@ __device__ __forceinline__ void scale_fixup(const uint8_t *__restrict__ Abar,
         const uint64_t b8 = *(const uint64_t *)(other + h);
 #pragma unroll
         for (int z8 = 0; z8 < 8; ++z8) {
-          const uint32_t ca = (uint32_t)(a8 >> (8 * z8)) & 0x7Fu;
-          const uint32_t cb = (uint32_t)(b8 >> (8 * z8)) & 0x7Fu;
-          // 2^9 x value of a non-negative E4M3 code: m (subnormal) or (8 + m) 2^(e - 1)
-          const uint32_t qa = (ca >> 3) ? (8u + (ca & 7u)) << ((ca >> 3) - 1) : (ca & 7u);
-          const uint32_t qb = (cb >> 3) ? (8u + (cb & 7u)) << ((cb >> 3) - 1) : (cb & 7u);
+          const uint32_t qa = e4m3_q9((uint32_t)(a8 >> (8 * z8)) & 0x7Fu);
+          const uint32_t qb = e4m3_q9((uint32_t)(b8 >> (8 * z8)) & 0x7Fu);
           sum += (uint64_t)qa * qb;
         }
       }

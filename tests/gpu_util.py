@@ -62,10 +62,11 @@ class Run:
 
 
 def run(opA, opB, N, transA="N", transB="N", alpha=1.0, beta=0.0, Cin=None,
-        pad=(0, 0, 0), keep_ws=False, stream=None):
+        pad=(0, 0, 0), keep_ws=False, stream=None, mode="accurate"):
     """Column-major ozaki2_dgemm on op(A) (m x k) and op(B) (k x n) given as
-    numpy arrays; leading-dimension padding is filled with NaN (A, B) or 7.0
-    (C) so reads or writes outside the views show."""
+    numpy arrays, in the given scaling mode; leading-dimension padding is
+    filled with NaN (A, B) or 7.0 (C) so reads or writes outside the views
+    show."""
     m, k = opA.shape
     n = opB.shape[1]
     Ab, lda = to_colmajor(opA, transA, ld=(max(1, m) if transA in "Nn" else max(1, k)) + pad[0])
@@ -83,24 +84,30 @@ def run(opA, opB, N, transA="N", transB="N", alpha=1.0, beta=0.0, Cin=None,
     oz.ozaki2_set_workspace(base, wbytes)
     s = stream if stream is not None else torch.cuda.current_stream(dev)
     oz.ozaki2_set_stream(s)
+    assert oz.ozaki2_set_mode(mode) == 0
     try:
         st = oz.ozaki2_dgemm(transA, transB, m, n, k, alpha, tA, lda, tB, ldb, beta, tC, ldc, N)
         torch.cuda.synchronize(dev)
     finally:
         oz.ozaki2_set_workspace(None, 0)
+        oz.ozaki2_set_mode("accurate")
     off = pads = None
     wsh = None
     if keep_ws:
+        # keep_ws == "lines": only the per-line vectors, which precede Abar
         off, pads = oz.ozaki2_workspace_layout(m, n, k, N)
         shift = base - ws.data_ptr()
-        wsh = ws[shift:shift + wbytes].cpu().numpy()
+        upto = off[3] if keep_ws == "lines" else wbytes
+        wsh = ws[shift:shift + upto].cpu().numpy()
     return Run(st, tC.cpu().numpy(), ldc, m, n, wsh, off, pads)
 
 
-def check_stages(r: Run, opA, opB, N, st=None):
-    """Every stored intermediate equals the oracle's, bit for bit."""
+def check_stages(r: Run, opA, opB, N, st=None, mode="accurate"):
+    """Every stored intermediate equals the oracle's, bit for bit.  Fast mode
+    stores no bound operands; there every line is flagged as finalized from
+    its exact bound and no line is queued for a fix-up."""
     if st is None:
-        _, st = ref.emulate(opA, opB, N, keep_stages=True)
+        _, st = ref.emulate(opA, opB, N, keep_stages=True, mode=mode)
     m, k = opA.shape
     n = opB.shape[1]
     EA, EB = r.lines(1)
@@ -109,12 +116,17 @@ def check_stages(r: Run, opA, opB, N, st=None):
     assert np.array_equal(eA, st["e"]) and np.array_equal(eB, st["f"]), "scale exponents"
     sA, sB = r.lines(0)
     assert np.array_equal(sA, st["sA"]) and np.array_equal(sB, st["sB"]), "shifts"
-    Ab = r.bar("A")
-    Bb = r.bar("B")
-    assert np.array_equal(Ab[:m, :k], ref.e4m3_encode_exact(st["Abar"])), "Abar"
-    assert np.array_equal(Bb[:n, :k], ref.e4m3_encode_exact(st["Bbar"].T)), "Bbar"
-    assert not Ab[m:].any() and not Ab[:, k:].any(), "Abar padding"
-    assert not Bb[n:].any() and not Bb[:, k:].any(), "Bbar padding"
+    if mode == "fast":
+        fA, fB = r.lines(9, np.uint32)
+        assert np.all(fA & 4) and np.all(fB & 4), "fast mode: every line from its norm"
+        assert r.fixups() == 0, "fast mode queues no fix-ups"
+    else:
+        Ab = r.bar("A")
+        Bb = r.bar("B")
+        assert np.array_equal(Ab[:m, :k], ref.e4m3_encode_exact(st["Abar"])), "Abar"
+        assert np.array_equal(Bb[:n, :k], ref.e4m3_encode_exact(st["Bbar"].T)), "Bbar"
+        assert not Ab[m:].any() and not Ab[:, k:].any(), "Abar padding"
+        assert not Bb[n:].any() and not Bb[:, k:].any(), "Bbar padding"
     SA = r.slices("A")
     SB = r.slices("B")
     sl = 0

@@ -152,3 +152,19 @@ def test_batched_no_device_on_cpu():
     assert oz.ozaki2_set_graph(True) == 0 and oz.ozaki2_set_graph(False) == 0
     assert oz.ozaki2_set_autotune(True) == 0 and oz.ozaki2_set_autotune(False) == 0
     assert oz.ozaki2_get_schedule() == -1
+
+
+def test_mode_setting_host_only():
+    # the scaling mode is a per-thread host setting (no device needed)
+    assert oz.ozaki2_get_mode() == oz.MODE_ACCURATE
+    assert oz.ozaki2_set_mode("fast") == 0 and oz.ozaki2_get_mode() == oz.MODE_FAST
+    assert oz.ozaki2_set_mode(2) == -1 and oz.ozaki2_set_mode(-1) == -1
+    assert oz.ozaki2_get_mode() == oz.MODE_FAST
+    with pytest.raises(ValueError):
+        oz.ozaki2_set_mode("fastest")
+    assert oz.ozaki2_set_mode(oz.MODE_ACCURATE) == 0 and oz.ozaki2_get_mode() == 0
+    # the workspace does not depend on the mode
+    oz.ozaki2_set_mode("fast")
+    w_fast = oz.ozaki2_workspace_bytes(300, 200, 700, 13)
+    oz.ozaki2_set_mode("accurate")
+    assert w_fast == oz.ozaki2_workspace_bytes(300, 200, 700, 13)

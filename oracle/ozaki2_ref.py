@@ -49,6 +49,10 @@ R13 fast mode (Section III-E names it and says only that it bounds the sum of
                            <= 2^(e_i + f_j + 1) sqrt(r_i c_j) <= P - 1,
     which is condition (3).  Squares of Abar are multiples of 2^-18, so r_i is
     an exact integer multiple of 2^-18 (below 2^34 for k <= 2^18).
+R14 Karatsuba-only moduli (the list of Section III-B, used as an ablation of
+    the hybrid list): p_l from the greedy scan down from 513, every one with
+    the Karatsuba split s = 16; residues follow R7, so p = 513 gives digits
+    in [-16, 16] like the hybrid list's largest moduli.
 """
 from __future__ import annotations
 
@@ -149,6 +153,19 @@ def hybrid_moduli(N: int) -> list[tuple[int, str, int]]:
     if len(out) < N:
         raise ValueError("not enough moduli")
     return out
+
+
+def moduli_table(N: int, moduli_set: str = "hybrid") -> list[tuple[int, str, int]]:
+    """The N moduli as (p, kind, s): the hybrid list of Section III-D, or the
+    Karatsuba-only list of Section III-B (every modulus with s = 16, R14)."""
+    if moduli_set == "hybrid":
+        return hybrid_moduli(N)
+    if moduli_set == "karatsuba":
+        out = [(p, "karatsuba", 16) for p in karatsuba_moduli(N)]
+        if len(out) < N:
+            raise ValueError("not enough moduli")
+        return out
+    raise ValueError("moduli_set must be 'hybrid' or 'karatsuba'")
 
 
 def crt_weights(moduli: list[int]) -> tuple[int, list[int]]:
@@ -359,7 +376,8 @@ def inverse_scale(Cp: np.ndarray, sA: np.ndarray, sB: np.ndarray) -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 
-def scaling(opA: np.ndarray, opB: np.ndarray, num_moduli: int, mode: str = "accurate") -> dict:
+def scaling(opA: np.ndarray, opB: np.ndarray, num_moduli: int, mode: str = "accurate",
+            moduli_set: str = "hybrid") -> dict:
     """Workflow steps 1-3 of Section IV-B: mu', nu', the round-up FP8 bound
     operands, the bound product's line maxima (accurate mode) or the bound
     operands' line norms (fast mode, R13) and the scale exponents.
@@ -371,7 +389,7 @@ def scaling(opA: np.ndarray, opB: np.ndarray, num_moduli: int, mode: str = "accu
     opB = np.asarray(opB, dtype=np.float64)
     m, k = opA.shape
     n = opB.shape[1]
-    mods = hybrid_moduli(num_moduli)
+    mods = moduli_table(num_moduli, moduli_set)
     P = math.prod(p for p, _, _ in mods)
 
     # R9: non-finite rows / columns are flagged and quantized as zeros
@@ -430,13 +448,13 @@ def products(sc: dict, rows, cols, keep_stages: bool = False):
 
 
 def emulate(opA: np.ndarray, opB: np.ndarray, num_moduli: int,
-            keep_stages: bool = False, mode: str = "accurate"):
+            keep_stages: bool = False, mode: str = "accurate", moduli_set: str = "hybrid"):
     """Chat ~ op(A) op(B) by the FP8 Ozaki-II scheme, accurate or fast mode.
 
     Returns Chat (m x n float64) and, with keep_stages, a dict of every
     intermediate quantity.  Implements Sections II and III-B..III-E in the
     order of the workflow of Section IV-B."""
-    sc = scaling(opA, opB, num_moduli, mode)
+    sc = scaling(opA, opB, num_moduli, mode, moduli_set)
     m, n = sc["A"].shape[0], sc["B"].shape[1]
     Chat, st = products(sc, slice(0, m), slice(0, n), keep_stages)
     if not keep_stages:
@@ -447,12 +465,12 @@ def emulate(opA: np.ndarray, opB: np.ndarray, num_moduli: int,
 
 
 def emulate_sampled(opA: np.ndarray, opB: np.ndarray, num_moduli: int, rows, cols,
-                    mode: str = "accurate"):
+                    mode: str = "accurate", moduli_set: str = "hybrid"):
     """The entries Chat[rows][:, cols] of emulate(opA, opB, num_moduli), with
     the scale exponents of every line (they depend on the whole product) but
     the residue products, CRT and inverse scaling only for the sample.
     Returns (Chat_sample, scaling dict)."""
-    sc = scaling(opA, opB, num_moduli, mode)
+    sc = scaling(opA, opB, num_moduli, mode, moduli_set)
     Chat, _ = products(sc, np.asarray(rows), np.asarray(cols), False)
     return Chat, sc
 
@@ -484,7 +502,8 @@ def _op_view(buf, trans, rows, cols, ld):
 
 def dgemm(transA: str, transB: str, m: int, n: int, k: int, alpha: float,
           A: np.ndarray, lda: int, B: np.ndarray, ldb: int, beta: float,
-          C: np.ndarray, ldc: int, num_moduli: int, mode: str = "accurate") -> np.ndarray:
+          C: np.ndarray, ldc: int, num_moduli: int, mode: str = "accurate",
+          moduli_set: str = "hybrid") -> np.ndarray:
     """Column-major C <- alpha op(A) op(B) + beta C, emulated; returns a new
     flat C buffer (entries outside the m x n view are copied unchanged)."""
     Cout = np.array(C, dtype=np.float64, copy=True)
@@ -497,6 +516,6 @@ def dgemm(transA: str, transB: str, m: int, n: int, k: int, alpha: float,
         return Cout
     opA = _op_view(A, transA, m, k, lda)
     opB = _op_view(B, transB, k, n, ldb)
-    Chat = emulate(opA, opB, num_moduli, mode=mode)
+    Chat = emulate(opA, opB, num_moduli, mode=mode, moduli_set=moduli_set)
     view[...] = combine_alpha_beta(Chat, alpha, beta, Cin)
     return Cout

@@ -36,9 +36,9 @@ def check_scale_exponent_brute(P, r18_values):
         assert r * Fraction(2) ** (2 * e + 3) > P - 1
 
 
-def check_condition3(A, B, N, mode="accurate"):
+def check_condition3(A, B, N, mode="accurate", moduli_set="hybrid"):
     """2 sum_h |a'_ih||b'_hj| < P for all i, j, in exact integers (eq. condition)."""
-    _, st = ref.emulate(A, B, N, keep_stages=True, mode=mode)
+    _, st = ref.emulate(A, B, N, keep_stages=True, mode=mode, moduli_set=moduli_set)
     Ai = [[int(x) for x in row] for row in st["Aint"]]
     Bi = [[int(x) for x in row] for row in st["Bint"]]
     m, k = len(Ai), len(Bi)
@@ -65,11 +65,11 @@ def check_bound_dominates(A, B, N):
             assert bound * 2 ** 18 <= st["r18"][i] and bound * 2 ** 18 <= st["c18"][j]
 
 
-def check_residue_products(A, B, N):
+def check_residue_products(A, B, N, moduli_set="hybrid"):
     """Per modulus: the direct product and the three-digit-product route both
     equal (A'B' mod p) computed with Python integers (eqs. CRTmatmul,
     Karatsuba, 3matmult-notKaratsuba)."""
-    _, st = ref.emulate(A, B, N, keep_stages=True)
+    _, st = ref.emulate(A, B, N, keep_stages=True, moduli_set=moduli_set)
     Ai = [[int(x) for x in row] for row in st["Aint"]]
     Bi = [[int(x) for x in row] for row in st["Bint"]]
     m, k = len(Ai), len(Bi)
@@ -85,9 +85,9 @@ def check_residue_products(A, B, N):
         assert all(pm["uA"][i][h] == ref.smod(Ai[i][h], p) for i in range(m) for h in range(k))
 
 
-def check_crt_is_exact_product(A, B, N):
+def check_crt_is_exact_product(A, B, N, moduli_set="hybrid"):
     """C' equals the exact integer product A'B' (Section II: exact products)."""
-    _, st = ref.emulate(A, B, N, keep_stages=True)
+    _, st = ref.emulate(A, B, N, keep_stages=True, moduli_set=moduli_set)
     Ai = [[int(x) for x in row] for row in st["Aint"]]
     Bi = [[int(x) for x in row] for row in st["Bint"]]
     m, k, n = len(Ai), len(Bi), len(Bi[0])
@@ -96,21 +96,21 @@ def check_crt_is_exact_product(A, B, N):
             assert int(st["Cp"][i, j]) == sum(Ai[i][h] * Bi[h][j] for h in range(k))
 
 
-def check_integer_inputs_exact(N=12, mode="accurate"):
+def check_integer_inputs_exact(N=12, mode="accurate", moduli_set="hybrid"):
     """Integer inputs with small products: truncation is exact and C equals the
     exact product (a closed-form special case)."""
     A = integer_matrix(9, 33, 1000, 11)
     B = integer_matrix(33, 7, 1000, 12)
-    C = ref.emulate(A, B, N, mode=mode)
+    C = ref.emulate(A, B, N, mode=mode, moduli_set=moduli_set)
     exact = np.array([[sum(int(A[i, h]) * int(B[h, j]) for h in range(33))
                        for j in range(7)] for i in range(9)], dtype=np.float64)
     assert np.array_equal(C, exact)
 
 
-def check_error_bound(A, B, N, mode="accurate"):
+def check_error_bound(A, B, N, mode="accurate", moduli_set="hybrid"):
     """|C - AB| <= sum_h(|da||b| + |a||db| + |da||db|) + half an ulp of C, with
     |da_ih| < 2^-log2(mu_i) from truncation (exact rationals)."""
-    C, st = ref.emulate(A, B, N, keep_stages=True, mode=mode)
+    C, st = ref.emulate(A, B, N, keep_stages=True, mode=mode, moduli_set=moduli_set)
     m, k = A.shape
     n = B.shape[1]
     for i in range(m):
@@ -267,6 +267,36 @@ def test_fast_norms(N, phi):
 @pytest.mark.parametrize("N", [1, 7, 12, 13])
 def test_fast_matches_accurate_when_tight(N):
     check_fast_matches_accurate_when_tight(N)
+
+
+# Karatsuba-only moduli (Section III-B list, R14): 513 = 3^3 19, 512 = 2^9 and
+# 505 = 5 101 are among the first five, so N = 5 covers the moduli whose
+# digits reach 16 and the ones sharing factors with 15 and 16
+@pytest.mark.parametrize("N", [1, 2, 5, 12, 13])
+def test_karatsuba_only_pins(N):
+    A, B = _small_problem(5, 6, 19, 1.5, 170 + N)
+    check_condition3(A, B, N, moduli_set="karatsuba")
+    check_residue_products(A, B, N, moduli_set="karatsuba")
+    check_crt_is_exact_product(A, B, N, moduli_set="karatsuba")
+    check_error_bound(A[:3, :], B[:, :3], N, moduli_set="karatsuba")
+    check_condition3(A, B, N, mode="fast", moduli_set="karatsuba")
+
+
+def test_karatsuba_only_integer_inputs_and_accuracy():
+    # P/2 > 2^115 from N = 13 on (Section III-B), so 13 Karatsuba-only moduli
+    # reach the accuracy that 12 hybrid moduli reach (P/2 > 2^110)
+    check_integer_inputs_exact(13, moduli_set="karatsuba")
+    A, B = _small_problem(24, 20, 1500, 0.5, 510)
+    hi, lo = dd_dot_rows(A, B)
+    err13 = normalised_error(ref.emulate(A, B, 13, moduli_set="karatsuba"), hi, lo,
+                             np.abs(A), np.abs(B))
+    err_h12 = normalised_error(ref.emulate(A, B, 12), hi, lo, np.abs(A), np.abs(B))
+    assert err13 <= 1e-15 and err_h12 <= 1e-15, (err13, err_h12)
+    for moduli_set in ("hybrid", "karatsuba"):
+        with pytest.raises(ValueError):
+            ref.moduli_table(10 ** 4, moduli_set)
+    with pytest.raises(ValueError):
+        ref.moduli_table(3, "int8")
 
 
 def test_bound_dominates():

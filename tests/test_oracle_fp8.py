@@ -81,7 +81,7 @@ def test_bound_operand_dominates_and_fits():
             assert EA[i] == 0
 
 
-@pytest.mark.parametrize("p,kind,s", ref.hybrid_moduli(34))
+@pytest.mark.parametrize("p,kind,s", ref.hybrid_moduli(34) + ref.moduli_table(33, "karatsuba"))
 def test_digits_exhaustive(p, kind, s):
     u = np.arange(-(p // 2), (p + 1) // 2, dtype=np.int64)
     d = ref.digit_slices(u, kind, s)

@@ -55,6 +55,18 @@ def test_hybrid_kinds_and_radix():
     assert mods[33] == (361, "square", 19)
 
 
+def test_karatsuba_only_table():
+    # Section III-B: every modulus of the Karatsuba-only list uses s = 16, and
+    # P/2 exceeds 2^115 = 2^(53+53+9) from N = 13 on (not at N = 12)
+    g = _golden_lists()
+    tab = ref.moduli_table(29, "karatsuba")
+    assert [p for p, _, _ in tab] == g["karatsuba"]
+    assert all(k == "karatsuba" and s == 16 for _, k, s in tab)
+    half12 = math.prod(p for p, _, _ in ref.moduli_table(12, "karatsuba")) / 2
+    half13 = math.prod(p for p, _, _ in ref.moduli_table(13, "karatsuba")) / 2
+    assert half12 < 2.0 ** 115 < half13
+
+
 def test_pairwise_coprime():
     for lst in (ref.int8_moduli(60), ref.karatsuba_moduli(60),
                 [p for p, _, _ in ref.hybrid_moduli(60)]):

@@ -42,6 +42,8 @@ def _parse():
     ap.add_argument("--phi", type=float, default=0.5)
     ap.add_argument("--mode", choices=["accurate", "fast"], default="accurate",
                     help="scaling mode (fast: Cauchy-Schwarz bound, no bound product)")
+    ap.add_argument("--moduli-list", choices=["hybrid", "karatsuba"], default="hybrid",
+                    help="modulus list (karatsuba: the Karatsuba-only ablation, N = 13)")
     ap.add_argument("--cpu-rows", type=int, default=48,
                     help="rows of op(A) in the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -58,7 +60,7 @@ def _parse():
     return ap.parse_args()
 
 
-def _cpu_baseline(A, B, N, rows, mode):
+def _cpu_baseline(A, B, N, rows, mode, moduli_list):
     """The oracle, as it stands, on op(A)[:rows] x op(B): a bounded slab of the
     same workload (its own emulated GEMM of shape rows x n x k)."""
     import numpy as np
@@ -70,14 +72,14 @@ def _cpu_baseline(A, B, N, rows, mode):
         threads = os.cpu_count() or 1
     Asub = np.ascontiguousarray(A[:rows])
     t0 = time.perf_counter()
-    ref.emulate(Asub, B, N, mode=mode)
+    ref.emulate(Asub, B, N, mode=mode, moduli_set=moduli_list)
     dt = time.perf_counter() - t0
     m, k = Asub.shape
     n = B.shape[1]
     return {"value": 2.0 * m * n * k / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads),
             "kind": "oracle",
             "sample": f"oracle emulate() on op(A)[:{rows}] x op(B) ({m}x{n}x{k}, "
-                      f"N={N}, {mode} mode), {dt:.1f} s wall"}
+                      f"N={N}, {mode} mode, {moduli_list} moduli), {dt:.1f} s wall"}
 
 
 def main():
@@ -112,6 +114,8 @@ def main():
     oz.ozaki2_set_stream(stream)
     if oz.ozaki2_set_mode(args.mode) != 0:
         raise RuntimeError("ozaki2_set_mode failed")
+    if oz.ozaki2_set_moduli_list(args.moduli_list) != 0:
+        raise RuntimeError("ozaki2_set_moduli_list failed")
     # caller-owned workspace (so the fix-up count can be read back afterwards)
     wbytes = oz.ozaki2_workspace_bytes(m, n, k, N)
     ws = torch.empty(wbytes + 256, dtype=torch.uint8, device=dev)
@@ -162,7 +166,8 @@ def main():
     res_flops = 3 * N * flops
     achieved = res_flops / (gemm_ms * 1e-3) / 1e12
     traffic = None
-    if args.traffic and os.path.exists(args.traffic) and (m, n, k, N) == (8192, 8192, 8192, 12):
+    if (args.traffic and os.path.exists(args.traffic) and (m, n, k, N) == (8192, 8192, 8192, 12)
+            and args.moduli_list == "hybrid"):
         from paper_2603_10634_amd.profile_summary import gemm_source_sha
         with open(args.traffic) as f:
             rec = json.load(f)
@@ -203,7 +208,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = _cpu_baseline(A, B, N, min(args.cpu_rows, m), args.mode)
+        cpu = _cpu_baseline(A, B, N, min(args.cpu_rows, m), args.mode, args.moduli_list)
 
     stage = dict(zip(["quant", "gemms", "requant", "dequant", "others"],
                      [float(k_med[0] + k_med[3]), float(k_med[1] + k_med[4]), 0.0,
@@ -222,9 +227,9 @@ def main():
         "dtype": "fp8e4m3-mfma->f64",
         "data": "synthetic",
         "config": {"workload": f"emulated dgemm {m}x{n}x{k} col-major NN, phi={args.phi}, "
-                               f"{N} moduli, {args.mode} mode",
+                               f"{N} {args.moduli_list} moduli, {args.mode} mode",
                    "m": m, "n": n, "k": k, "num_moduli": N, "phi": args.phi,
-                   "mode": args.mode,
+                   "mode": args.mode, "moduli_list": args.moduli_list,
                    "alpha": 1.0, "beta": 0.0},
         "error_normalised": err_emu,
         "native_fp64": native,

@@ -26,8 +26,8 @@
  *   - Work is enqueued on the stream set by ozaki2_set_stream (default: the
  *     null stream) and runs asynchronously; inputs must stay valid and
  *     unmodified until the stream reaches the end of the call.
- *   - Stream, workspace, timing, graph, autotune and mode settings are per
- *     host thread.
+ *   - Stream, workspace, timing, graph, autotune, mode and modulus-list
+ *     settings are per host thread.
  *   - Results are deterministic: the same inputs give bit-identical C on every
  *     call and for all four transA/transB storage combinations.
  *
@@ -61,6 +61,10 @@ extern "C" {
 #define OZ2_MODE_ACCURATE 0
 #define OZ2_MODE_FAST     1
 
+/* Modulus lists (ozaki2_set_moduli_list). */
+#define OZ2_MODULI_HYBRID    0
+#define OZ2_MODULI_KARATSUBA 1
+
 /*
  * ozaki2_dgemm - emulated DGEMM in the calling thread's mode (ozaki2_set_mode,
  * accurate by default).
@@ -74,7 +78,8 @@ extern "C" {
  *  B, ldb          device pointer; ldb >= max(1, k) for 'N', >= max(1, n) else.
  *  C, ldc          device pointer; ldc >= max(1, m).
  *  num_moduli      N in [1, OZ2_MAX_MODULI]; 12 is the full-accuracy count of
- *                  the paper (P/2 > 2^110, about 55 effective bits).
+ *                  the paper (P/2 > 2^110, about 55 effective bits) for the
+ *                  default hybrid list (13 for the Karatsuba-only list).
  *
  * Quick returns: m == 0 or n == 0 does nothing; k == 0 or alpha == 0 sets
  * C <- beta*C (C <- 0, unread, when beta == 0).  A row of op(A) or column of
@@ -92,8 +97,9 @@ int ozaki2_dgemm(char transA, char transB, int64_t m, int64_t n, int64_t k,
  * ozaki2_workspace_bytes - device workspace one ozaki2_dgemm call of this
  * shape needs (every dimension padded to a multiple of 256, as in the paper's
  * Section IV-C): the FP8 bound operands, the FP8 digit slices of both
- * operands, one int16 residue plane per modulus and per-line vectors.
- * Returns 0 for invalid sizes.
+ * operands, one int16 residue plane per modulus and per-line vectors, for
+ * the calling thread's modulus list (ozaki2_set_moduli_list).  Returns 0 for
+ * invalid sizes.
  */
 size_t ozaki2_workspace_bytes(int64_t m, int64_t n, int64_t k, int num_moduli);
 
@@ -143,7 +149,8 @@ int ozaki2_get_stage_times(float ms[5]);
 int ozaki2_get_kernel_times(float *ms, int count);
 
 /*
- * ozaki2_moduli - the moduli the library uses for N = num_moduli, written to
+ * ozaki2_moduli - the moduli the library uses for N = num_moduli under the
+ * calling thread's modulus list (ozaki2_set_moduli_list), written to
  * p[0..N-1], with kinds[l] = 0 for a square modulus (modular reduction split,
  * Section III-C) and 1 for a Karatsuba modulus (Section III-B).  Either output
  * may be NULL.  Returns 0 or -1 for an invalid N.
@@ -272,6 +279,25 @@ int ozaki2_set_mode(int mode);
 
 /* ozaki2_get_mode - the calling thread's scaling mode. */
 int ozaki2_get_mode(void);
+
+/*
+ * ozaki2_set_moduli_list - modulus list of the calling thread's subsequent
+ * calls (and of the workspace, layout and moduli queries):
+ *   OZ2_MODULI_HYBRID (default)  Section III-D: the squares 1089, 1024, 961,
+ *        841, 625, 529 first (modular-reduction split, Section III-C), then
+ *        511, 509, 503, ... (Karatsuba split, s = 16).
+ *   OZ2_MODULI_KARATSUBA  Section III-B: 513, 512, 511, 509, 505, ...
+ *        (greedy pairwise coprime from 513), all with the Karatsuba split.
+ *        Three FP8 products per modulus like the hybrid list, but a smaller
+ *        P for the same N (P/2 > 2^115 needs N = 13 instead of 12), so about
+ *        one more modulus for the same accuracy: an ablation of the hybrid
+ *        list's saving.
+ * Returns 0, or -1 for an unknown list (the setting is then unchanged).
+ */
+int ozaki2_set_moduli_list(int list);
+
+/* ozaki2_get_moduli_list - the calling thread's modulus list. */
+int ozaki2_get_moduli_list(void);
 
 /* ozaki2_release - free the calling thread's library-owned workspace, timing
  * events, cached batch plans and graphs. */

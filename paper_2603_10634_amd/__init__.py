@@ -18,7 +18,8 @@ __all__ = [
     "ozaki2_get_kernel_times", "ozaki2_moduli", "ozaki2_workspace_layout", "ozaki2_release",
     "ozaki2_status_string", "ozaki2_dgemm_batched", "ozaki2_workspace_bytes_batched",
     "ozaki2_set_graph", "ozaki2_set_autotune", "ozaki2_get_schedule", "ozaki2_set_mode",
-    "ozaki2_get_mode", "MODE_ACCURATE", "MODE_FAST", "dgemm", "dgemm_batched",
+    "ozaki2_get_mode", "MODE_ACCURATE", "MODE_FAST", "ozaki2_set_moduli_list",
+    "ozaki2_get_moduli_list", "MODULI_HYBRID", "MODULI_KARATSUBA", "dgemm", "dgemm_batched",
     "LIB_PATH", "HEADER_PATH", "header_functions",
 ]
 
@@ -28,6 +29,8 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "ozaki2.h")
 
 MODE_ACCURATE = 0   # OZ2_MODE_ACCURATE
 MODE_FAST = 1       # OZ2_MODE_FAST
+MODULI_HYBRID = 0     # OZ2_MODULI_HYBRID
+MODULI_KARATSUBA = 1  # OZ2_MODULI_KARATSUBA
 
 _i64 = ctypes.c_int64
 _vp = ctypes.c_void_p
@@ -82,6 +85,8 @@ def lib() -> ctypes.CDLL:
         "ozaki2_get_schedule": (ctypes.c_int, []),
         "ozaki2_set_mode": (ctypes.c_int, [ctypes.c_int]),
         "ozaki2_get_mode": (ctypes.c_int, []),
+        "ozaki2_set_moduli_list": (ctypes.c_int, [ctypes.c_int]),
+        "ozaki2_get_moduli_list": (ctypes.c_int, []),
         "ozaki2_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     }
     for name, (res, args) in sig.items():
@@ -240,6 +245,24 @@ def ozaki2_set_mode(mode) -> int:
 
 def ozaki2_get_mode() -> int:
     return lib().ozaki2_get_mode()
+
+
+def _list_code(moduli) -> int:
+    if isinstance(moduli, str):
+        codes = {"hybrid": MODULI_HYBRID, "karatsuba": MODULI_KARATSUBA}
+        if moduli not in codes:
+            raise ValueError("moduli list must be 'hybrid' or 'karatsuba'")
+        return codes[moduli]
+    return int(moduli)
+
+
+def ozaki2_set_moduli_list(moduli) -> int:
+    """moduli: MODULI_HYBRID / MODULI_KARATSUBA, or 'hybrid' / 'karatsuba'."""
+    return lib().ozaki2_set_moduli_list(_list_code(moduli))
+
+
+def ozaki2_get_moduli_list() -> int:
+    return lib().ozaki2_get_moduli_list()
 
 
 class _ModeScope:

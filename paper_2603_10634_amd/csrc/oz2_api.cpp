@@ -10,6 +10,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -39,6 +40,7 @@ struct ThreadState {
   bool autotune = false;                   // tune the grouped residue-product schedule
   int last_schedule = -1;                  // schedule of the last batched call
   int mode = OZ2_MODE_ACCURATE;            // scaling mode (Section III-E)
+  int list = OZ2_MODULI_HYBRID;            // modulus list (Sections III-B, III-D)
   hipStream_t cap_stream = nullptr;        // private stream used only for capture
   int cap_dev = -1;
   std::list<std::unique_ptr<Plan>> plans;  // cached plans, most recent first
@@ -47,9 +49,9 @@ struct ThreadState {
 thread_local ThreadState g_ts;
 
 std::mutex g_mu;
-std::map<std::pair<int, int>, Tables *> g_tables;  // (device, N) -> device copy
+std::map<std::tuple<int, int, int>, Tables *> g_tables;  // (device, N, list) -> device copy
 std::map<int, bool> g_is_gfx950;
-std::map<int, Tables> g_host_tables;                // N -> host copy
+std::map<std::pair<int, int>, Tables> g_host_tables;     // (N, list) -> host copy
 
 // Schedules of the grouped residue products chosen by the autotuner, keyed
 // by the shapes of a batch (not its pointers).
@@ -64,11 +66,23 @@ struct Layout {
   size_t total;
 };
 
-// Offsets of every workspace buffer (256-byte aligned).  The zero-initialised
-// per-line vectors come first and contiguously so one fill clears them.
-bool make_layout(int64_t m, int64_t n, int64_t k, int N, Layout *L) {
+const Tables *host_tables(int N, int list) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto key = std::make_pair(N, list);
+  auto it = g_host_tables.find(key);
+  if (it != g_host_tables.end()) return &it->second;
   Tables t;
-  if (!build_tables(N, &t)) return false;
+  if (!build_tables(N, list, &t)) return nullptr;
+  return &(g_host_tables[key] = t);
+}
+
+// Offsets of every workspace buffer (256-byte aligned) for N moduli of the
+// calling thread's list.  The zero-initialised per-line vectors come first
+// and contiguously so one fill clears them.
+bool make_layout(int64_t m, int64_t n, int64_t k, int N, Layout *L) {
+  const Tables *ht = host_tables(N, g_ts.list);
+  if (!ht) return false;
+  const Tables &t = *ht;
   L->mp = round_up(m > 0 ? m : 1, kPad);
   L->np = round_up(n > 0 ? n : 1, kPad);
   L->kp = round_up(k > 0 ? k : 1, kPad);
@@ -112,21 +126,16 @@ bool device_ok(int dev) {
   return ok;
 }
 
-const Tables *host_tables(int N) {
+// Device copy of the tables, created once per (device, N, list) and kept for
+// the life of the process.
+const Tables *device_tables(int dev, int N, int list, hipError_t *err) {
+  const Tables *h = host_tables(N, list);
+  if (!h) {
+    *err = hipErrorInvalidValue;
+    return nullptr;
+  }
   std::lock_guard<std::mutex> lk(g_mu);
-  auto it = g_host_tables.find(N);
-  if (it != g_host_tables.end()) return &it->second;
-  Tables t;
-  if (!build_tables(N, &t)) return nullptr;
-  return &(g_host_tables[N] = t);
-}
-
-// Device copy of the tables, created once per (device, N) and kept for the
-// life of the process.
-const Tables *device_tables(int dev, int N, hipError_t *err) {
-  const Tables *h = host_tables(N);
-  std::lock_guard<std::mutex> lk(g_mu);
-  auto key = std::make_pair(dev, N);
+  auto key = std::make_tuple(dev, N, list);
   auto it = g_tables.find(key);
   if (it != g_tables.end()) return it->second;
   Tables *d = nullptr;
@@ -165,7 +174,7 @@ bool is_trans(char c) { return !(c == 'N' || c == 'n'); }
 Problem make_problem(char transA, char transB, int64_t m, int64_t n, int64_t k, double alpha,
                      const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
                      double *C, int64_t ldc, int N, uint8_t *ws, const Layout &L,
-                     const Tables *dt, int limbs) {
+                     const Tables *dt, const Tables *ht) {
   Problem P;
   memset(&P, 0, sizeof(P));
   const bool tA = is_trans(transA), tB = is_trans(transB);
@@ -179,7 +188,7 @@ Problem make_problem(char transA, char transB, int64_t m, int64_t n, int64_t k, 
   P.B.k = k;
   P.B.sr = tB ? 1 : ldb;
   P.B.sh = tB ? ldb : 1;
-  P.g = Geometry{m, n, k, L.mp, L.np, L.kp, N, L.M};
+  P.g = Geometry{m, n, k, L.mp, L.np, L.kp, N, L.M, ht->nsq, g_ts.list};
   Work &w = P.w;
   w.amax = (uint64_t *)(ws + L.off[10]);
   w.flags = (uint32_t *)(ws + L.off[11]);
@@ -201,7 +210,7 @@ Problem make_problem(char transA, char transB, int64_t m, int64_t n, int64_t k, 
   P.beta = beta;
   P.C = C;
   P.ldc = ldc;
-  P.limbs = limbs;
+  P.limbs = ht->limbs;
   P.mode = g_ts.mode;
   return P;
 }
@@ -527,7 +536,7 @@ const char *ozaki2_status_string(int status) {
 }
 
 int ozaki2_moduli(int num_moduli, int32_t *p, int32_t *kinds) {
-  const Tables *t = host_tables(num_moduli);
+  const Tables *t = host_tables(num_moduli, g_ts.list);
   if (!t) return -1;
   for (int l = 0; l < num_moduli; ++l) {
     if (p) p[l] = t->p[l];
@@ -686,16 +695,16 @@ int ozaki2_dgemm(char transA, char transB, int64_t m, int64_t n, int64_t k, doub
   Layout L;
   if (!make_layout(m, n, k, num_moduli, &L)) return OZ2_ERR_UNSUPPORTED;
   hipError_t herr = hipSuccess;
-  const Tables *dt = device_tables(dev, num_moduli, &herr);
+  const Tables *dt = device_tables(dev, num_moduli, ts.list, &herr);
   if (!dt) return OZ2_ERR_HIP;
-  const Tables *ht = host_tables(num_moduli);
+  const Tables *ht = host_tables(num_moduli, ts.list);
 
   uint8_t *ws = nullptr;
   size_t have = 0;
   int r = get_workspace(dev, L.total, &ws, &have);
   if (r != OZ2_SUCCESS) return r;
   const Problem P = make_problem(transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
-                                 num_moduli, ws, L, dt, ht->limbs);
+                                 num_moduli, ws, L, dt, ht);
 
   if (ts.graph) {
     KeyBuilder kb;
@@ -804,9 +813,9 @@ int ozaki2_dgemm_batched(int count, const char *transA, const char *transB, cons
   if (!device_ok(dev)) return OZ2_ERR_NO_DEVICE;
   hipStream_t st = ts.stream;
   hipError_t herr = hipSuccess;
-  const Tables *dt = device_tables(dev, num_moduli, &herr);
+  const Tables *dt = device_tables(dev, num_moduli, ts.list, &herr);
   if (!dt) return OZ2_ERR_HIP;
-  const Tables *ht = host_tables(num_moduli);
+  const Tables *ht = host_tables(num_moduli, ts.list);
 
   // workspace: library-owned grows to the whole batch, capped at 16 GiB
   // (or the largest single problem); a caller's is used as given
@@ -830,6 +839,7 @@ int ozaki2_dgemm_batched(int count, const char *transA, const char *transB, cons
   KeyBuilder kb;
   kb.add(dev);
   kb.add(ts.mode);
+  kb.add(ts.list);
   kb.add(num_moduli);
   kb.add(count);
   kb.add(ws);
@@ -877,7 +887,7 @@ int ozaki2_dgemm_batched(int count, const char *transA, const char *transB, cons
       if (used + L.total > have) flush();
       cur.push_back(make_problem(transA[q], transB[q], m[q], n[q], k[q], alpha[q], A[q], lda[q],
                                  B[q], ldb[q], beta[q], C[q], ldc[q], num_moduli, ws + used, L,
-                                 dt, ht->limbs));
+                                 dt, ht));
       used += L.total;
       for (int64_t v : {m[q], n[q], k[q]}) p->shape_key.push_back(v);
     }
@@ -990,5 +1000,13 @@ int ozaki2_set_mode(int mode) {
 }
 
 int ozaki2_get_mode(void) { return g_ts.mode; }
+
+int ozaki2_set_moduli_list(int list) {
+  if (list != OZ2_MODULI_HYBRID && list != OZ2_MODULI_KARATSUBA) return -1;
+  g_ts.list = list;
+  return OZ2_SUCCESS;
+}
+
+int ozaki2_get_moduli_list(void) { return g_ts.list; }
 
 }  // extern "C"

@@ -560,12 +560,15 @@ __device__ __forceinline__ void fold_w(v16f (&acc)[4][4], int mul, int p, float 
 // One 256 x 256 tile (j0.., i0..) of Karatsuba modulus l (s = 16) over k in
 // [kbeg, kbeg + 64 nk), three single-product passes in one accumulator.
 // The digit products C1 = A1 B1, C2 = A2 B2, C3 = A3 B3 combine to
-// 240 C1 - 15 C2 + 16 C3 (eq. C'-Karatsuba) = 16 (C3 + 15 C1) - 15 C2:
-//   pass 1: acc = C1;        fold: acc = smod(15 smod(acc))
-//   pass 2: acc += C3;       fold: acc = smod(kinit smod(acc)),  kinit = -16/15 mod p
-//   pass 3: acc += C2;       result smod(-15 acc)
-// Every fold leaves |acc| < p/2 <= 256, so the FP32 accumulation of each pass
-// stays an exact integer below 2^24.
+// 240 C1 - 15 C2 + 16 C3 (eq. C'-Karatsuba) = c (b (a X + Y) + Z) (mod p),
+// with the passes (X, Y, Z) and multipliers from the tables:
+//   (C1, C3, C2), a = 15, b = -16/15, c = -15  (p coprime to 15), or
+//   (C1, C2, C3), a = -16, b = -15/16, c = 16  (other odd p):
+//   pass 1: acc = X;         fold: acc = smod(a smod(acc))
+//   pass 2: acc += Y;        fold: acc = smod(b smod(acc))
+//   pass 3: acc += Z;        result smod(c acc)
+// Every fold leaves |acc| <= p/2 <= 256, so the FP32 accumulation of each
+// pass stays an exact integer below 2^24.
 __device__ __forceinline__ void karatsuba_tile_w(const uint8_t *Asl, const uint8_t *Bsl,
                                                  int16_t *__restrict__ planes,
                                                  const Tables *__restrict__ tab, int64_t mp,
@@ -575,8 +578,12 @@ __device__ __forceinline__ void karatsuba_tile_w(const uint8_t *Asl, const uint8
   const int sl0 = (int)uni(tab->slice0[l]);
   const int p = (int)uni(tab->p[l]);
   const float inv = __int_as_float((int)uni(__float_as_int(tab->inv_p[l])));
-  const int kinit = (int)uni(tab->kinit[l]);
-  resident(sl0, p, __float_as_int(inv), kinit);
+  const int mul_a = (int)uni(tab->kfold[l][0]);
+  const int mul_b = (int)uni(tab->kfold[l][1]);
+  const int mul_c = (int)uni(tab->kfold[l][2]);
+  const int second = (int)uni(tab->kfold[l][3]);  // slice of pass 2 (pass 3: 3 - second)
+  resident(sl0, p, __float_as_int(inv), mul_a);
+  resident(mul_b, mul_c, second, second);
   resident_ptr(planes, planes);
   resident(accumulate, accumulate, accumulate, accumulate);
   const int64_t sA = mp * kp, sB = np * kp;
@@ -592,11 +599,12 @@ __device__ __forceinline__ void karatsuba_tile_w(const uint8_t *Asl, const uint8
       for (int v = 0; v < 16; ++v) acc[tj][ti][v] = 0.0f;
 
   pin_agpr(acc);
-  kloop_w(B0, A0, kp, kbeg, nk, lds, acc);                    // C1 (x1 slices)
-  fold_w(acc, 15, p, inv);
-  kloop_w(B0 + 2 * sB, A0 + 2 * sA, kp, kbeg, nk, lds, acc);  // + C3 (x3 slices)
-  fold_w(acc, kinit, p, inv);
-  kloop_w(B0 + sB, A0 + sA, kp, kbeg, nk, lds, acc);          // + C2 (x2 slices)
+  const int third = 3 - second;
+  kloop_w(B0, A0, kp, kbeg, nk, lds, acc);                              // X = C1
+  fold_w(acc, mul_a, p, inv);
+  kloop_w(B0 + second * sB, A0 + second * sA, kp, kbeg, nk, lds, acc);  // + Y
+  fold_w(acc, mul_b, p, inv);
+  kloop_w(B0 + third * sB, A0 + third * sA, kp, kbeg, nk, lds, acc);    // + Z
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wj = wave >> 1, wi = wave & 1;
@@ -607,7 +615,7 @@ __device__ __forceinline__ void karatsuba_tile_w(const uint8_t *Asl, const uint8
     for (int ti = 0; ti < 4; ++ti) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        int r = smod_i32(-15 * (int)acc[tj][ti][v], p, inv);
+        int r = smod_i32(mul_c * (int)acc[tj][ti][v], p, inv);
         const int64_t i = i0 + wi * 128 + ti * 32 + (lane & 31);
         const int64_t j = j0 + wj * 128 + tj * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
         int16_t *dst = out + j * mp + i;
@@ -635,7 +643,7 @@ __global__ __launch_bounds__(256, 1) void k_residue_gemm(Problem P1, Group G, in
     const int64_t mp = uni(g.mp), np = uni(g.np), kp = uni(g.kp);
     const int64_t kbeg = (int64_t)chunk * kChunkK;
     const int64_t len = kp - kbeg < kChunkK ? kp - kbeg : kChunkK;
-    const int l = (int)uni((KIND == 0 ? 0 : num_square(g.N)) + c.z);
+    const int l = (int)uni((KIND == 0 ? 0 : g.nsq) + c.z);
     if (KIND == 0)
       square_tile(uni(P.w.Asl), uni(P.w.Bsl), uni(P.w.planes), uni(P.tab), mp, np, kp, kbeg,
                   (int)(len / BK), chunk > 0 ? 1 : 0, l, uni(c.x * TI), uni(c.y * TJ), lds);

@@ -22,12 +22,14 @@ struct Tables {
   int32_t N;                  // number of moduli
   int32_t M;                  // digit slices per operand: 2 per square, 3 otherwise
   int32_t limbs;              // 32-bit limbs of P
-  int32_t reserved;
+  int32_t nsq;                // square moduli (they come first): min(N, 6) or 0
   int32_t p[kMaxN];           // moduli, hybrid order (Section III-D)
   int32_t s[kMaxN];           // digit radix: sqrt(p) for squares, 16 otherwise
   int32_t kind[kMaxN];        // 0 square (Section III-C), 1 Karatsuba (III-B)
   int32_t slice0[kMaxN];      // index of the modulus' first digit slice
-  int32_t kinit[kMaxN];       // Karatsuba: -16 / 15 mod p (symmetric), see the residue products
+  int32_t kfold[kMaxN][4];    // Karatsuba: multipliers of the two folds and the final
+                              // reduction, and the slice (1 or 2) of the second pass;
+                              // see the residue products
   int32_t k16[kMaxN];         // 2^16 mod p
   int32_t k32[kMaxN];         // 2^32 mod p
   int32_t k48[kMaxN];         // 2^48 mod p
@@ -42,14 +44,17 @@ struct Tables {
   double D;                   // largest double <= P - 1 (scale rule)
 };
 
-// Builds the tables for N moduli (host).  Returns false for an unsupported N.
-bool build_tables(int N, Tables *t);
+// Builds the tables for N moduli of list `list` (OZ2_MODULI_HYBRID or
+// OZ2_MODULI_KARATSUBA) on the host.  Returns false for an unsupported N.
+bool build_tables(int N, int list, Tables *t);
 
 // Per-call geometry shared by the launchers.
 struct Geometry {
   int64_t m, n, k;            // logical sizes
   int64_t mp, np, kp;         // padded sizes
   int N, M;
+  int nsq;                    // square moduli (the first nsq of the list)
+  int list;                   // OZ2_MODULI_HYBRID or OZ2_MODULI_KARATSUBA
 };
 
 // Workspace views of one call.
@@ -148,8 +153,6 @@ __host__ __device__ inline LmaxShape lmax_shape(const Operand &op) {
   return s;
 }
 
-__host__ __device__ inline int num_square(int N) { return N < 6 ? N : 6; }
-
 struct Dims {
   int64_t x, y, z;
 };
@@ -191,7 +194,7 @@ __host__ __device__ inline Dims family_dims(int fam, const Problem &P, int chunk
     case kFamGemmSq:
     case kFamGemmKa: {
       if ((int64_t)chunk * kChunkK >= g.kp) return {0, 1, 1};
-      const int nsq = num_square(g.N);
+      const int nsq = g.nsq;
       if (fam == kFamGemmSq) return {g.mp / kGemmTI, g.np / kGemmTJ, nsq};
       return {g.mp / kGemmTIW, g.np / kGemmTJ, g.N - nsq};
     }

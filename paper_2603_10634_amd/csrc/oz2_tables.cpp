@@ -5,7 +5,20 @@
 // order; a candidate is kept when it is coprime to every kept modulus.  This
 // puts 1089, 1024, 961, 841, 625, 529 first and continues 511, 509, 503, ...
 // Squares use the modular-reduction split with s = sqrt(p) (Section III-C),
-// the others the Karatsuba split with s = 16 (Section III-B).
+// the others the Karatsuba split with s = 16 (Section III-B).  The
+// Karatsuba-only list of Section III-B (the same scan over 2..513 alone:
+// 513, 512, 511, 509, 505, ...) uses the Karatsuba split for every modulus.
+//
+// Karatsuba products: the residue-product kernel sums the three digit
+// products C1 = A1 B1, C2 = A2 B2, C3 = A3 B3 in one accumulator, one pass
+// after the other, and folds it between passes; the combination
+// 240 C1 - 15 C2 + 16 C3 (eq. C'-Karatsuba) is reached as
+// c (b (a X + Y) + Z) with (X, Y, Z) the passes in order:
+//   p coprime to 15: (C1, C3, C2), a = 15,  b = -16/15, c = -15
+//   p odd otherwise: (C1, C2, C3), a = -16, b = -15/16, c = 16
+// (the divisions modulo p).  Every modulus of the hybrid list is coprime to
+// 15 (1089 = 3^2 11^2 and 625 = 5^4 precede them); of the Karatsuba-only
+// list, 513 = 3^3 19 and 505 = 5 101 take the second order.
 //
 // CRT: with P the product of the moduli, w_l = q_l P / p_l where q_l is the
 // inverse of P / p_l modulo p_l (eq. CRT_finalreduction), stored as 32-bit
@@ -102,9 +115,10 @@ int inv_mod(int a, int p) {  // a^{-1} mod p, gcd(a, p) = 1
   return t < 0 ? t + p : t;
 }
 
-std::vector<int> hybrid_list(int N) {
+std::vector<int> modulus_list(int N, bool hybrid) {
   std::vector<int> cand;
-  for (int s = 2; s <= 33; ++s) cand.push_back(s * s);
+  if (hybrid)
+    for (int s = 2; s <= 33; ++s) cand.push_back(s * s);
   for (int v = 2; v <= 513; ++v) cand.push_back(v);
   std::sort(cand.begin(), cand.end(), [](int a, int b) { return a > b; });
   cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
@@ -118,18 +132,29 @@ std::vector<int> hybrid_list(int N) {
   return out;
 }
 
+// x in the symmetric range [-floor(p/2), ceil(p/2) - 1]
+int sym(int64_t x, int p) {
+  int r = (int)(((x % p) + p) % p);
+  return r > p - 1 - p / 2 ? r - p : r;
+}
+
 }  // namespace
 
-bool build_tables(int N, Tables *t) {
+bool build_tables(int N, int list, Tables *t) {
   if (N < 1 || N > kMaxN) return false;
+  if (list != OZ2_MODULI_HYBRID && list != OZ2_MODULI_KARATSUBA) return false;
+  const bool hybrid = list == OZ2_MODULI_HYBRID;
   memset(t, 0, sizeof(*t));
-  std::vector<int> p = hybrid_list(N);
+  std::vector<int> p = modulus_list(N, hybrid);
   if ((int)p.size() != N) return false;
   t->N = N;
   int slice = 0;
   for (int l = 0; l < N; ++l) {
     int r = (int)std::lround(std::sqrt((double)p[l]));
-    bool square = r * r == p[l];
+    bool square = hybrid && r * r == p[l];
+    // squares must form a prefix of the list (the kernels index them first)
+    if (square && l != t->nsq) return false;
+    if (square) t->nsq = l + 1;
     t->p[l] = p[l];
     t->kind[l] = square ? 0 : 1;
     t->s[l] = square ? r : 16;
@@ -138,11 +163,20 @@ bool build_tables(int N, Tables *t) {
     t->inv_p[l] = 1.0f / (float)p[l];
     t->inv_s[l] = 1.0f / (float)t->s[l];
     if (!square) {
-      // 16 t - 15 G2 = -15 (G2 + t') with t' = -16 t / 15 (mod p); p is coprime
-      // to 15 because 1089 = 3^2 11^2 and 625 = 5^4 precede every Karatsuba modulus
-      int c = (int)((int64_t)(p[l] - 16) * inv_mod(15 % p[l], p[l]) % p[l]);
-      if (c > p[l] - 1 - p[l] / 2) c -= p[l];
-      t->kinit[l] = c;
+      const int q = p[l];
+      if (gcd_int(q, 15) == 1) {          // passes C1, C3, C2
+        t->kfold[l][0] = sym(15, q);
+        t->kfold[l][1] = sym((int64_t)-16 * inv_mod(15 % q, q), q);
+        t->kfold[l][2] = sym(-15, q);
+        t->kfold[l][3] = 2;
+      } else if (q % 2 == 1) {            // passes C1, C2, C3
+        t->kfold[l][0] = sym(-16, q);
+        t->kfold[l][1] = sym((int64_t)-15 * inv_mod(16 % q, q), q);
+        t->kfold[l][2] = sym(16, q);
+        t->kfold[l][3] = 1;
+      } else {
+        return false;
+      }
     }
     uint64_t v = 1;
     for (int e = 0; e < kPowT; ++e) {

@@ -62,11 +62,11 @@ class Run:
 
 
 def run(opA, opB, N, transA="N", transB="N", alpha=1.0, beta=0.0, Cin=None,
-        pad=(0, 0, 0), keep_ws=False, stream=None, mode="accurate"):
+        pad=(0, 0, 0), keep_ws=False, stream=None, mode="accurate", moduli="hybrid"):
     """Column-major ozaki2_dgemm on op(A) (m x k) and op(B) (k x n) given as
-    numpy arrays, in the given scaling mode; leading-dimension padding is
-    filled with NaN (A, B) or 7.0 (C) so reads or writes outside the views
-    show."""
+    numpy arrays, in the given scaling mode and modulus list; leading-dimension
+    padding is filled with NaN (A, B) or 7.0 (C) so reads or writes outside
+    the views show."""
     m, k = opA.shape
     n = opB.shape[1]
     Ab, lda = to_colmajor(opA, transA, ld=(max(1, m) if transA in "Nn" else max(1, k)) + pad[0])
@@ -78,6 +78,16 @@ def run(opA, opB, N, transA="N", transB="N", alpha=1.0, beta=0.0, Cin=None,
     tA = torch.from_numpy(Ab.copy()).to(dev)
     tB = torch.from_numpy(Bb.copy()).to(dev)
     tC = torch.from_numpy(Cb.copy()).to(dev)
+    assert oz.ozaki2_set_moduli_list(moduli) == 0
+    try:
+        return _run_list(tA, tB, tC, transA, transB, m, n, k, alpha, lda, ldb, beta, ldc, N,
+                         keep_ws, stream, mode, dev)
+    finally:
+        oz.ozaki2_set_moduli_list("hybrid")
+
+
+def _run_list(tA, tB, tC, transA, transB, m, n, k, alpha, lda, ldb, beta, ldc, N, keep_ws,
+              stream, mode, dev):
     wbytes = oz.ozaki2_workspace_bytes(m, n, k, N)
     ws = torch.full((wbytes + 256,), 0xEE, dtype=torch.uint8, device=dev)
     base = (ws.data_ptr() + 255) // 256 * 256
@@ -102,12 +112,12 @@ def run(opA, opB, N, transA="N", transB="N", alpha=1.0, beta=0.0, Cin=None,
     return Run(st, tC.cpu().numpy(), ldc, m, n, wsh, off, pads)
 
 
-def check_stages(r: Run, opA, opB, N, st=None, mode="accurate"):
+def check_stages(r: Run, opA, opB, N, st=None, mode="accurate", moduli="hybrid"):
     """Every stored intermediate equals the oracle's, bit for bit.  Fast mode
     stores no bound operands; there every line is flagged as finalized from
     its exact bound and no line is queued for a fix-up."""
     if st is None:
-        _, st = ref.emulate(opA, opB, N, keep_stages=True, mode=mode)
+        _, st = ref.emulate(opA, opB, N, keep_stages=True, mode=mode, moduli_set=moduli)
     m, k = opA.shape
     n = opB.shape[1]
     EA, EB = r.lines(1)

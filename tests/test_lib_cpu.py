@@ -168,3 +168,26 @@ def test_mode_setting_host_only():
     w_fast = oz.ozaki2_workspace_bytes(300, 200, 700, 13)
     oz.ozaki2_set_mode("accurate")
     assert w_fast == oz.ozaki2_workspace_bytes(300, 200, 700, 13)
+
+
+def test_karatsuba_only_list_host_only():
+    # the modulus list is a per-thread host setting; tables, moduli queries
+    # and workspace sizes follow it
+    assert oz.ozaki2_get_moduli_list() == oz.MODULI_HYBRID
+    assert oz.ozaki2_set_moduli_list(5) == -1
+    with pytest.raises(ValueError):
+        oz.ozaki2_set_moduli_list("int8")
+    w_h = oz.ozaki2_workspace_bytes(300, 200, 700, 13)
+    assert oz.ozaki2_set_moduli_list("karatsuba") == 0
+    try:
+        assert oz.ozaki2_get_moduli_list() == oz.MODULI_KARATSUBA
+        for N in range(1, 34):
+            p, kinds = oz.ozaki2_moduli(N)
+            assert p == [q for q, _, _ in ref.moduli_table(N, "karatsuba")]
+            assert kinds == [1] * N
+            _, pads = oz.ozaki2_workspace_layout(300, 200, 700, N)
+            assert pads["M"] == 3 * N
+        assert oz.ozaki2_workspace_bytes(300, 200, 700, 13) > w_h
+    finally:
+        oz.ozaki2_set_moduli_list("hybrid")
+    assert oz.ozaki2_workspace_bytes(300, 200, 700, 13) == w_h

@@ -53,6 +53,14 @@ R14 Karatsuba-only moduli (the list of Section III-B, used as an ablation of
     the hybrid list): p_l from the greedy scan down from 513, every one with
     the Karatsuba split s = 16; residues follow R7, so p = 513 gives digits
     in [-16, 16] like the hybrid list's largest moduli.
+R15 INT8 arm (the INT8-based Ozaki-II scheme of Section II, the paper's
+    baseline): moduli from the Section II list (greedy scan down from 256),
+    one INT8 operand per modulus (the residue itself, in [-128, 127] by R7)
+    and one integer product per modulus, exact in INT32 for k <= 2^16 per
+    chunk.  The scale exponents come from the same bound as the FP8 arm (the
+    FP8 bound product in accurate mode, R13 in fast mode): any upper bound
+    that gives condition (3) serves, and sharing it makes the two arms differ
+    only in their moduli and residue products.
 """
 from __future__ import annotations
 
@@ -156,16 +164,19 @@ def hybrid_moduli(N: int) -> list[tuple[int, str, int]]:
 
 
 def moduli_table(N: int, moduli_set: str = "hybrid") -> list[tuple[int, str, int]]:
-    """The N moduli as (p, kind, s): the hybrid list of Section III-D, or the
-    Karatsuba-only list of Section III-B (every modulus with s = 16, R14)."""
+    """The N moduli as (p, kind, s): the hybrid list of Section III-D, the
+    Karatsuba-only list of Section III-B (every modulus with s = 16, R14), or
+    the INT8 list of Section II (kind "int8", no digit split, R15)."""
     if moduli_set == "hybrid":
         return hybrid_moduli(N)
-    if moduli_set == "karatsuba":
-        out = [(p, "karatsuba", 16) for p in karatsuba_moduli(N)]
+    if moduli_set in ("karatsuba", "int8"):
+        lst = karatsuba_moduli(N) if moduli_set == "karatsuba" else int8_moduli(N)
+        out = [(p, "karatsuba", 16) if moduli_set == "karatsuba" else (p, "int8", 0)
+               for p in lst]
         if len(out) < N:
             raise ValueError("not enough moduli")
         return out
-    raise ValueError("moduli_set must be 'hybrid' or 'karatsuba'")
+    raise ValueError("moduli_set must be 'hybrid', 'karatsuba' or 'int8'")
 
 
 def crt_weights(moduli: list[int]) -> tuple[int, list[int]]:
@@ -291,8 +302,11 @@ def digits_karatsuba(u: np.ndarray, s: int = 16):
 
 
 def digit_slices(u: np.ndarray, kind: str, s: int) -> list[np.ndarray]:
-    """The FP8 slices stored for one modulus: 2 for squares, 3 for Karatsuba
-    (workflow steps 5-6 of Section IV-B)."""
+    """The slices stored for one modulus: 2 FP8 digit slices for squares, 3
+    for Karatsuba (workflow steps 5-6 of Section IV-B), and for the INT8 arm
+    the residue itself as one INT8 slice (Section II)."""
+    if kind == "int8":
+        return [u]
     return list(digits_square(u, s) if kind == "square" else digits_karatsuba(u, s))
 
 
@@ -315,12 +329,14 @@ def residue_product(uA: np.ndarray, uB: np.ndarray, p: int) -> np.ndarray:
 
 def residue_product_fp8(dA: list, dB: list, p: int, kind: str, s: int,
                         chunk: int = 2 ** 16) -> np.ndarray:
-    """C'_l from the three digit products, as the FP8 MMA path forms it.
+    """C'_l from the digit products, as the MMA path forms it.
 
     Squares (eq. 3matmult-notKaratsuba): s A1 B2 + s A2 B1 + A2 B2 (mod p).
     Karatsuba (eq. C'-Karatsuba): s^2 C1 + C2 + s (C3 - C1 - C2) (mod p).
-    Each digit product over a chunk of k <= 2^16 is an integer of magnitude at
-    most 2^24 (eq. error-free-FP8-matmult); chunks are reduced modulo p."""
+    Each FP8 digit product over a chunk of k <= 2^16 is an integer of
+    magnitude at most 2^24 (eq. error-free-FP8-matmult); chunks are reduced
+    modulo p.  INT8 (Section II): the one product of the residues, whose sum
+    over a chunk stays inside INT32 (|u| <= 128, 2^16 2^14 = 2^30)."""
     m, k = dA[0].shape
     acc = np.zeros((m, dB[0].shape[1]), dtype=np.int64)
     for h in range(0, max(k, 1), chunk):
@@ -329,6 +345,10 @@ def residue_product_fp8(dA: list, dB: list, p: int, kind: str, s: int,
                           dB[y][sl, :].astype(np.float64)).astype(np.int64)
         if kind == "square":
             v = s * G(0, 1) + s * G(1, 0) + G(1, 1)
+        elif kind == "int8":
+            v = G(0, 0)
+            if v.size and int(np.max(np.abs(v))) >= 2 ** 31:
+                raise ArithmeticError("INT32 accumulation would overflow")
         else:
             c1, c2, c3 = G(0, 0), G(1, 1), G(2, 2)
             v = s * s * c1 + c2 + s * (c3 - c1 - c2)

@@ -296,7 +296,43 @@ def test_karatsuba_only_integer_inputs_and_accuracy():
         with pytest.raises(ValueError):
             ref.moduli_table(10 ** 4, moduli_set)
     with pytest.raises(ValueError):
-        ref.moduli_table(3, "int8")
+        ref.moduli_table(3, "binary")
+
+
+# INT8 arm (Section II list, R15): 256 = 2^8 and 255 = 3 5 17 come first; the
+# residues are the INT8 operands themselves
+@pytest.mark.parametrize("N", [1, 2, 5, 14, 16])
+def test_int8_arm_pins(N):
+    A, B = _small_problem(5, 6, 19, 1.5, 180 + N)
+    check_condition3(A, B, N, moduli_set="int8")
+    check_residue_products(A, B, N, moduli_set="int8")
+    check_crt_is_exact_product(A, B, N, moduli_set="int8")
+    check_error_bound(A[:3, :], B[:, :3], N, moduli_set="int8")
+    check_condition3(A, B, N, mode="fast", moduli_set="int8")
+    _, st = ref.emulate(A, B, N, keep_stages=True, moduli_set="int8")
+    for pm in st["per_modulus"]:
+        assert len(pm["dA"]) == 1 and np.array_equal(pm["dA"][0], pm["uA"])
+        assert pm["uA"].min() >= -128 and pm["uA"].max() <= 127
+
+
+def test_int8_arm_accuracy_and_int32_limit():
+    # P/2 > 2^109 from N = 14 on (Section II): 14 INT8 moduli reach FP64-level
+    # accuracy on narrow-range inputs, 13 do not
+    check_integer_inputs_exact(14, moduli_set="int8")
+    A, B = _small_problem(24, 20, 1500, 0.5, 520)
+    hi, lo = dd_dot_rows(A, B)
+    e14 = normalised_error(ref.emulate(A, B, 14, moduli_set="int8"), hi, lo, np.abs(A), np.abs(B))
+    e13 = normalised_error(ref.emulate(A, B, 13, moduli_set="int8"), hi, lo, np.abs(A), np.abs(B))
+    assert e14 <= 1e-15 < e13, (e13, e14)
+    # all residues -128 over a chunk of 2^16: 2^30, inside INT32; the check
+    # refuses a chunk whose sum would not be
+    k = 2 ** 16
+    u = np.full((1, k), -128, dtype=np.int64)
+    got = ref.residue_product_fp8([u], [u.T.copy()], 251, "int8", 0)
+    assert int(got[0, 0]) == ref.smod(2 ** 30, 251)
+    with pytest.raises(ArithmeticError):
+        ref.residue_product_fp8([np.full((1, 2 ** 17), -128)], [np.full((2 ** 17, 1), -128)],
+                                251, "int8", 0, chunk=2 ** 17)
 
 
 def test_bound_dominates():

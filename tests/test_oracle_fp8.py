@@ -100,6 +100,15 @@ def test_digits_exhaustive(p, kind, s):
         assert np.all(x1 == np.sign(u) * np.ceil(np.abs(u) / 16))
 
 
+@pytest.mark.parametrize("p,kind,s", ref.moduli_table(33, "int8"))
+def test_int8_operands_exhaustive(p, kind, s):
+    # INT8 arm: the operand is the residue, in [-128, 127] for every p <= 256
+    u = np.arange(-(p // 2), (p + 1) // 2, dtype=np.int64)
+    (x,) = ref.digit_slices(u, kind, s)
+    assert np.array_equal(x, u) and x.min() >= -128 and x.max() <= 127
+    assert np.array_equal(ref.smod(u, p), u)
+
+
 def test_max_digit_is_16():
     # the bound 16 is reached (so it is tight) for 1089, 1024 and 511..487;
     # the smaller moduli stay at 15 or below

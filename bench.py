@@ -42,8 +42,9 @@ def _parse():
     ap.add_argument("--phi", type=float, default=0.5)
     ap.add_argument("--mode", choices=["accurate", "fast"], default="accurate",
                     help="scaling mode (fast: Cauchy-Schwarz bound, no bound product)")
-    ap.add_argument("--moduli-list", choices=["hybrid", "karatsuba"], default="hybrid",
-                    help="modulus list (karatsuba: the Karatsuba-only ablation, N = 13)")
+    ap.add_argument("--moduli-list", choices=["hybrid", "karatsuba", "int8"], default="hybrid",
+                    help="modulus list (karatsuba: the Karatsuba-only ablation, N = 13; "
+                         "int8: the INT8 arm of Section II, N = 14-16)")
     ap.add_argument("--cpu-rows", type=int, default=48,
                     help="rows of op(A) in the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -163,7 +164,9 @@ def main():
 
     # residue products (3 FP8 products per modulus) against the FP8 MFMA peak
     gemm_ms = float(k_mean[4])
-    res_flops = 3 * N * flops
+    # FP8 lists: three products per modulus; INT8 arm: one (same peak rate)
+    products = N if args.moduli_list == "int8" else 3 * N
+    res_flops = products * flops
     achieved = res_flops / (gemm_ms * 1e-3) / 1e12
     traffic = None
     if (args.traffic and os.path.exists(args.traffic) and (m, n, k, N) == (8192, 8192, 8192, 12)
@@ -177,7 +180,8 @@ def main():
                 "unit": "TFLOP/s", "frac": round(achieved / FP8_PEAK_TFLOPS, 4),
                 "traffic": traffic,
                 "kernel": "k_residue_gemm (square + Karatsuba launches), "
-                          f"{3 * N} FP8 products of {m}x{n}x{k} per call"}
+                          f"{products} {'INT8' if args.moduli_list == 'int8' else 'FP8'} "
+                          f"products of {m}x{n}x{k} per call"}
 
     # accuracy against a double-double reference on sampled rows
     Cemu = tC.cpu().numpy().T                    # m x n

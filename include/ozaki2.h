@@ -64,6 +64,7 @@ extern "C" {
 /* Modulus lists (ozaki2_set_moduli_list). */
 #define OZ2_MODULI_HYBRID    0
 #define OZ2_MODULI_KARATSUBA 1
+#define OZ2_MODULI_INT8      2
 
 /*
  * ozaki2_dgemm - emulated DGEMM in the calling thread's mode (ozaki2_set_mode,
@@ -152,8 +153,9 @@ int ozaki2_get_kernel_times(float *ms, int count);
  * ozaki2_moduli - the moduli the library uses for N = num_moduli under the
  * calling thread's modulus list (ozaki2_set_moduli_list), written to
  * p[0..N-1], with kinds[l] = 0 for a square modulus (modular reduction split,
- * Section III-C) and 1 for a Karatsuba modulus (Section III-B).  Either output
- * may be NULL.  Returns 0 or -1 for an invalid N.
+ * Section III-C), 1 for a Karatsuba modulus (Section III-B) and 2 for an INT8
+ * modulus (Section II).  Either output may be NULL.  Returns 0 or -1 for an
+ * invalid N.
  */
 int ozaki2_moduli(int num_moduli, int32_t *p, int32_t *kinds);
 
@@ -292,6 +294,15 @@ int ozaki2_get_mode(void);
  *        P for the same N (P/2 > 2^115 needs N = 13 instead of 12), so about
  *        one more modulus for the same accuracy: an ablation of the hybrid
  *        list's saving.
+ *   OZ2_MODULI_INT8  Section II, the INT8-based Ozaki-II scheme (the
+ *        paper's baseline): 256, 255, 253, 251, 247, ... (greedy pairwise
+ *        coprime from 256); each residue, in [-128, 127], is one INT8
+ *        operand and each modulus costs ONE INT8 product (INT32
+ *        accumulation, v_mfma_i32_32x32x32_i8).  P/2 > 2^109 needs N = 14.
+ *        The scale exponents come from the same FP8 bound (or, in fast mode,
+ *        the same norms) as the FP8 lists.
+ * ozaki2_moduli reports kind 2 for INT8 moduli; the workspace holds one
+ * slice per INT8 modulus (M = N).
  * Returns 0, or -1 for an unknown list (the setting is then unchanged).
  */
 int ozaki2_set_moduli_list(int list);

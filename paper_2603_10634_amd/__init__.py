@@ -19,7 +19,8 @@ __all__ = [
     "ozaki2_status_string", "ozaki2_dgemm_batched", "ozaki2_workspace_bytes_batched",
     "ozaki2_set_graph", "ozaki2_set_autotune", "ozaki2_get_schedule", "ozaki2_set_mode",
     "ozaki2_get_mode", "MODE_ACCURATE", "MODE_FAST", "ozaki2_set_moduli_list",
-    "ozaki2_get_moduli_list", "MODULI_HYBRID", "MODULI_KARATSUBA", "dgemm", "dgemm_batched",
+    "ozaki2_get_moduli_list", "MODULI_HYBRID", "MODULI_KARATSUBA", "MODULI_INT8", "dgemm",
+    "dgemm_batched",
     "LIB_PATH", "HEADER_PATH", "header_functions",
 ]
 
@@ -31,6 +32,7 @@ MODE_ACCURATE = 0   # OZ2_MODE_ACCURATE
 MODE_FAST = 1       # OZ2_MODE_FAST
 MODULI_HYBRID = 0     # OZ2_MODULI_HYBRID
 MODULI_KARATSUBA = 1  # OZ2_MODULI_KARATSUBA
+MODULI_INT8 = 2       # OZ2_MODULI_INT8
 
 _i64 = ctypes.c_int64
 _vp = ctypes.c_void_p
@@ -249,15 +251,16 @@ def ozaki2_get_mode() -> int:
 
 def _list_code(moduli) -> int:
     if isinstance(moduli, str):
-        codes = {"hybrid": MODULI_HYBRID, "karatsuba": MODULI_KARATSUBA}
+        codes = {"hybrid": MODULI_HYBRID, "karatsuba": MODULI_KARATSUBA, "int8": MODULI_INT8}
         if moduli not in codes:
-            raise ValueError("moduli list must be 'hybrid' or 'karatsuba'")
+            raise ValueError("moduli list must be 'hybrid', 'karatsuba' or 'int8'")
         return codes[moduli]
     return int(moduli)
 
 
 def ozaki2_set_moduli_list(moduli) -> int:
-    """moduli: MODULI_HYBRID / MODULI_KARATSUBA, or 'hybrid' / 'karatsuba'."""
+    """moduli: MODULI_HYBRID / MODULI_KARATSUBA / MODULI_INT8, or 'hybrid' /
+    'karatsuba' / 'int8'."""
     return lib().ozaki2_set_moduli_list(_list_code(moduli))
 
 

@@ -188,7 +188,7 @@ Problem make_problem(char transA, char transB, int64_t m, int64_t n, int64_t k, 
   P.B.k = k;
   P.B.sr = tB ? 1 : ldb;
   P.B.sh = tB ? ldb : 1;
-  P.g = Geometry{m, n, k, L.mp, L.np, L.kp, N, L.M, ht->nsq, g_ts.list};
+  P.g = Geometry{m, n, k, L.mp, L.np, L.kp, N, L.M, ht->nsq, ht->nka, g_ts.list};
   Work &w = P.w;
   w.amax = (uint64_t *)(ws + L.off[10]);
   w.flags = (uint32_t *)(ws + L.off[11]);
@@ -260,10 +260,9 @@ int enqueue_single(const Problem &P, hipStream_t st, Marks &mark) {
   OZ2_TRY(launch_quant_family(kFamResB, &P, nullptr, st));
   mark();
   // steps 7-8: residue products and their reduction modulo p, per k chunk
-  for (int c = 0; c < num_chunks(P.g.kp); ++c) {
-    OZ2_TRY(launch_gemm_family(kFamGemmSq, &P, nullptr, c, 0, st));
-    OZ2_TRY(launch_gemm_family(kFamGemmKa, &P, nullptr, c, 0, st));
-  }
+  for (int c = 0; c < num_chunks(P.g.kp); ++c)
+    for (int f : {kFamGemmSq, kFamGemmKa, kFamGemmI8})
+      OZ2_TRY(launch_gemm_family(f, &P, nullptr, c, 0, st));
   mark();
   // steps 9-10: CRT and inverse scaling
   OZ2_TRY(launch_crt_family(&P, nullptr, P.limbs, st));
@@ -467,6 +466,7 @@ void build_subbatch(const std::vector<Problem> &probs, ImageWriter &W, SubBatch 
     for (int c = 0; c < chunks; ++c) {
       add(kFamGemmSq, c, order);
       add(kFamGemmKa, c, order);
+      add(kFamGemmI8, c, order);
     }
   add(kFamCrt, 0, 0);
 }
@@ -477,7 +477,7 @@ int family_group(int fam) {
     case kFamBgemm: return 1;
     case kFamDecide: case kFamFixup: case kFamFinal: return 2;
     case kFamResA: case kFamResB: return 3;
-    case kFamGemmSq: case kFamGemmKa: return 4;
+    case kFamGemmSq: case kFamGemmKa: case kFamGemmI8: return 4;
     case kFamCrt: return 5;
     default: return 0;
   }
@@ -502,7 +502,7 @@ int enqueue_subbatch(const SubBatch &sb, int sched, int cus, hipStream_t st, Mar
     return OZ2_SUCCESS;
   };
   for (const GLaunch &L : sb.launches) {
-    const bool gemm = L.fam == kFamGemmSq || L.fam == kFamGemmKa;
+    const bool gemm = L.fam == kFamGemmSq || L.fam == kFamGemmKa || L.fam == kFamGemmI8;
     if (gemm && L.order != order) continue;
     const int gq = family_group(L.fam);
     if (gq < g0 || gq > g1) continue;
@@ -1002,7 +1002,8 @@ int ozaki2_set_mode(int mode) {
 int ozaki2_get_mode(void) { return g_ts.mode; }
 
 int ozaki2_set_moduli_list(int list) {
-  if (list != OZ2_MODULI_HYBRID && list != OZ2_MODULI_KARATSUBA) return -1;
+  if (list != OZ2_MODULI_HYBRID && list != OZ2_MODULI_KARATSUBA && list != OZ2_MODULI_INT8)
+    return -1;
   g_ts.list = list;
   return OZ2_SUCCESS;
 }

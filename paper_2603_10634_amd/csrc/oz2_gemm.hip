@@ -8,6 +8,8 @@
 //    k <= 2^15 every partial sum is an integer of magnitude <= 2^24 and the
 //    FP32 accumulation is exact (eq. error-free-FP8-matmult); the epilogue
 //    combines the products and reduces them modulo p into int16 planes.
+//  * INT8 arm (Section II): one product of the INT8 residues per modulus on
+//    v_mfma_i32_32x32x32_i8, INT32 accumulation, the same wide loop.
 //
 // Layout: operand slices are K-contiguous (line r's k bytes at r * kp).  The
 // MFMA "A" operand is fed from B's slices (rows j) and the "B" operand from
@@ -32,6 +34,7 @@ namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v8i __attribute__((ext_vector_type(8)));
+typedef int v16i __attribute__((ext_vector_type(16)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr int TJ = 256;                  // tile rows (j, from B's slices)
@@ -61,6 +64,21 @@ __device__ __forceinline__ v16f mfma_f8(v8i a, v8i b, v16f c) {
   // cbsz = blgp = 0 selects E4M3 for both operands; zero scale operands give
   // the unscaled instruction
   return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 0, 0, 0);
+}
+
+// One 32 x 32 x 64 step of the single-product loop: an FP8 MFMA into FP32
+// accumulators, or two INT8 MFMAs (32 k each) into INT32 accumulators.  The
+// INT8 pair takes the low 16 bytes of every lane's 32-byte fragment first and
+// the high 16 bytes second; both operands are split alike, so every byte of A
+// still meets the byte of B with the same k and the sum covers all 64 k.
+__device__ __forceinline__ v16f mma(v8i a, v8i b, v16f c) { return mfma_f8(a, b, c); }
+__device__ __forceinline__ v16i mma(v8i a, v8i b, v16i c) {
+  const v4i alo = __builtin_shufflevector(a, a, 0, 1, 2, 3);
+  const v4i ahi = __builtin_shufflevector(a, a, 4, 5, 6, 7);
+  const v4i blo = __builtin_shufflevector(b, b, 0, 1, 2, 3);
+  const v4i bhi = __builtin_shufflevector(b, b, 4, 5, 6, 7);
+  c = __builtin_amdgcn_mfma_i32_32x32x32_i8(alo, blo, c, 0, 0, 0);
+  return __builtin_amdgcn_mfma_i32_32x32x32_i8(ahi, bhi, c, 0, 0, 0);
 }
 
 // Operand fragment of a 32-row sub-tile: lane l holds row (l % 32) and the 32
@@ -437,12 +455,14 @@ __device__ __forceinline__ void dma_part_w(const uint8_t *gB, const uint8_t *gA,
 }
 
 // One stage of the wide loop, scheduled as stage_iter (blocks rows tj of 4
-// MFMAs; barrier B_j before the last block row; loads in four parts of 2).
+// MFMA steps; barrier B_j before the last block row; loads in four parts of
+// 2).  ACC is v16f (FP8 products) or v16i (INT8 products).
+template <class ACC>
 __device__ __forceinline__ void stage_iter_w(int j, int nk, const uint8_t *gB, const uint8_t *gA,
                                              const DmaOffsets &d, int64_t kbeg,
                                              const uint8_t *lds, uint32_t ring,
                                              const v8i (&fa)[4], v8i (&fan)[4], v8i (&fb)[4],
-                                             v16f (&acc)[4][4]) {
+                                             ACC (&acc)[4][4]) {
   constexpr int L = 8;
   const int wave = threadIdx.x >> 6;
   const int wj = wave >> 1, wi = wave & 1;
@@ -458,7 +478,7 @@ __device__ __forceinline__ void stage_iter_w(int j, int nk, const uint8_t *gB, c
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int ti = 0; ti < 4; ++ti) {
-      acc[tj][ti] = mfma_f8(fb[tj], fa[ti], acc[tj][ti]);
+      acc[tj][ti] = mma(fb[tj], fa[ti], acc[tj][ti]);
       __builtin_amdgcn_sched_barrier(0);
       if (ti == 0 && ld_prev) {
         if (tj == 0) dma_part_w<1>(gB, gA, d, kofs_prev, slot_prev);
@@ -475,7 +495,7 @@ __device__ __forceinline__ void stage_iter_w(int j, int nk, const uint8_t *gB, c
   const uint8_t *nxt = lds + ((j + 1) % SW) * STAGEW;
 #pragma unroll
   for (int ti = 0; ti < 4; ++ti) {
-    acc[3][ti] = mfma_f8(fb[3], fa[ti], acc[3][ti]);
+    acc[3][ti] = mma(fb[3], fa[ti], acc[3][ti]);
     __builtin_amdgcn_sched_barrier(0);
     if (ti == 0 && ld_next)
       dma_part_w<0>(gB, gA, d, kbeg + (int64_t)(j + SW) * BK, ring + (j % SW) * STAGEW);
@@ -497,8 +517,9 @@ __device__ __forceinline__ void stage_iter_w(int j, int nk, const uint8_t *gB, c
 
 // acc += A B over nk stages of 64 k for one wide tile; gB / gA point at row
 // j0 / i0 of one B-side / A-side slice.
+template <class ACC>
 __device__ __forceinline__ void kloop_w(const uint8_t *gB, const uint8_t *gA, int64_t kp,
-                                        int64_t kbeg, int nk, uint8_t *lds, v16f (&acc)[4][4]) {
+                                        int64_t kbeg, int nk, uint8_t *lds, ACC (&acc)[4][4]) {
   constexpr int L = 8;
   const int wave = threadIdx.x >> 6;
   const int wj = wave >> 1, wi = wave & 1;
@@ -531,7 +552,8 @@ __device__ __forceinline__ void kloop_w(const uint8_t *gB, const uint8_t *gA, in
 // Keeps the accumulator tiles in AGPRs at this point (an empty asm with
 // AGPR in/out operands), so the register allocator does not move the whole
 // accumulator to VGPRs around the folds between passes.
-__device__ __forceinline__ void pin_agpr(v16f (&acc)[4][4]) {
+template <class ACC>
+__device__ __forceinline__ void pin_agpr(ACC (&acc)[4][4]) {
 #pragma unroll
   for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
@@ -626,9 +648,60 @@ __device__ __forceinline__ void karatsuba_tile_w(const uint8_t *Asl, const uint8
     }
 }
 
+// One 256 x 256 tile (j0.., i0..) of INT8 modulus l (Section II) over k in
+// [kbeg, kbeg + 64 nk): the one product of the INT8 residues, accumulated in
+// INT32 (|u| <= 128, so a chunk of k <= 2^15 sums to at most 2^29), then
+// reduced modulo p.
+__device__ __forceinline__ void int8_tile_w(const uint8_t *Asl, const uint8_t *Bsl,
+                                            int16_t *__restrict__ planes,
+                                            const Tables *__restrict__ tab, int64_t mp,
+                                            int64_t np, int64_t kp, int64_t kbeg, int nk,
+                                            int accumulate, int l, int64_t i0, int64_t j0,
+                                            uint8_t *lds) {
+  const int sl0 = (int)uni(tab->slice0[l]);
+  const int p = (int)uni(tab->p[l]);
+  const float inv = __int_as_float((int)uni(__float_as_int(tab->inv_p[l])));
+  resident(sl0, p, __float_as_int(inv), p);
+  resident_ptr(planes, planes);
+  resident(accumulate, accumulate, accumulate, accumulate);
+  const uint8_t *A0 = Asl + (int64_t)sl0 * mp * kp + i0 * kp;
+  const uint8_t *B0 = Bsl + (int64_t)sl0 * np * kp + j0 * kp;
+
+  v16i acc[4][4];
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[tj][ti][v] = 0;
+  pin_agpr(acc);
+  kloop_w(B0, A0, kp, kbeg, nk, lds, acc);
+  pin_agpr(acc);
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wj = wave >> 1, wi = wave & 1;
+  int16_t *out = planes + (int64_t)l * np * mp;
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        int r = smod_i32(acc[tj][ti][v], p, inv);
+        const int64_t i = i0 + wi * 128 + ti * 32 + (lane & 31);
+        const int64_t j = j0 + wj * 128 + tj * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+        int16_t *dst = out + j * mp + i;
+        if (accumulate) r = smod_i32(r + (int)*dst, p, inv);
+        *dst = (int16_t)r;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 // Residue products of k chunk `chunk`: KIND 0 over the square moduli (256 x
 // 128 tiles, tile index z = l), 1 over the Karatsuba moduli (256 x 256
-// tiles, l = 6 + z).
+// tiles, l = nsq + z), 2 over the INT8 moduli (256 x 256 tiles,
+// l = nsq + nka + z).
 // A grouped launch may run fewer workgroups than tiles; each then loops.
 template <int KIND, bool GROUPED>
 __global__ __launch_bounds__(256, 1) void k_residue_gemm(Problem P1, Group G, int chunk) {
@@ -638,19 +711,23 @@ __global__ __launch_bounds__(256, 1) void k_residue_gemm(Problem P1, Group G, in
     int64_t local;
     const Problem &P = *locate<GROUPED>(P1, G, b, local);
     const Geometry &g = P.g;
-    const Dims d = family_dims(KIND == 0 ? kFamGemmSq : kFamGemmKa, P, chunk);
+    const Dims d =
+        family_dims(KIND == 0 ? kFamGemmSq : (KIND == 1 ? kFamGemmKa : kFamGemmI8), P, chunk);
     const Dims c = decode_block(d, local);
     const int64_t mp = uni(g.mp), np = uni(g.np), kp = uni(g.kp);
     const int64_t kbeg = (int64_t)chunk * kChunkK;
     const int64_t len = kp - kbeg < kChunkK ? kp - kbeg : kChunkK;
-    const int l = (int)uni((KIND == 0 ? 0 : g.nsq) + c.z);
+    const int l = (int)uni((KIND == 0 ? 0 : (KIND == 1 ? g.nsq : g.nsq + g.nka)) + c.z);
     if (KIND == 0)
       square_tile(uni(P.w.Asl), uni(P.w.Bsl), uni(P.w.planes), uni(P.tab), mp, np, kp, kbeg,
                   (int)(len / BK), chunk > 0 ? 1 : 0, l, uni(c.x * TI), uni(c.y * TJ), lds);
-    else
+    else if (KIND == 1)
       karatsuba_tile_w(uni(P.w.Asl), uni(P.w.Bsl), uni(P.w.planes), uni(P.tab), mp, np, kp,
                        kbeg, (int)(len / BK), chunk > 0 ? 1 : 0, l, uni(c.x * TIW),
                        uni(c.y * TJ), lds);
+    else
+      int8_tile_w(uni(P.w.Asl), uni(P.w.Bsl), uni(P.w.planes), uni(P.tab), mp, np, kp, kbeg,
+                  (int)(len / BK), chunk > 0 ? 1 : 0, l, uni(c.x * TIW), uni(c.y * TJ), lds);
   }
 }
 
@@ -756,6 +833,12 @@ hipError_t launch_gemm_family(int fam, const Problem *P, const Group *G, int chu
         hipLaunchKernelGGL((k_residue_gemm<1, true>), gr, blk, 0, st, p1, g1, chunk);
       else
         hipLaunchKernelGGL((k_residue_gemm<1, false>), gr, blk, 0, st, p1, g1, chunk);
+      break;
+    case kFamGemmI8:
+      if (grouped)
+        hipLaunchKernelGGL((k_residue_gemm<2, true>), gr, blk, 0, st, p1, g1, chunk);
+      else
+        hipLaunchKernelGGL((k_residue_gemm<2, false>), gr, blk, 0, st, p1, g1, chunk);
       break;
     default:
       return hipErrorInvalidValue;

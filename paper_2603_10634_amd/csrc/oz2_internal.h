@@ -23,17 +23,18 @@ struct Tables {
   int32_t M;                  // digit slices per operand: 2 per square, 3 otherwise
   int32_t limbs;              // 32-bit limbs of P
   int32_t nsq;                // square moduli (they come first): min(N, 6) or 0
+                              // (then the Karatsuba moduli, or the INT8 ones)
+  int32_t nka;                // Karatsuba moduli
+  int32_t reserved[3];
   int32_t p[kMaxN];           // moduli, hybrid order (Section III-D)
-  int32_t s[kMaxN];           // digit radix: sqrt(p) for squares, 16 otherwise
-  int32_t kind[kMaxN];        // 0 square (Section III-C), 1 Karatsuba (III-B)
-  int32_t slice0[kMaxN];      // index of the modulus' first digit slice
+  int32_t s[kMaxN];           // digit radix: sqrt(p) for squares, 16 for Karatsuba
+  int32_t kind[kMaxN];        // 0 square (Section III-C), 1 Karatsuba (III-B), 2 INT8 (II)
+  int32_t slice0[kMaxN];      // index of the modulus' first slice (2, 3 or 1 slices)
   int32_t kfold[kMaxN][4];    // Karatsuba: multipliers of the two folds and the final
                               // reduction, and the slice (1 or 2) of the second pass;
                               // see the residue products
-  int32_t k16[kMaxN];         // 2^16 mod p
-  int32_t k32[kMaxN];         // 2^32 mod p
-  int32_t k48[kMaxN];         // 2^48 mod p
   float inv_p[kMaxN];         // 1/p, float
+  double inv_pd[kMaxN];       // 1/p, double
   float inv_s[kMaxN];         // 1/s, float
   uint16_t pw[kMaxN][kPowT];  // 2^t mod p, t < kPowT
   uint32_t w[kMaxN][kLimbs];  // CRT weights q_l P / p_l, little-endian limbs
@@ -44,8 +45,9 @@ struct Tables {
   double D;                   // largest double <= P - 1 (scale rule)
 };
 
-// Builds the tables for N moduli of list `list` (OZ2_MODULI_HYBRID or
-// OZ2_MODULI_KARATSUBA) on the host.  Returns false for an unsupported N.
+// Builds the tables for N moduli of list `list` (OZ2_MODULI_HYBRID,
+// OZ2_MODULI_KARATSUBA or OZ2_MODULI_INT8) on the host.  Returns false for an
+// unsupported N.
 bool build_tables(int N, int list, Tables *t);
 
 // Per-call geometry shared by the launchers.
@@ -54,7 +56,8 @@ struct Geometry {
   int64_t mp, np, kp;         // padded sizes
   int N, M;
   int nsq;                    // square moduli (the first nsq of the list)
-  int list;                   // OZ2_MODULI_HYBRID or OZ2_MODULI_KARATSUBA
+  int nka;                    // Karatsuba moduli (the next nka); the rest are INT8
+  int list;                   // OZ2_MODULI_HYBRID, _KARATSUBA or _INT8
 };
 
 // Workspace views of one call.
@@ -125,6 +128,7 @@ enum Family : int {
   kFamResB,
   kFamGemmSq,     // residue products, square moduli (one launch per k chunk)
   kFamGemmKa,     // residue products, Karatsuba moduli
+  kFamGemmI8,     // residue products, INT8 moduli
   kFamCrt,        // CRT, inverse scaling, alpha / beta
   kNumFamilies
 };
@@ -192,11 +196,12 @@ __host__ __device__ inline Dims family_dims(int fam, const Problem &P, int chunk
       return {b < 8 ? 8 : (b > 512 ? 512 : b), 1, 1};
     }
     case kFamGemmSq:
-    case kFamGemmKa: {
+    case kFamGemmKa:
+    case kFamGemmI8: {
       if ((int64_t)chunk * kChunkK >= g.kp) return {0, 1, 1};
-      const int nsq = g.nsq;
-      if (fam == kFamGemmSq) return {g.mp / kGemmTI, g.np / kGemmTJ, nsq};
-      return {g.mp / kGemmTIW, g.np / kGemmTJ, g.N - nsq};
+      if (fam == kFamGemmSq) return {g.mp / kGemmTI, g.np / kGemmTJ, g.nsq};
+      if (fam == kFamGemmKa) return {g.mp / kGemmTIW, g.np / kGemmTJ, g.nka};
+      return {g.mp / kGemmTIW, g.np / kGemmTJ, g.N - g.nsq - g.nka};
     }
     case kFamCrt:
       return {(g.m + 255) / 256, g.n, 1};

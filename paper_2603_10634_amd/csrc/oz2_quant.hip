@@ -225,49 +225,125 @@ __global__ __launch_bounds__(256) void k_bound_norm(Problem P1, Group G) {
                   P.w.rfix + base, tile);
 }
 
-// Symmetric remainder of |x| < 2^29 modulo p, in [lo, hi] = [-floor(p/2),
-// ceil(p/2) - 1].  The float quotient estimate is within 1 of the rounded
-// quotient (|x| p^-1 carries a relative error below 2^-22), so one correction
-// in either direction suffices; both products fit the 24-bit multiplier.
-__device__ __forceinline__ int mod_sym(int x, int p, float invp, int lo, int hi) {
-  const int q = (int)rintf((float)x * invp);
-  int r = x - __mul24(q, p);
-  r = r > hi ? r - p : r;
-  r = r < lo ? r + p : r;
-  return r;
-}
-
-// Residues of a' (eq. def:A') for every modulus, split into FP8 digits, for
-// one tile (lines r0.., k h0..).
+// Residues of a' (eq. def:A') for every modulus, split into digits, for one
+// tile (lines r0.., k h0..).
 //
 // Each finite input is |a| = mant 2^qe with mant < 2^53; with s = log2 mu_r
 // the integer is a' = sign (mant 2^t) for t = qe + s > 0, else
-// sign floor(mant 2^t) (eq. def:A': truncation toward zero).  The magnitude
-// m (mant or mant 2^t) is split into four 16-bit chunks carrying the sign,
-// so a' = c0 + c1 2^16 + c2 2^32 + c3 2^48 and
-//   a' = c0 + c1 (2^16 mod p) + c2 (2^32 mod p) + c3 (2^48 mod p)  (mod p)
-// is a sum below 2^29 in 24-bit multiply-adds; for t > 0 it is multiplied by
-// 2^t mod p afterwards.  Digits (Sections III-B, III-C) are formed in FP32,
-// exact for these small integers, and packed to E4M3 two at a time by the
-// hardware conversion (exact: every digit has |d| <= 16).
+// sign floor(mant 2^t) (eq. def:A': truncation toward zero).  Per input the
+// signed integer x = sign mant 2^min(t, 10) (t > 0) or a' (t <= 0) is held
+// exactly in a double (|x| < 2^63).  Per modulus, x mod p is taken in FP64:
+// q = rint(x p^-1) is within 21 of the rounded quotient (within one when
+// |x| < 2^53), x - q p is exact in one fused multiply-add (|x - q p| < 2^15),
+// and when some input of the wave has t > 0 one FP32 step reduces it to
+// within one of [lo, hi] = [-floor(p/2), ceil(p/2) - 1]; one correction in
+// each direction finishes.  Inputs with t > 10 (only for large N: t <= e - 45
+// for the scale exponent e) are then multiplied by 2^(t - 10) mod p (tables)
+// and reduced again in FP32 (products below 2^20, exact).  Digits (Sections
+// III-B, III-C) are formed in FP32, exact for these small integers, and
+// packed to E4M3 two at a time by the hardware conversion (exact: every digit
+// has |d| <= 16).  An INT8 modulus (Section II) stores the residue itself,
+// in [-128, 127], as one INT8 byte.  The moduli are visited kind by kind
+// (squares, then Karatsuba, then INT8), so no loop body branches on the kind.
+constexpr int kDirectT = 10;  // powers 2^t applied in FP64 directly
+
+struct ResidueIn {
+  double x[16];  // sign mant 2^min(t, 10) (t > 0) or signed a' (t <= 0), exact
+  int t[16];     // t > 10: the power of two t - 10 still to apply, else 0
+  bool big;      // some lane of the wave has t > 0
+  bool huge;     // some lane of the wave has t > 10
+};
+
+template <int KIND>
+__device__ __forceinline__ void modulus_pass(const ResidueIn &in, const Tables *__restrict__ tab,
+                                             int l, uint8_t *dst, int64_t slice_stride) {
+  const int p = tab->p[l];
+  const float pf = (float)p;
+  const float lof = (float)(-(p >> 1)), hif = (float)(p - 1 - (p >> 1));
+  const double pd = (double)p, invpd = tab->inv_pd[l];
+  const float invpf = tab->inv_p[l];
+  float fu[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const double x = in.x[q];
+    float f = (float)fma(-rint(x * invpd), pd, x);
+    if (in.big) f = fmaf(-rintf(f * invpf), pf, f);
+    f = f > hif ? f - pf : f;
+    f = f < lof ? f + pf : f;
+    fu[q] = f;
+  }
+  if (in.huge) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      if (in.t[q] > 0) {
+        const float prod = fu[q] * (float)tab->pw[l][in.t[q]];
+        const float qq = rintf(prod * invpf);
+        float f = fmaf(-qq, pf, prod);
+        f = f > hif ? f - pf : f;
+        f = f < lof ? f + pf : f;
+        fu[q] = f;
+      }
+    }
+  }
+  int w1[4], w2[4], w3[4];
+  if (KIND == 2) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      uint32_t word = 0;
+#pragma unroll
+      for (int z = 0; z < 4; ++z) word |= ((uint32_t)(int)fu[4 * g + z] & 0xFFu) << (8 * z);
+      w1[g] = (int)word;
+    }
+    *(uint4 *)dst = make_uint4(w1[0], w1[1], w1[2], w1[3]);
+    return;
+  }
+  const float sf = (float)tab->s[l], invs = tab->inv_s[l];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    float x1[4], x2[4], x3[4];
+#pragma unroll
+    for (int z = 0; z < 4; ++z) {
+      const float f = fu[4 * g + z];
+      if (KIND == 0) {
+        // p = s^2: x1 = round(u / s) (ties away from zero), x2 = u - s x1
+        const float tq = f * invs;
+        x1[z] = truncf(tq + copysignf(0.5f, tq)) + 0.0f;  // + 0 turns -0 into +0
+        x2[z] = fmaf(-sf, x1[z], f);
+      } else {
+        // s = 16: x1 = sign(u) ceil(|u| / 16), x2 = u - 16 x1, x3 = x1 + x2
+        x1[z] = copysignf(ceilf(fabsf(f) * 0.0625f), f);
+        x2[z] = fmaf(-16.0f, x1[z], f);
+        x3[z] = x1[z] + x2[z];
+      }
+    }
+    w1[g] = __builtin_amdgcn_cvt_pk_fp8_f32(x1[0], x1[1], 0, false);
+    w1[g] = __builtin_amdgcn_cvt_pk_fp8_f32(x1[2], x1[3], w1[g], true);
+    w2[g] = __builtin_amdgcn_cvt_pk_fp8_f32(x2[0], x2[1], 0, false);
+    w2[g] = __builtin_amdgcn_cvt_pk_fp8_f32(x2[2], x2[3], w2[g], true);
+    if (KIND == 1) {
+      w3[g] = __builtin_amdgcn_cvt_pk_fp8_f32(x3[0], x3[1], 0, false);
+      w3[g] = __builtin_amdgcn_cvt_pk_fp8_f32(x3[2], x3[3], w3[g], true);
+    }
+  }
+  *(uint4 *)dst = make_uint4(w1[0], w1[1], w1[2], w1[3]);
+  *(uint4 *)(dst + slice_stride) = make_uint4(w2[0], w2[1], w2[2], w2[3]);
+  if (KIND == 1) *(uint4 *)(dst + 2 * slice_stride) = make_uint4(w3[0], w3[1], w3[2], w3[3]);
+}
+
 __device__ __forceinline__ void residues_tile(const Operand &op, int64_t kp, int64_t lines_pad,
                                               int64_t r0, int64_t h0,
                                               const int32_t *__restrict__ shift,
-                                              const Tables *__restrict__ tab, int N,
-                                              uint8_t *__restrict__ slices, double *tile,
-                                              uint16_t *wtab) {
+                                              const Tables *__restrict__ tab, int N, int nsq,
+                                              int nka, uint8_t *__restrict__ slices,
+                                              double *tile) {
   stage_tile(op, r0, h0, tile);
-  {
-    const uint16_t *src = &tab->pw[0][0];
-    for (int i = threadIdx.x; i < N * kPowT; i += 256) wtab[i] = src[i];
-  }
   __syncthreads();
   const int rl = threadIdx.x >> 3, b = threadIdx.x & 7;
   const int64_t r = r0 + rl;
   const int s = shift[r];  // log2(mu_r)
 
-  int c0[16], c1[16], c2[16], c3[16], tt[16];
-  bool big = false;
+  ResidueIn in;
+  bool big = false, huge = false;
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const uint64_t bits = (uint64_t)__double_as_longlong(tile[tile_at(rl, b * 16 + q)]);
@@ -285,77 +361,30 @@ __device__ __forceinline__ void residues_tile(const Operand &op, int64_t kp, int
         m = mant >> (-e2);
       }
     }
-    const int lo32 = (int)(uint32_t)m, hi32 = (int)(uint32_t)(m >> 32);
-    const int neg = (int)(bits >> 63);
-    // chunks with the sign of a
-    const int a0 = lo32 & 0xFFFF, a1 = (int)((uint32_t)lo32 >> 16);
-    const int a2 = hi32 & 0xFFFF, a3 = (int)((uint32_t)hi32 >> 16);
-    c0[q] = neg ? -a0 : a0;
-    c1[q] = neg ? -a1 : a1;
-    c2[q] = neg ? -a2 : a2;
-    c3[q] = neg ? -a3 : a3;
-    tt[q] = t;
+    // exact: m < 2^53, times 2^min(t, 10); never -0 (a zero digit encodes as +0)
+    const double md = ldexp((double)m, t < kDirectT ? t : kDirectT);
+    in.x[q] = ((bits >> 63) && m) ? -md : md;
+    in.t[q] = t > kDirectT ? t - kDirectT : 0;
     big |= t > 0;
+    huge |= t > kDirectT;
   }
-  const bool wave_big = __any(big);
+  in.big = __any(big);
+  in.huge = __any(huge);
 
   const int64_t slice_stride = lines_pad * kp;
   uint8_t *base = slices + r * kp + h0 + b * 16;
-  for (int l = 0; l < N; ++l) {
-    const int p = tab->p[l];
-    const int lo = -(p >> 1), hi = p - 1 - (p >> 1);
-    const int K1 = tab->k16[l], K2 = tab->k32[l], K3 = tab->k48[l];
-    const float invp = tab->inv_p[l];
-    const int kind = tab->kind[l];
-    const float sf = (float)tab->s[l], invs = tab->inv_s[l];
-    const uint16_t *wl = wtab + l * kPowT;
-    int w1[4] = {0, 0, 0, 0}, w2[4] = {0, 0, 0, 0}, w3[4] = {0, 0, 0, 0};
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      float x1[4], x2[4], x3[4];
-#pragma unroll
-      for (int z = 0; z < 4; ++z) {
-        const int q = 4 * g + z;
-        const int x = c0[q] + __mul24(c1[q], K1) + __mul24(c2[q], K2) + __mul24(c3[q], K3);
-        int u = mod_sym(x, p, invp, lo, hi);
-        if (wave_big) {
-          const int w = tt[q] > 0 ? (int)wl[tt[q]] : 1;
-          u = mod_sym(__mul24(u, w), p, invp, lo, hi);
-        }
-        const float fu = (float)u;
-        if (kind == 0) {
-          // p = s^2: x1 = round(u / s) (ties away from zero), x2 = u - s x1
-          const float tq = fu * invs;
-          x1[z] = truncf(tq + copysignf(0.5f, tq)) + 0.0f;  // + 0 turns -0 into +0
-          x2[z] = fmaf(-sf, x1[z], fu);
-          x3[z] = 0.0f;
-        } else {
-          // s = 16: x1 = sign(u) ceil(|u| / 16), x2 = u - 16 x1, x3 = x1 + x2
-          x1[z] = copysignf(ceilf(fabsf(fu) * 0.0625f), fu);
-          x2[z] = fmaf(-16.0f, x1[z], fu);
-          x3[z] = x1[z] + x2[z];
-        }
-      }
-      w1[g] = __builtin_amdgcn_cvt_pk_fp8_f32(x1[0], x1[1], 0, false);
-      w1[g] = __builtin_amdgcn_cvt_pk_fp8_f32(x1[2], x1[3], w1[g], true);
-      w2[g] = __builtin_amdgcn_cvt_pk_fp8_f32(x2[0], x2[1], 0, false);
-      w2[g] = __builtin_amdgcn_cvt_pk_fp8_f32(x2[2], x2[3], w2[g], true);
-      if (kind != 0) {
-        w3[g] = __builtin_amdgcn_cvt_pk_fp8_f32(x3[0], x3[1], 0, false);
-        w3[g] = __builtin_amdgcn_cvt_pk_fp8_f32(x3[2], x3[3], w3[g], true);
-      }
-    }
-    uint8_t *dst = base + (int64_t)tab->slice0[l] * slice_stride;
-    *(uint4 *)dst = make_uint4(w1[0], w1[1], w1[2], w1[3]);
-    *(uint4 *)(dst + slice_stride) = make_uint4(w2[0], w2[1], w2[2], w2[3]);
-    if (kind != 0) *(uint4 *)(dst + 2 * slice_stride) = make_uint4(w3[0], w3[1], w3[2], w3[3]);
-  }
+  int l = 0;
+  for (; l < nsq; ++l)
+    modulus_pass<0>(in, tab, l, base + (int64_t)tab->slice0[l] * slice_stride, slice_stride);
+  for (; l < nsq + nka; ++l)
+    modulus_pass<1>(in, tab, l, base + (int64_t)tab->slice0[l] * slice_stride, slice_stride);
+  for (; l < N; ++l)
+    modulus_pass<2>(in, tab, l, base + (int64_t)tab->slice0[l] * slice_stride, slice_stride);
 }
 
 template <bool GROUPED, int SIDE>
 __global__ __launch_bounds__(256) void k_residues(Problem P1, Group G) {
   __shared__ double tile[kQL * kRowLd];
-  __shared__ uint16_t wtab[kMaxN * kPowT];
   int64_t local;
   const Problem &P = *locate<GROUPED>(P1, G, blockIdx.x, local);
   const Operand &op = SIDE == 0 ? P.A : P.B;
@@ -363,7 +392,7 @@ __global__ __launch_bounds__(256) void k_residues(Problem P1, Group G) {
   const Dims d = family_dims(SIDE == 0 ? kFamResA : kFamResB, P, 0);
   const int64_t bx = local % d.x, by = local / d.x;
   residues_tile(op, P.g.kp, SIDE == 0 ? P.g.mp : P.g.np, bx * kQL, by * kQK, P.w.shift + base,
-                P.tab, P.g.N, SIDE == 0 ? P.w.Asl : P.w.Bsl, tile, wtab);
+                P.tab, P.g.N, P.g.nsq, P.g.nka, SIDE == 0 ? P.w.Asl : P.w.Bsl, tile);
 }
 
 }  // namespace

@@ -8,6 +8,8 @@
 // the others the Karatsuba split with s = 16 (Section III-B).  The
 // Karatsuba-only list of Section III-B (the same scan over 2..513 alone:
 // 513, 512, 511, 509, 505, ...) uses the Karatsuba split for every modulus.
+// The INT8 list of Section II (the scan over 2..256: 256, 255, 253, ...)
+// keeps each residue, in [-128, 127], as one INT8 operand.
 //
 // Karatsuba products: the residue-product kernel sums the three digit
 // products C1 = A1 B1, C2 = A2 B2, C3 = A3 B3 in one accumulator, one pass
@@ -115,11 +117,12 @@ int inv_mod(int a, int p) {  // a^{-1} mod p, gcd(a, p) = 1
   return t < 0 ? t + p : t;
 }
 
-std::vector<int> modulus_list(int N, bool hybrid) {
+std::vector<int> modulus_list(int N, int list) {
   std::vector<int> cand;
-  if (hybrid)
+  if (list == OZ2_MODULI_HYBRID)
     for (int s = 2; s <= 33; ++s) cand.push_back(s * s);
-  for (int v = 2; v <= 513; ++v) cand.push_back(v);
+  const int top = list == OZ2_MODULI_INT8 ? 256 : 513;
+  for (int v = 2; v <= top; ++v) cand.push_back(v);
   std::sort(cand.begin(), cand.end(), [](int a, int b) { return a > b; });
   cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
   std::vector<int> out;
@@ -142,10 +145,11 @@ int sym(int64_t x, int p) {
 
 bool build_tables(int N, int list, Tables *t) {
   if (N < 1 || N > kMaxN) return false;
-  if (list != OZ2_MODULI_HYBRID && list != OZ2_MODULI_KARATSUBA) return false;
-  const bool hybrid = list == OZ2_MODULI_HYBRID;
+  if (list != OZ2_MODULI_HYBRID && list != OZ2_MODULI_KARATSUBA && list != OZ2_MODULI_INT8)
+    return false;
+  const bool hybrid = list == OZ2_MODULI_HYBRID, int8 = list == OZ2_MODULI_INT8;
   memset(t, 0, sizeof(*t));
-  std::vector<int> p = modulus_list(N, hybrid);
+  std::vector<int> p = modulus_list(N, list);
   if ((int)p.size() != N) return false;
   t->N = N;
   int slice = 0;
@@ -155,14 +159,16 @@ bool build_tables(int N, int list, Tables *t) {
     // squares must form a prefix of the list (the kernels index them first)
     if (square && l != t->nsq) return false;
     if (square) t->nsq = l + 1;
+    if (!square && !int8) t->nka += 1;
     t->p[l] = p[l];
-    t->kind[l] = square ? 0 : 1;
-    t->s[l] = square ? r : 16;
+    t->kind[l] = square ? 0 : (int8 ? 2 : 1);
+    t->s[l] = square ? r : (int8 ? 1 : 16);
     t->slice0[l] = slice;
-    slice += square ? 2 : 3;
+    slice += square ? 2 : (int8 ? 1 : 3);
     t->inv_p[l] = 1.0f / (float)p[l];
+    t->inv_pd[l] = 1.0 / (double)p[l];
     t->inv_s[l] = 1.0f / (float)t->s[l];
-    if (!square) {
+    if (!square && !int8) {
       const int q = p[l];
       if (gcd_int(q, 15) == 1) {          // passes C1, C3, C2
         t->kfold[l][0] = sym(15, q);
@@ -181,9 +187,6 @@ bool build_tables(int N, int list, Tables *t) {
     uint64_t v = 1;
     for (int e = 0; e < kPowT; ++e) {
       t->pw[l][e] = (uint16_t)v;
-      if (e == 16) t->k16[l] = (int32_t)v;
-      if (e == 32) t->k32[l] = (int32_t)v;
-      if (e == 48) t->k48[l] = (int32_t)v;
       v = (v * 2) % p[l];
     }
   }

@@ -141,9 +141,12 @@ def check_stages(r: Run, opA, opB, N, st=None, mode="accurate", moduli="hybrid")
     SB = r.slices("B")
     sl = 0
     for pm in st["per_modulus"]:
+        # FP8 digits as E4M3 codes; INT8 residues as two's-complement bytes
+        enc = ((lambda x: x.astype(np.int8).view(np.uint8)) if pm["kind"] == "int8"
+               else ref.e4m3_encode_exact)
         for dA, dB in zip(pm["dA"], pm["dB"]):
-            assert np.array_equal(SA[sl, :m, :k], ref.e4m3_encode_exact(dA)), f"A slice {sl}"
-            assert np.array_equal(SB[sl, :n, :k], ref.e4m3_encode_exact(dB.T)), f"B slice {sl}"
+            assert np.array_equal(SA[sl, :m, :k], enc(dA)), f"A slice {sl}"
+            assert np.array_equal(SB[sl, :n, :k], enc(dB.T)), f"B slice {sl}"
             assert not SA[sl, m:].any() and not SA[sl, :, k:].any(), f"A slice {sl} padding"
             assert not SB[sl, n:].any() and not SB[sl, :, k:].any(), f"B slice {sl} padding"
             sl += 1

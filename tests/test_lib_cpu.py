@@ -176,7 +176,7 @@ def test_karatsuba_only_list_host_only():
     assert oz.ozaki2_get_moduli_list() == oz.MODULI_HYBRID
     assert oz.ozaki2_set_moduli_list(5) == -1
     with pytest.raises(ValueError):
-        oz.ozaki2_set_moduli_list("int8")
+        oz.ozaki2_set_moduli_list("binary")
     w_h = oz.ozaki2_workspace_bytes(300, 200, 700, 13)
     assert oz.ozaki2_set_moduli_list("karatsuba") == 0
     try:
@@ -191,3 +191,17 @@ def test_karatsuba_only_list_host_only():
     finally:
         oz.ozaki2_set_moduli_list("hybrid")
     assert oz.ozaki2_workspace_bytes(300, 200, 700, 13) == w_h
+
+
+def test_int8_list_host_only():
+    assert oz.ozaki2_set_moduli_list("int8") == 0
+    try:
+        assert oz.ozaki2_get_moduli_list() == oz.MODULI_INT8
+        for N in range(1, 34):
+            p, kinds = oz.ozaki2_moduli(N)
+            assert p == [q for q, _, _ in ref.moduli_table(N, "int8")]
+            assert kinds == [2] * N
+            _, pads = oz.ozaki2_workspace_layout(300, 200, 700, N)
+            assert pads["M"] == N
+    finally:
+        oz.ozaki2_set_moduli_list("hybrid")

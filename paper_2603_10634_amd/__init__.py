@@ -19,8 +19,8 @@ __all__ = [
     "ozaki2_status_string", "ozaki2_dgemm_batched", "ozaki2_workspace_bytes_batched",
     "ozaki2_set_graph", "ozaki2_set_autotune", "ozaki2_get_schedule", "ozaki2_set_mode",
     "ozaki2_get_mode", "MODE_ACCURATE", "MODE_FAST", "ozaki2_set_moduli_list",
-    "ozaki2_get_moduli_list", "MODULI_HYBRID", "MODULI_KARATSUBA", "MODULI_INT8", "dgemm",
-    "dgemm_batched",
+    "ozaki2_get_moduli_list", "MODULI_HYBRID", "MODULI_KARATSUBA", "MODULI_INT8",
+    "ozaki2_set_blocking", "ozaki2_get_blocking", "dgemm", "dgemm_batched",
     "LIB_PATH", "HEADER_PATH", "header_functions",
 ]
 
@@ -89,6 +89,8 @@ def lib() -> ctypes.CDLL:
         "ozaki2_get_mode": (ctypes.c_int, []),
         "ozaki2_set_moduli_list": (ctypes.c_int, [ctypes.c_int]),
         "ozaki2_get_moduli_list": (ctypes.c_int, []),
+        "ozaki2_set_blocking": (ctypes.c_int, [_i64, _i64]),
+        "ozaki2_get_blocking": (ctypes.c_int, [_p64, _p64]),
         "ozaki2_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     }
     for name, (res, args) in sig.items():
@@ -266,6 +268,16 @@ def ozaki2_set_moduli_list(moduli) -> int:
 
 def ozaki2_get_moduli_list() -> int:
     return lib().ozaki2_get_moduli_list()
+
+
+def ozaki2_set_blocking(m_blk: int, n_blk: int) -> int:
+    return lib().ozaki2_set_blocking(m_blk, n_blk)
+
+
+def ozaki2_get_blocking() -> tuple[int, int]:
+    a, b = ctypes.c_int64(0), ctypes.c_int64(0)
+    lib().ozaki2_get_blocking(ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
 
 
 class _ModeScope:

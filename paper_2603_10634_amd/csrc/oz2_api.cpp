@@ -41,6 +41,7 @@ struct ThreadState {
   int last_schedule = -1;                  // schedule of the last batched call
   int mode = OZ2_MODE_ACCURATE;            // scaling mode (Section III-E)
   int list = OZ2_MODULI_HYBRID;            // modulus list (Sections III-B, III-D)
+  int64_t blk_m = 0, blk_n = 0;            // m/n blocking of ozaki2_dgemm (0: none)
   hipStream_t cap_stream = nullptr;        // private stream used only for capture
   int cap_dev = -1;
   std::list<std::unique_ptr<Plan>> plans;  // cached plans, most recent first
@@ -61,6 +62,7 @@ int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
   int64_t mp, np, kp;
+  int64_t mbp, nbp;  // padded block extents (mp, np when the call is not blocked)
   int M;
   size_t off[17];
   size_t total;
@@ -77,15 +79,21 @@ const Tables *host_tables(int N, int list) {
 }
 
 // Offsets of every workspace buffer (256-byte aligned) for N moduli of the
-// calling thread's list.  The zero-initialised per-line vectors come first
-// and contiguously so one fill clears them.
-bool make_layout(int64_t m, int64_t n, int64_t k, int N, Layout *L) {
+// calling thread's list, for blocks of at most mb x nb outputs (0: whole
+// extent).  The per-line vectors and the bound operands cover the whole
+// problem; digit slices and residue planes cover one block.  The
+// zero-initialised per-line vectors come first and contiguously so one fill
+// clears them.
+bool make_layout(int64_t m, int64_t n, int64_t k, int N, Layout *L, int64_t mb = 0,
+                 int64_t nb = 0) {
   const Tables *ht = host_tables(N, g_ts.list);
   if (!ht) return false;
   const Tables &t = *ht;
   L->mp = round_up(m > 0 ? m : 1, kPad);
   L->np = round_up(n > 0 ? n : 1, kPad);
   L->kp = round_up(k > 0 ? k : 1, kPad);
+  L->mbp = mb > 0 && mb < L->mp ? mb : L->mp;
+  L->nbp = nb > 0 && nb < L->np ? nb : L->np;
   L->M = t.M;
   const int64_t lines = L->mp + L->np;
   size_t o = 0;
@@ -105,9 +113,9 @@ bool make_layout(int64_t m, int64_t n, int64_t k, int N, Layout *L) {
   take(2, sizeof(int32_t) * lines);            // e
   take(3, (size_t)(L->mp * L->kp));            // Abar
   take(4, (size_t)(L->np * L->kp));            // Bbar
-  take(5, (size_t)t.M * L->mp * L->kp);        // A slices
-  take(6, (size_t)t.M * L->np * L->kp);        // B slices
-  take(7, sizeof(int16_t) * (size_t)N * L->mp * L->np);  // planes
+  take(5, (size_t)t.M * L->mbp * L->kp);       // A slices (one block)
+  take(6, (size_t)t.M * L->nbp * L->kp);       // B slices
+  take(7, sizeof(int16_t) * (size_t)N * L->mbp * L->nbp);  // planes
   L->off[8] = L->off[12];
   L->off[9] = L->off[11];
   L->off[16] = L->off[14];
@@ -205,6 +213,7 @@ Problem make_problem(char transA, char transB, int64_t m, int64_t n, int64_t k, 
   w.planes = (int16_t *)(ws + L.off[7]);
   w.zero = (uint32_t *)(ws + L.off[10]);
   w.zero_words = (int64_t)((L.off[15] - L.off[10]) / 4);
+  w.lineB = L.mp;
   P.tab = dt;
   P.alpha = alpha;
   P.beta = beta;
@@ -236,10 +245,10 @@ struct Marks {
     }                                 \
   } while (0)
 
-// The launch sequence of one problem (workflow steps 1-10 of Section IV-B).
-// Fast mode replaces the bound operands, bound product and its decision by
-// the exact line norms of the bound operands (Section III-E).
-int enqueue_single(const Problem &P, hipStream_t st, Marks &mark) {
+// Workflow steps 1-3 of Section IV-B for one problem: maxima, bound, scale
+// exponents.  Fast mode replaces the bound operands, bound product and its
+// decision by the exact line norms of the bound operands (Section III-E).
+int enqueue_scaling(const Problem &P, hipStream_t st, Marks &mark) {
   const bool fast = P.mode == OZ2_MODE_FAST;
   mark();
   // step 1: mu', nu' and the FP8 bound operands (fast mode: their line norms)
@@ -255,9 +264,16 @@ int enqueue_single(const Problem &P, hipStream_t st, Marks &mark) {
     for (int f : {kFamDecide, kFamFixup}) OZ2_TRY(launch_scale_family(f, &P, nullptr, st));
   OZ2_TRY(launch_scale_family(kFamFinal, &P, nullptr, st));
   mark();
+  return OZ2_SUCCESS;
+}
+
+// Workflow steps 4-10 for one problem or block; res_a / res_b select which
+// operand's residues are (re)computed.
+int enqueue_products(const Problem &P, hipStream_t st, Marks &mark, bool res_a = true,
+                     bool res_b = true) {
   // steps 4-6: integers, residues and FP8 digits
-  OZ2_TRY(launch_quant_family(kFamResA, &P, nullptr, st));
-  OZ2_TRY(launch_quant_family(kFamResB, &P, nullptr, st));
+  if (res_a) OZ2_TRY(launch_quant_family(kFamResA, &P, nullptr, st));
+  if (res_b) OZ2_TRY(launch_quant_family(kFamResB, &P, nullptr, st));
   mark();
   // steps 7-8: residue products and their reduction modulo p, per k chunk
   for (int c = 0; c < num_chunks(P.g.kp); ++c)
@@ -267,6 +283,56 @@ int enqueue_single(const Problem &P, hipStream_t st, Marks &mark) {
   // steps 9-10: CRT and inverse scaling
   OZ2_TRY(launch_crt_family(&P, nullptr, P.limbs, st));
   mark();
+  return OZ2_SUCCESS;
+}
+
+// The launch sequence of one problem (workflow steps 1-10 of Section IV-B).
+int enqueue_single(const Problem &P, hipStream_t st, Marks &mark) {
+  const int r = enqueue_scaling(P, st, mark);
+  return r != OZ2_SUCCESS ? r : enqueue_products(P, st, mark);
+}
+
+// Block (i0.., j0..) of mi x nj outputs of problem P: its operand lines, its
+// C entries, and the per-line vectors of P at those lines; digit slices and
+// planes are the block buffers of P's workspace.
+Problem block_problem(const Problem &P, int64_t i0, int64_t j0, int64_t mi, int64_t nj) {
+  Problem B = P;
+  B.A.ptr += i0 * P.A.sr;
+  B.A.lines = mi;
+  B.B.ptr += j0 * P.B.sr;
+  B.B.lines = nj;
+  B.g.m = mi;
+  B.g.n = nj;
+  B.g.mp = round_up(mi, kPad);
+  B.g.np = round_up(nj, kPad);
+  B.w.shift += i0;
+  B.w.E += i0;
+  B.w.e += i0;
+  B.w.flags += i0;
+  B.w.amax += i0;
+  B.w.lineB = P.g.mp + j0 - i0;
+  B.C += i0 + j0 * P.ldc;
+  return B;
+}
+
+// m/n-blocked launch sequence (the blocking the paper recommends for the
+// working memory, Section IV-C): the scale exponents of the whole problem
+// first, so that every block is bit-identical to the unblocked call, then
+// per block of mb x nb outputs the residues, products and CRT.  A's residues
+// are computed once per block row; B's once per block column when there is
+// a single block row, else again for every block.
+int enqueue_blocked(const Problem &P, int64_t mb, int64_t nb, hipStream_t st) {
+  Marks none{nullptr, st, false};
+  int r = enqueue_scaling(P, st, none);
+  if (r != OZ2_SUCCESS) return r;
+  const int64_t m = P.g.m, n = P.g.n;
+  const int64_t nJ = (n + nb - 1) / nb;
+  for (int64_t i0 = 0; i0 < m; i0 += mb)
+    for (int64_t j0 = 0; j0 < n; j0 += nb) {
+      const Problem B = block_problem(P, i0, j0, std::min(mb, m - i0), std::min(nb, n - j0));
+      r = enqueue_products(B, st, none, j0 == 0, i0 == 0 || nJ > 1);
+      if (r != OZ2_SUCCESS) return r;
+    }
   return OZ2_SUCCESS;
 }
 
@@ -548,7 +614,7 @@ int ozaki2_moduli(int num_moduli, int32_t *p, int32_t *kinds) {
 size_t ozaki2_workspace_bytes(int64_t m, int64_t n, int64_t k, int num_moduli) {
   if (m < 0 || n < 0 || k < 0 || num_moduli < 1 || num_moduli > OZ2_MAX_MODULI) return 0;
   Layout L;
-  if (!make_layout(m, n, k, num_moduli, &L)) return 0;
+  if (!make_layout(m, n, k, num_moduli, &L, g_ts.blk_m, g_ts.blk_n)) return 0;
   return L.total;
 }
 
@@ -693,7 +759,7 @@ int ozaki2_dgemm(char transA, char transB, int64_t m, int64_t n, int64_t k, doub
   if (k > OZ2_MAX_K) return OZ2_ERR_UNSUPPORTED;
 
   Layout L;
-  if (!make_layout(m, n, k, num_moduli, &L)) return OZ2_ERR_UNSUPPORTED;
+  if (!make_layout(m, n, k, num_moduli, &L, ts.blk_m, ts.blk_n)) return OZ2_ERR_UNSUPPORTED;
   hipError_t herr = hipSuccess;
   const Tables *dt = device_tables(dev, num_moduli, ts.list, &herr);
   if (!dt) return OZ2_ERR_HIP;
@@ -705,11 +771,15 @@ int ozaki2_dgemm(char transA, char transB, int64_t m, int64_t n, int64_t k, doub
   if (r != OZ2_SUCCESS) return r;
   const Problem P = make_problem(transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
                                  num_moduli, ws, L, dt, ht);
+  const bool blocked = L.mbp < L.mp || L.nbp < L.np;
+  const int64_t mb = L.mbp, nb = L.nbp;
 
   if (ts.graph) {
     KeyBuilder kb;
     kb.add(dev);
     kb.add(P);
+    kb.add(mb);
+    kb.add(nb);
     Plan *plan = find_plan(kb.b);
     if (!plan) {
       std::unique_ptr<Plan> p(new Plan);
@@ -720,10 +790,12 @@ int ozaki2_dgemm(char transA, char transB, int64_t m, int64_t n, int64_t k, doub
       plan = add_plan(std::move(p));
     }
     return run_maybe_graph(plan, dev, st, [&](hipStream_t s) {
+      if (blocked) return enqueue_blocked(plan->single_problem, mb, nb, s);
       Marks none{&ts, s, false};
       return enqueue_single(plan->single_problem, s, none);
     });
   }
+  if (blocked) return enqueue_blocked(P, mb, nb, st);  // not timed
   const bool timed = ts.timing;
   if (timed) {
     r = ensure_events(dev);
@@ -1009,5 +1081,19 @@ int ozaki2_set_moduli_list(int list) {
 }
 
 int ozaki2_get_moduli_list(void) { return g_ts.list; }
+
+int ozaki2_set_blocking(int64_t m_blk, int64_t n_blk) {
+  if (m_blk < 0 || m_blk % kPad) return -1;
+  if (n_blk < 0 || n_blk % kPad) return -2;
+  g_ts.blk_m = m_blk;
+  g_ts.blk_n = n_blk;
+  return OZ2_SUCCESS;
+}
+
+int ozaki2_get_blocking(int64_t *m_blk, int64_t *n_blk) {
+  if (m_blk) *m_blk = g_ts.blk_m;
+  if (n_blk) *n_blk = g_ts.blk_n;
+  return OZ2_SUCCESS;
+}
 
 }  // extern "C"

@@ -76,11 +76,11 @@ __device__ __forceinline__ void crt_entry(const int16_t *__restrict__ planes,
                                           const int32_t *__restrict__ shift,
                                           const uint32_t *__restrict__ flags,
                                           const Tables *__restrict__ tab, int N, int64_t m,
-                                          int64_t mp, int64_t np, double alpha, double beta,
-                                          double *__restrict__ C, int64_t ldc, int64_t i,
-                                          int64_t j) {
+                                          int64_t mp, int64_t np, int64_t lineB, double alpha,
+                                          double beta, double *__restrict__ C, int64_t ldc,
+                                          int64_t i, int64_t j) {
   if (i >= m) return;
-  const bool bad = ((flags[i] | flags[mp + j]) & kNonFinite) != 0;
+  const bool bad = ((flags[i] | flags[lineB + j]) & kNonFinite) != 0;
   double chat;
   if (bad) {
     chat = __longlong_as_double(0x7FF8000000000000ll);
@@ -181,7 +181,7 @@ __device__ __forceinline__ void crt_entry(const int16_t *__restrict__ planes,
       mag[q] = (uint32_t)d;
       b = d >> 32;
     }
-    const int t = shift[i] + shift[mp + j];
+    const int t = shift[i] + shift[lineB + j];
     chat = scaled_rn<L>(mag, t);
     if (!ge) chat = -chat;
   }
@@ -196,8 +196,8 @@ __global__ __launch_bounds__(256) void k_crt(Problem P1, Group G) {
   const Problem &P = *locate<GROUPED>(P1, G, blockIdx.x, local);
   const int64_t nbx = (P.g.m + 255) / 256;
   const int64_t bx = local % nbx, j = local / nbx;
-  crt_entry<L>(P.w.planes, P.w.shift, P.w.flags, P.tab, P.g.N, P.g.m, P.g.mp, P.g.np, P.alpha,
-               P.beta, P.C, P.ldc, bx * 256 + threadIdx.x, j);
+  crt_entry<L>(P.w.planes, P.w.shift, P.w.flags, P.tab, P.g.N, P.g.m, P.g.mp, P.g.np,
+               P.w.lineB, P.alpha, P.beta, P.C, P.ldc, bx * 256 + threadIdx.x, j);
 }
 
 __global__ void k_scal(int64_t m, double beta, double *__restrict__ C, int64_t ldc) {

@@ -76,6 +76,8 @@ struct Work {
   int16_t *planes;
   uint32_t *zero;     // the buffers that start at zero (amax .. amb), contiguous
   int64_t zero_words;
+  int64_t lineB;      // index of op(B)'s first line in the per-line vectors, counted
+                      // from op(A)'s first line (mp, or a block's offset)
 };
 
 // kFixup: the line's exponent comes from the exact bound in rfix.

@@ -388,7 +388,7 @@ __global__ __launch_bounds__(256) void k_residues(Problem P1, Group G) {
   int64_t local;
   const Problem &P = *locate<GROUPED>(P1, G, blockIdx.x, local);
   const Operand &op = SIDE == 0 ? P.A : P.B;
-  const int64_t base = SIDE == 0 ? 0 : P.g.mp;
+  const int64_t base = SIDE == 0 ? 0 : P.w.lineB;
   const Dims d = family_dims(SIDE == 0 ? kFamResA : kFamResB, P, 0);
   const int64_t bx = local % d.x, by = local / d.x;
   residues_tile(op, P.g.kp, SIDE == 0 ? P.g.mp : P.g.np, bx * kQL, by * kQK, P.w.shift + base,

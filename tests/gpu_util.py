@@ -62,11 +62,12 @@ class Run:
 
 
 def run(opA, opB, N, transA="N", transB="N", alpha=1.0, beta=0.0, Cin=None,
-        pad=(0, 0, 0), keep_ws=False, stream=None, mode="accurate", moduli="hybrid"):
+        pad=(0, 0, 0), keep_ws=False, stream=None, mode="accurate", moduli="hybrid",
+        blocking=(0, 0)):
     """Column-major ozaki2_dgemm on op(A) (m x k) and op(B) (k x n) given as
     numpy arrays, in the given scaling mode and modulus list; leading-dimension
     padding is filled with NaN (A, B) or 7.0 (C) so reads or writes outside
-    the views show."""
+    the views show.  `blocking` = (m_blk, n_blk) runs the call m/n-blocked."""
     m, k = opA.shape
     n = opB.shape[1]
     Ab, lda = to_colmajor(opA, transA, ld=(max(1, m) if transA in "Nn" else max(1, k)) + pad[0])
@@ -79,11 +80,13 @@ def run(opA, opB, N, transA="N", transB="N", alpha=1.0, beta=0.0, Cin=None,
     tB = torch.from_numpy(Bb.copy()).to(dev)
     tC = torch.from_numpy(Cb.copy()).to(dev)
     assert oz.ozaki2_set_moduli_list(moduli) == 0
+    assert oz.ozaki2_set_blocking(*blocking) == 0
     try:
         return _run_list(tA, tB, tC, transA, transB, m, n, k, alpha, lda, ldb, beta, ldc, N,
                          keep_ws, stream, mode, dev)
     finally:
         oz.ozaki2_set_moduli_list("hybrid")
+        oz.ozaki2_set_blocking(0, 0)
 
 
 def _run_list(tA, tB, tC, transA, transB, m, n, k, alpha, lda, ldb, beta, ldc, N, keep_ws,

@@ -205,3 +205,30 @@ def test_int8_list_host_only():
             assert pads["M"] == N
     finally:
         oz.ozaki2_set_moduli_list("hybrid")
+
+
+def test_blocking_setting_and_workspace():
+    assert oz.ozaki2_get_blocking() == (0, 0)
+    assert oz.ozaki2_set_blocking(100, 256) == -1
+    assert oz.ozaki2_set_blocking(256, -256) == -2
+    assert oz.ozaki2_get_blocking() == (0, 0)
+    full = oz.ozaki2_workspace_bytes(16384, 16384, 16384, 12)
+    assert oz.ozaki2_set_blocking(4096, 4096) == 0
+    try:
+        assert oz.ozaki2_get_blocking() == (4096, 4096)
+        blk = oz.ozaki2_workspace_bytes(16384, 16384, 16384, 12)
+        # per-line vectors and bound operands for the whole problem, slices
+        # and planes for one 4096 x 4096 block
+        M, N, kp = 30, 12, 16384
+        lines = 2 * 16384
+        want_core = 2 * 16384 * kp + M * 2 * 4096 * kp + 2 * N * 4096 * 4096
+        assert want_core < blk < want_core + 64 * lines + 4096
+        assert full > 4 * blk
+        # a problem that fits one block is not blocked
+        assert oz.ozaki2_workspace_bytes(1000, 4000, 300, 12) == \
+            oz.ozaki2_workspace_bytes(1000, 4000, 300, 12)
+        small = oz.ozaki2_workspace_bytes(1000, 4000, 300, 12)
+    finally:
+        oz.ozaki2_set_blocking(0, 0)
+    assert oz.ozaki2_workspace_bytes(1000, 4000, 300, 12) == small
+    assert oz.ozaki2_workspace_bytes(16384, 16384, 16384, 12) == full

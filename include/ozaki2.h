@@ -166,9 +166,12 @@ int ozaki2_moduli(int num_moduli, int32_t *p, int32_t *kinds);
  *   off[0] int32  [m_pad + n_pad]  log2 of mu_i / nu_j (shift applied to each line)
  *   off[1] int32  [m_pad + n_pad]  E with ufp(max|x|) = 2^E per line (0 for zero lines)
  *   off[2] int32  [m_pad + n_pad]  scale exponent e_i / f_j (log2(mu/mu'))
- *   off[3] uint8  [m_pad x k_pad]  Abar, row i at i*k_pad (E4M3 codes; accurate mode)
- *   off[4] uint8  [n_pad x k_pad]  Bbar, column j of op(B) at j*k_pad (accurate mode)
- *   off[5] uint8  [M x m_pad x k_pad]  digit slices of A' (slice order below)
+ *   off[3] uint8  [m_pad x k_pad]  Abar (E4M3 codes; accurate mode), k-blocked:
+ *          element (row i, k h) at (h / 64) * 64 m_pad + 64 i + h % 64
+ *   off[4] uint8  [n_pad x k_pad]  Bbar (column j of op(B) as line j; accurate mode),
+ *          k-blocked with n_pad lines
+ *   off[5] uint8  [M x m_pad x k_pad]  digit slices of A' (slice order below), each
+ *          k-blocked like Abar (INT8 residues as two's-complement bytes)
  *   off[6] uint8  [M x n_pad x k_pad]  digit slices of B'
  *   off[7] int16  [N x n_pad x m_pad]  C'_l, entry (i, j) at l*n_pad*m_pad + j*m_pad + i
  *   off[8] uint32 [m_pad + n_pad]  FP32 bits of the bound product's line maxima

@@ -11,7 +11,8 @@
 //  * INT8 arm (Section II): one product of the INT8 residues per modulus on
 //    v_mfma_i32_32x32x32_i8, INT32 accumulation, the same wide loop.
 //
-// Layout: operand slices are K-contiguous (line r's k bytes at r * kp).  The
+// Layout: operand slices are k-blocked (see kblocked): one 64-k stage of a
+// tile of 256 consecutive lines is 16 KB of contiguous memory.  The
 // MFMA "A" operand is fed from B's slices (rows j) and the "B" operand from
 // A's slices (rows i), so the accumulator holds D[j][i] = (A'B')_ij and each
 // lane owns consecutive i of C's column-major planes.
@@ -21,9 +22,11 @@
 // through an LDS ring of S stages filled by direct global-to-LDS loads
 // (global_load_lds_dwordx4) issued S - 1 stages ahead, so HBM/L2 latency
 // hides behind S - 1 stages of MFMAs; no VGPRs stage the operands.  LDS rows
-// are 64 B with the four 16 B chunks of row r XOR-swizzled by
-// ((r >> 1) ^ (r >> 3)) & 3, which keeps the fragment reads (ds_read_b128)
-// free of bank conflicts.
+// are 64 B with the four 16 B chunks of row r XOR-swizzled by (r >> 2) & 3,
+// which keeps the fragment reads (ds_read_b128) free of bank conflicts: gfx950
+// serves a ds_read_b128 in passes of lanes 8p..8p+7 with 32+8p..32+8p+7, four
+// cycles per instruction when each pass touches 16 different 16-byte bank
+// groups (measured; the swizzle ((r >> 1) ^ (r >> 3)) & 3 took eight).
 #include <string.h>
 
 #include "oz2_internal.h"
@@ -46,7 +49,7 @@ constexpr int ASZ = TI * ROWB;           // bytes of one A-side slice tile
 constexpr int LDS_RING = 147456;         // 144 KB: 3 stages of 2 slices or 6 of 1
 static_assert(TI == kGemmTI && TJ == kGemmTJ && BK == kGemmBK, "tile shape");
 
-__device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
+__device__ __forceinline__ int swz(int r) { return (r >> 2) & 3; }
 
 // s_waitcnt with only the vector-memory counter constrained (gfx9 encoding:
 // vmcnt[3:0], expcnt[6:4], lgkmcnt[11:8], vmcnt[5:4] at [15:14])
@@ -136,12 +139,15 @@ __device__ __forceinline__ uint32_t lds_offset(const uint8_t *p) {
 // instruction for tile rows 16q..16q+15 (q = wave + 4u) has lane L fetch row
 // 16q + L/4, logical chunk (L & 3) ^ swz(row), which lands at physical chunk
 // L & 3 of the row.  ob[u] serve the 256-row B side, oa[u] the 128-row A side.
+// In the k-blocked layout the 16 rows of one load are 1 KB of contiguous
+// memory; sB / sA are the bytes of one 64-k block of all lines of a side.
 struct DmaOffsets {
   uint32_t ob[4], oa[2];
   uint32_t lds_wave;  // 1024 * wave: this wave's first 1 KB in each tile
+  int64_t sB, sA;
 };
 
-__device__ __forceinline__ DmaOffsets dma_offsets(int64_t kp) {
+__device__ __forceinline__ DmaOffsets dma_offsets(int64_t rowsB, int64_t rowsA) {
   DmaOffsets d;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -149,18 +155,20 @@ __device__ __forceinline__ DmaOffsets dma_offsets(int64_t kp) {
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int r = 16 * (wave + 4 * u) + rsub;
-    d.ob[u] = (uint32_t)(r * kp) + 16u * (uint32_t)(pc ^ swz(r));
+    d.ob[u] = (uint32_t)(r * 64) + 16u * (uint32_t)(pc ^ swz(r));
     if (u < 2) d.oa[u] = d.ob[u];
   }
   d.lds_wave = 1024u * (uint32_t)wave;
+  d.sB = rowsB * 64;
+  d.sA = rowsA * 64;
   return d;
 }
 
 // Direct-to-LDS load number `idx` (0 .. 6 NS - 1) of one stage (64 k) of NS
 // slices per side: per slice four 1 KB loads of the 256-row B-side tile and
 // two of the 128-row A-side tile, each filling 16 rows.  `slot` is the LDS
-// byte address of the stage's ring slot; gB[s] / gA[s] + kofs are the
-// wave-uniform bases of the stage in global memory.
+// byte address of the stage's ring slot; gB[s] / gA[s] point at the tile's
+// first line in k block 0, and the stage starts at k = kofs.
 template <int NS>
 __device__ __forceinline__ void dma_one(int idx, const uint8_t *const *gB,
                                         const uint8_t *const *gA, const DmaOffsets &d,
@@ -168,9 +176,9 @@ __device__ __forceinline__ void dma_one(int idx, const uint8_t *const *gB,
   const int s = idx / 6, t = idx % 6;
   const uint32_t w = slot + d.lds_wave;
   if (t < 4)
-    dma16(gB[s] + kofs, d.ob[t], w + s * BSZ + t * 4096);
+    dma16(gB[s] + (kofs >> 6) * d.sB, d.ob[t], w + s * BSZ + t * 4096);
   else
-    dma16(gA[s] + kofs, d.oa[t - 4], w + NS * BSZ + s * ASZ + (t - 4) * 4096);
+    dma16(gA[s] + (kofs >> 6) * d.sA, d.oa[t - 4], w + NS * BSZ + s * ASZ + (t - 4) * 4096);
 }
 
 // The loads of a stage are issued in four parts; part q is loads
@@ -296,15 +304,15 @@ __device__ __forceinline__ void stage_iter(int j, int nk, const uint8_t *const *
 
 template <int NS = 2>
 __device__ __forceinline__ void kloop(const uint8_t *const *gB, const uint8_t *const *gA,
-                                      int64_t kp, int64_t kbeg, int nk, uint8_t *lds,
-                                      v16f (&acc0)[4][2], v16f (&acc1)[4][2]) {
+                                      int64_t rowsB, int64_t rowsA, int64_t kbeg, int nk,
+                                      uint8_t *lds, v16f (&acc0)[4][2], v16f (&acc1)[4][2]) {
   constexpr int STAGE = NS * (BSZ + ASZ);
   constexpr int S = NS == 2 ? 3 : 6;
   constexpr int L = 6 * NS;
   static_assert(S * STAGE <= LDS_RING, "LDS ring");
   const int wave = threadIdx.x >> 6;
   const int wj = wave >> 1, wi = wave & 1;
-  const DmaOffsets d = dma_offsets(kp);
+  const DmaOffsets d = dma_offsets(rowsB, rowsA);
   const uint32_t ring = lds_offset(lds);
   // prologue: stages 0 .. S - 2 and part 0 of stage S - 1
 #pragma unroll
@@ -390,15 +398,15 @@ __device__ __forceinline__ void square_tile(const uint8_t *Asl, const uint8_t *B
   resident_ptr(planes, planes);
   resident(accumulate, accumulate, accumulate, accumulate);
   const int64_t sA = mp * kp, sB = np * kp;
-  const uint8_t *A0 = Asl + (int64_t)sl0 * sA + i0 * kp;
-  const uint8_t *B0 = Bsl + (int64_t)sl0 * sB + j0 * kp;
+  const uint8_t *A0 = Asl + (int64_t)sl0 * sA + i0 * 64;
+  const uint8_t *B0 = Bsl + (int64_t)sl0 * sB + j0 * 64;
 
   v16f acc0[4][2], acc1[4][2];
   zero_acc(acc0);
   zero_acc(acc1);
   const uint8_t *gB[2] = {B0, B0 + sB};
   const uint8_t *gA[2] = {A0, A0 + sA};
-  kloop(gB, gA, kp, kbeg, nk, lds, acc0, acc1);
+  kloop(gB, gA, np, mp, kbeg, nk, lds, acc0, acc1);
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wj = wave >> 1, wi = wave & 1;
@@ -439,9 +447,9 @@ __device__ __forceinline__ void dma_one_w(int idx, const uint8_t *gB, const uint
                                           const DmaOffsets &d, int64_t kofs, uint32_t slot) {
   const uint32_t w = slot + d.lds_wave;
   if (idx < 4)
-    dma16(gB + kofs, d.ob[idx], w + idx * 4096);
+    dma16(gB + (kofs >> 6) * d.sB, d.ob[idx], w + idx * 4096);
   else
-    dma16(gA + kofs, d.ob[idx - 4], w + BSZ + (idx - 4) * 4096);
+    dma16(gA + (kofs >> 6) * d.sA, d.ob[idx - 4], w + BSZ + (idx - 4) * 4096);
 }
 
 template <int Q>
@@ -518,12 +526,13 @@ __device__ __forceinline__ void stage_iter_w(int j, int nk, const uint8_t *gB, c
 // acc += A B over nk stages of 64 k for one wide tile; gB / gA point at row
 // j0 / i0 of one B-side / A-side slice.
 template <class ACC>
-__device__ __forceinline__ void kloop_w(const uint8_t *gB, const uint8_t *gA, int64_t kp,
-                                        int64_t kbeg, int nk, uint8_t *lds, ACC (&acc)[4][4]) {
+__device__ __forceinline__ void kloop_w(const uint8_t *gB, const uint8_t *gA, int64_t rowsB,
+                                        int64_t rowsA, int64_t kbeg, int nk, uint8_t *lds,
+                                        ACC (&acc)[4][4]) {
   constexpr int L = 8;
   const int wave = threadIdx.x >> 6;
   const int wj = wave >> 1, wi = wave & 1;
-  const DmaOffsets d = dma_offsets(kp);
+  const DmaOffsets d = dma_offsets(rowsB, rowsA);
   const uint32_t ring = lds_offset(lds);
 #pragma unroll
   for (int t = 0; t < SW - 1; ++t)
@@ -609,8 +618,8 @@ __device__ __forceinline__ void karatsuba_tile_w(const uint8_t *Asl, const uint8
   resident_ptr(planes, planes);
   resident(accumulate, accumulate, accumulate, accumulate);
   const int64_t sA = mp * kp, sB = np * kp;
-  const uint8_t *A0 = Asl + (int64_t)sl0 * sA + i0 * kp;
-  const uint8_t *B0 = Bsl + (int64_t)sl0 * sB + j0 * kp;
+  const uint8_t *A0 = Asl + (int64_t)sl0 * sA + i0 * 64;
+  const uint8_t *B0 = Bsl + (int64_t)sl0 * sB + j0 * 64;
 
   v16f acc[4][4];
 #pragma unroll
@@ -622,11 +631,11 @@ __device__ __forceinline__ void karatsuba_tile_w(const uint8_t *Asl, const uint8
 
   pin_agpr(acc);
   const int third = 3 - second;
-  kloop_w(B0, A0, kp, kbeg, nk, lds, acc);                              // X = C1
+  kloop_w(B0, A0, np, mp, kbeg, nk, lds, acc);                              // X = C1
   fold_w(acc, mul_a, p, inv);
-  kloop_w(B0 + second * sB, A0 + second * sA, kp, kbeg, nk, lds, acc);  // + Y
+  kloop_w(B0 + second * sB, A0 + second * sA, np, mp, kbeg, nk, lds, acc);  // + Y
   fold_w(acc, mul_b, p, inv);
-  kloop_w(B0 + third * sB, A0 + third * sA, kp, kbeg, nk, lds, acc);    // + Z
+  kloop_w(B0 + third * sB, A0 + third * sA, np, mp, kbeg, nk, lds, acc);    // + Z
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wj = wave >> 1, wi = wave & 1;
@@ -664,8 +673,8 @@ __device__ __forceinline__ void int8_tile_w(const uint8_t *Asl, const uint8_t *B
   resident(sl0, p, __float_as_int(inv), p);
   resident_ptr(planes, planes);
   resident(accumulate, accumulate, accumulate, accumulate);
-  const uint8_t *A0 = Asl + (int64_t)sl0 * mp * kp + i0 * kp;
-  const uint8_t *B0 = Bsl + (int64_t)sl0 * np * kp + j0 * kp;
+  const uint8_t *A0 = Asl + (int64_t)sl0 * mp * kp + i0 * 64;
+  const uint8_t *B0 = Bsl + (int64_t)sl0 * np * kp + j0 * 64;
 
   v16i acc[4][4];
 #pragma unroll
@@ -675,7 +684,7 @@ __device__ __forceinline__ void int8_tile_w(const uint8_t *Asl, const uint8_t *B
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[tj][ti][v] = 0;
   pin_agpr(acc);
-  kloop_w(B0, A0, kp, kbeg, nk, lds, acc);
+  kloop_w(B0, A0, np, mp, kbeg, nk, lds, acc);
   pin_agpr(acc);
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -734,8 +743,8 @@ __global__ __launch_bounds__(256, 1) void k_residue_gemm(Problem P1, Group G, in
 // Line maxima of one 256 x 256 tile of the bound product Abar Bbar (wide
 // single-product loop; FP32 accumulation in one fixed k order, so the result
 // does not depend on the tiling).
-__device__ __forceinline__ void bound_tile(const uint8_t *Abar, const uint8_t *Bbar, int64_t kp,
-                                           int nk, uint32_t *__restrict__ rmaxA,
+__device__ __forceinline__ void bound_tile(const uint8_t *Abar, const uint8_t *Bbar, int64_t mp,
+                                           int64_t np, int nk, uint32_t *__restrict__ rmaxA,
                                            uint32_t *__restrict__ rmaxB, int64_t i0, int64_t j0,
                                            uint8_t *lds) {
   v16f acc[4][4];
@@ -747,7 +756,7 @@ __device__ __forceinline__ void bound_tile(const uint8_t *Abar, const uint8_t *B
       for (int v = 0; v < 16; ++v) acc[tj][ti][v] = 0.0f;
   resident_ptr(rmaxA, rmaxB);
   pin_agpr(acc);
-  kloop_w(Bbar + j0 * kp, Abar + i0 * kp, kp, 0, nk, lds, acc);
+  kloop_w(Bbar + j0 * 64, Abar + i0 * 64, np, mp, 0, nk, lds, acc);
   pin_agpr(acc);
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -789,9 +798,9 @@ __global__ __launch_bounds__(256, 1) void k_bound_gemm(Problem P1, Group G) {
     const Geometry &g = P.g;
     const Dims d = family_dims(kFamBgemm, P, 0);
     const Dims c = decode_block(d, local);
-    const int64_t mp = uni(g.mp), kp = uni(g.kp);
+    const int64_t mp = uni(g.mp), np = uni(g.np), kp = uni(g.kp);
     uint32_t *rmax = uni(P.w.rmax);
-    bound_tile(uni(P.w.Abar), uni(P.w.Bbar), kp, (int)(kp / BK), rmax, rmax + mp,
+    bound_tile(uni(P.w.Abar), uni(P.w.Bbar), mp, np, (int)(kp / BK), rmax, rmax + mp,
                uni(c.x * TIW), uni(c.y * TJ), lds);
   }
 }

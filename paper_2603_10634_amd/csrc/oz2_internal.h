@@ -103,6 +103,15 @@ struct Problem {
   int32_t mode;        // OZ2_MODE_ACCURATE or OZ2_MODE_FAST (selects the launch sequence)
 };
 
+// Layout of the FP8 bound operands and of every digit slice ("k-blocked"):
+// a buffer of R padded lines and kp padded k holds element (line r, k h) at
+// byte (h / 64) (64 R) + 64 r + h % 64, i.e. blocks of 64 k, each block the
+// 64-byte pieces of all R lines in line order.  One 64-k stage of a tile of
+// consecutive lines is then one contiguous range of memory.
+__host__ __device__ inline int64_t kblocked(int64_t r, int64_t h, int64_t R) {
+  return (h >> 6) * (R << 6) + (r << 6) + (h & 63);
+}
+
 // Tile shapes of the kernels (the block grids below depend on them).
 constexpr int kGemmTI = 128;  // residue / bound products: output rows i per tile
 constexpr int kGemmTJ = 256;  // output columns j per tile

@@ -4,7 +4,7 @@
 //    mode the squared norms of their lines (Cauchy-Schwarz bound),
 //  - the residues of A', B' for every modulus, split into FP8 digits
 //    (eqs. def:A', def:B', CRTmatmul; digit splits of Sections III-B..III-D).
-// Outputs are K-contiguous: line r's k values at r * kp, zero padded.
+// Outputs are k-blocked (kblocked in oz2_internal.h), zero padded.
 #include <string.h>
 
 #include "oz2_device.h"
@@ -132,9 +132,10 @@ __device__ __forceinline__ void stage_tile(const Operand &op, int64_t r0, int64_
 }
 
 // FP8 round-up bound operand of one tile (lines r0.., k h0..).
-__device__ __forceinline__ void bound_operand_tile(const Operand &op, int64_t kp, int64_t r0,
-                                                   int64_t h0, const uint64_t *amax, int32_t *E,
-                                                   uint32_t *flags, uint8_t *bar, double *tile) {
+__device__ __forceinline__ void bound_operand_tile(const Operand &op, int64_t lines_pad,
+                                                   int64_t r0, int64_t h0, const uint64_t *amax,
+                                                   int32_t *E, uint32_t *flags, uint8_t *bar,
+                                                   double *tile) {
   stage_tile(op, r0, h0, tile);
   __syncthreads();
   const int rl = threadIdx.x >> 3, b = threadIdx.x & 7;
@@ -160,7 +161,8 @@ __device__ __forceinline__ void bound_operand_tile(const Operand &op, int64_t kp
     }
     packed[w] = word;
   }
-  *(uint4 *)(bar + r * kp + h0 + b * 16) = make_uint4(packed[0], packed[1], packed[2], packed[3]);
+  *(uint4 *)(bar + kblocked(r, h0 + b * 16, lines_pad)) =
+      make_uint4(packed[0], packed[1], packed[2], packed[3]);
 }
 
 template <bool GROUPED, int SIDE>
@@ -172,8 +174,8 @@ __global__ __launch_bounds__(256) void k_bound_operand(Problem P1, Group G) {
   const int64_t base = SIDE == 0 ? 0 : P.g.mp;
   const Dims d = family_dims(SIDE == 0 ? kFamBarA : kFamBarB, P, 0);
   const int64_t bx = local % d.x, by = local / d.x;
-  bound_operand_tile(op, P.g.kp, bx * kQL, by * kQK, P.w.amax + base, P.w.E + base,
-                     P.w.flags + base, SIDE == 0 ? P.w.Abar : P.w.Bbar, tile);
+  bound_operand_tile(op, SIDE == 0 ? P.g.mp : P.g.np, bx * kQL, by * kQK, P.w.amax + base,
+                     P.w.E + base, P.w.flags + base, SIDE == 0 ? P.w.Abar : P.w.Bbar, tile);
 }
 
 // Fast mode: 2^18 x the squared Euclidean norm of every line of the round-up
@@ -372,7 +374,7 @@ __device__ __forceinline__ void residues_tile(const Operand &op, int64_t kp, int
   in.huge = __any(huge);
 
   const int64_t slice_stride = lines_pad * kp;
-  uint8_t *base = slices + r * kp + h0 + b * 16;
+  uint8_t *base = slices + kblocked(r, h0 + b * 16, lines_pad);
   int l = 0;
   for (; l < nsq; ++l)
     modulus_pass<0>(in, tab, l, base + (int64_t)tab->slice0[l] * slice_stride, slice_stride);

@@ -99,18 +99,19 @@ __device__ __forceinline__ void scale_fixup(const uint8_t *__restrict__ Abar,
     const int64_t L = amb[1 + it / npb];
     const int64_t pb = it % npb;
     const bool rowA = L < mp;
-    const uint8_t *own = rowA ? Abar + L * kp : Bbar + (L - mp) * kp;
+    const uint8_t *own = rowA ? Abar : Bbar;
+    const int64_t rown = rowA ? L : L - mp, nown = rowA ? mp : np;
     const uint8_t *part = rowA ? Bbar : Abar;
     const int64_t npart = rowA ? np : mp;
     uint64_t best = 0;
     for (int z = 0; z < 8; ++z) {
       const int64_t j = pb * 32 + wave * 8 + z;
       if (j >= npart) break;
-      const uint8_t *other = part + j * kp;
       uint64_t sum = 0;
       for (int64_t h = (int64_t)lane * 8; h < kp; h += 512) {
-        const uint64_t a8 = *(const uint64_t *)(own + h);
-        const uint64_t b8 = *(const uint64_t *)(other + h);
+        // 8 bytes at h (h % 8 == 0) sit in one 64-byte piece of the line
+        const uint64_t a8 = *(const uint64_t *)(own + kblocked(rown, h, nown));
+        const uint64_t b8 = *(const uint64_t *)(part + kblocked(j, h, npart));
 #pragma unroll
         for (int z8 = 0; z8 < 8; ++z8) {
           const uint32_t qa = e4m3_q9((uint32_t)(a8 >> (8 * z8)) & 0x7Fu);

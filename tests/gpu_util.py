@@ -42,17 +42,24 @@ class Run:
         """Number of lines whose scale exponent was settled by the exact fix-up."""
         return int(self._vec(10, np.uint32, 1)[0])
 
+    @staticmethod
+    def _unblock(buf, rows, kp):
+        """rows x kp view of a k-blocked buffer: element (r, h) at
+        (h // 64) * 64 rows + 64 r + h % 64."""
+        return buf.reshape(kp // 64, rows, 64).transpose(1, 0, 2).reshape(rows, kp)
+
     def bar(self, which):
         mp, np_, kp = self.pads["mp"], self.pads["np"], self.pads["kp"]
         rows = mp if which == "A" else np_
         o = self.off[3 if which == "A" else 4]
-        return self.ws[o:o + rows * kp].reshape(rows, kp)
+        return self._unblock(self.ws[o:o + rows * kp], rows, kp)
 
     def slices(self, which):
         mp, np_, kp, M = self.pads["mp"], self.pads["np"], self.pads["kp"], self.pads["M"]
         rows = mp if which == "A" else np_
         o = self.off[5 if which == "A" else 6]
-        return self.ws[o:o + M * rows * kp].reshape(M, rows, kp)
+        return np.stack([self._unblock(self.ws[o + q * rows * kp:o + (q + 1) * rows * kp], rows, kp)
+                         for q in range(M)])
 
     def planes(self, N):
         mp, np_ = self.pads["mp"], self.pads["np"]

@@ -85,34 +85,43 @@ __device__ __forceinline__ void crt_entry(const int16_t *__restrict__ planes,
   if (bad) {
     chat = __longlong_as_double(0x7FF8000000000000ll);
   } else {
-    // S = sum_l w_l u_l + floor(P/2), accumulated per limb in 64 bits
-    uint64_t acc[L + 1];
+    // S = sum_l w_l u_l + floor(P/2), accumulated per 32-bit limb in FP64
+    // (full rate on this GPU, unlike 64-bit integer multiply-adds): every
+    // limb sum stays below 2^32 (1 + 33 * 1089) < 2^48, so it is exact
+    double acc[L];
 #pragma unroll
-    for (int q = 0; q < L; ++q) acc[q] = tab->half[q];
-    acc[L] = 0;
+    for (int q = 0; q < L; ++q) acc[q] = (double)tab->half[q];
     const int16_t *pl = planes + j * mp + i;
     const int64_t pstride = mp * np;
     // all N residues are requested before the first is used
     int uu[kMaxN];
+    const int16_t *ql = pl;
 #pragma unroll
     for (int l = 0; l < kMaxN; ++l)
-      if (l < N) uu[l] = pl[l * pstride];
+      if (l < N) {
+        uu[l] = *ql;
+        ql += pstride;
+      }
 #pragma unroll
     for (int l = 0; l < kMaxN; ++l) {
       if (l < N) {
         const int u = uu[l] + (tab->p[l] & (uu[l] >> 31));  // C'_l mod p_l in [0, p_l)
+        const double ud = (double)u;
 #pragma unroll
-        for (int q = 0; q < L; ++q) acc[q] += (uint64_t)tab->w[l][q] * (uint32_t)u;
+        for (int q = 0; q < L; ++q) acc[q] = fma(tab->wd[l][q], ud, acc[q]);
       }
     }
+    // carry-propagate into 32-bit limbs: t = acc + carry < 2^49, split exactly
     uint32_t S[L + 1];
-    uint64_t carry = 0;
+    double carry = 0.0;
 #pragma unroll
-    for (int q = 0; q <= L; ++q) {
-      const uint64_t t = acc[q] + carry;
-      S[q] = (uint32_t)t;
-      carry = t >> 32;
+    for (int q = 0; q < L; ++q) {
+      const double t = acc[q] + carry;
+      const double hi = floor(t * 0x1p-32);
+      S[q] = (uint32_t)fma(-hi, 0x1p32, t);
+      carry = hi;
     }
+    S[L] = (uint32_t)carry;
     // quotient estimate t ~ S / P (S < 2^16 P), then R = S - t P, corrected once
     double sd = 0.0;
 #pragma unroll

@@ -38,6 +38,7 @@ struct Tables {
   float inv_s[kMaxN];         // 1/s, float
   uint16_t pw[kMaxN][kPowT];  // 2^t mod p, t < kPowT
   uint32_t w[kMaxN][kLimbs];  // CRT weights q_l P / p_l, little-endian limbs
+  double wd[kMaxN][kLimbs];   // the same limbs as doubles (exact)
   uint32_t P[kLimbs];         // product of the moduli
   uint32_t half[kLimbs];      // floor(P / 2)
   double P_d;                 // P rounded to double

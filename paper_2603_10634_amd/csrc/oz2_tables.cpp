@@ -208,7 +208,10 @@ bool build_tables(int N, int list, Tables *t) {
     int q = inv_mod((int)big_mod_small(others, (uint32_t)p[l]), p[l]);
     big_mul_small(others, (uint32_t)q);
     if ((int)others.size() > limbs) return false;
-    for (size_t i = 0; i < others.size(); ++i) t->w[l][i] = others[i];
+    for (size_t i = 0; i < others.size(); ++i) {
+      t->w[l][i] = others[i];
+      t->wd[l][i] = (double)others[i];
+    }
   }
   t->P_d = big_to_double(P, true);
   t->inv_P_d = 1.0 / t->P_d;

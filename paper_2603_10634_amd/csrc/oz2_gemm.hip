@@ -569,8 +569,15 @@ __device__ __forceinline__ void pin_agpr(ACC (&acc)[4][4]) {
     for (int ti = 0; ti < 4; ++ti) asm volatile("" : "+a"(acc[tj][ti]));
 }
 
-// acc = smod(mul smod(acc)), one 16-value MFMA tile at a time.
+// acc = mul acc (mod p), reduced to |acc| <= p/2 + 2, one 16-value MFMA tile
+// at a time, in FP32: for an exact integer |x| < 2^24 the quotient estimate
+// rint(x p^-1) misses x / p by less than 2 / p + 1/2, so x - q p (one exact
+// fused multiply-add) has |x - q p| <= p/2 + 2; times |mul| <= 256 it stays
+// below 2^17 and is reduced the same way.  Any representative that small
+// keeps the next pass's FP32 accumulation exact (below 2^24); the epilogue
+// takes the symmetric remainder.
 __device__ __forceinline__ void fold_w(v16f (&acc)[4][4], int mul, int p, float inv) {
+  const float pf = (float)p, mf = (float)mul;
   pin_agpr(acc);
 #pragma unroll
   for (int tj = 0; tj < 4; ++tj)
@@ -579,8 +586,9 @@ __device__ __forceinline__ void fold_w(v16f (&acc)[4][4], int mul, int p, float 
       v16f t16;
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const int t = smod_i32((int)acc[tj][ti][v], p, inv);
-        t16[v] = (float)smod_i32(mul * t, p, inv);
+        const float x = acc[tj][ti][v];
+        const float y = fmaf(-rintf(x * inv), pf, x) * mf;
+        t16[v] = fmaf(-rintf(y * inv), pf, y);
       }
       acc[tj][ti] = t16;
       asm volatile("" : "+a"(acc[tj][ti]));

@@ -99,7 +99,9 @@ __global__ __launch_bounds__(256) void k_line_max(Problem P1, Group G) {
 
 // Quantization tiles: 32 lines x 128 k per workgroup of 256 threads; thread t
 // owns line t / 8 and the 16 consecutive k (t % 8) * 16 .. + 15, so a line's
-// bytes of a tile leave as one 128-byte segment per output slice.  The FP64
+// bytes of a tile leave as one 128-byte segment per output slice (the residue
+// pass uses 16 lines x 128 k, 8 k per thread, for a smaller register
+// footprint and more waves in flight).  The FP64
 // tile is staged in LDS to read along whichever dimension is contiguous;
 // element h of a row sits at h + h / 16 (one pad double per 16) so that the
 // threads of one read (same q, consecutive t) fall into different banks.
@@ -107,15 +109,15 @@ constexpr int kRowLd = kQK + kQK / 16 + 1;   // 137 doubles per staged row
 
 __device__ __forceinline__ int tile_at(int rr, int hh) { return rr * kRowLd + hh + (hh >> 4); }
 
-template <bool LCONTIG>
+template <bool LCONTIG, int QL>
 __device__ __forceinline__ void load_tile(const double *__restrict__ x, int64_t lines, int64_t k,
                                           int64_t sr, int64_t sh, int64_t r0, int64_t h0,
                                           double *tile) {
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
+  for (int q = 0; q < QL * kQK / 256; ++q) {
     const int idx = threadIdx.x + 256 * q;
-    const int rr = LCONTIG ? (idx & 31) : (idx >> 7);
-    const int hh = LCONTIG ? (idx >> 5) : (idx & 127);
+    const int rr = LCONTIG ? (idx % QL) : (idx >> 7);
+    const int hh = LCONTIG ? (idx / QL) : (idx & 127);
     const int64_t r = r0 + rr, h = h0 + hh;
     double v = 0.0;
     if (r < lines && h < k) v = x[r * sr + h * sh];
@@ -123,12 +125,13 @@ __device__ __forceinline__ void load_tile(const double *__restrict__ x, int64_t 
   }
 }
 
+template <int QL = kQL>
 __device__ __forceinline__ void stage_tile(const Operand &op, int64_t r0, int64_t h0,
                                            double *tile) {
   if (op.sr == 1)
-    load_tile<true>(op.ptr, op.lines, op.k, op.sr, op.sh, r0, h0, tile);
+    load_tile<true, QL>(op.ptr, op.lines, op.k, op.sr, op.sh, r0, h0, tile);
   else
-    load_tile<false>(op.ptr, op.lines, op.k, op.sr, op.sh, r0, h0, tile);
+    load_tile<false, QL>(op.ptr, op.lines, op.k, op.sr, op.sh, r0, h0, tile);
 }
 
 // FP8 round-up bound operand of one tile (lines r0.., k h0..).
@@ -249,9 +252,11 @@ __global__ __launch_bounds__(256) void k_bound_norm(Problem P1, Group G) {
 // (squares, then Karatsuba, then INT8), so no loop body branches on the kind.
 constexpr int kDirectT = 10;  // powers 2^t applied in FP64 directly
 
+constexpr int kRE = kQK * kQLR / 256;  // inputs per thread in the residue pass (8)
+
 struct ResidueIn {
-  double x[16];  // sign mant 2^min(t, 10) (t > 0) or signed a' (t <= 0), exact
-  int t[16];     // t > 10: the power of two t - 10 still to apply, else 0
+  double x[kRE];  // sign mant 2^min(t, 10) (t > 0) or signed a' (t <= 0), exact
+  int t[kRE];     // t > 10: the power of two t - 10 still to apply, else 0
   bool big;      // some lane of the wave has t > 0
   bool huge;     // some lane of the wave has t > 10
 };
@@ -264,9 +269,9 @@ __device__ __forceinline__ void modulus_pass(const ResidueIn &in, const Tables *
   const float lof = (float)(-(p >> 1)), hif = (float)(p - 1 - (p >> 1));
   const double pd = (double)p, invpd = tab->inv_pd[l];
   const float invpf = tab->inv_p[l];
-  float fu[16];
+  float fu[kRE];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
+  for (int q = 0; q < kRE; ++q) {
     const double x = in.x[q];
     float f = (float)fma(-rint(x * invpd), pd, x);
     if (in.big) f = fmaf(-rintf(f * invpf), pf, f);
@@ -276,7 +281,7 @@ __device__ __forceinline__ void modulus_pass(const ResidueIn &in, const Tables *
   }
   if (in.huge) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < kRE; ++q) {
       if (in.t[q] > 0) {
         const float prod = fu[q] * (float)tab->pw[l][in.t[q]];
         const float qq = rintf(prod * invpf);
@@ -287,21 +292,22 @@ __device__ __forceinline__ void modulus_pass(const ResidueIn &in, const Tables *
       }
     }
   }
-  int w1[4], w2[4], w3[4];
+  constexpr int G = kRE / 4;
+  int w1[G], w2[G], w3[G];
   if (KIND == 2) {
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
+    for (int g = 0; g < G; ++g) {
       uint32_t word = 0;
 #pragma unroll
       for (int z = 0; z < 4; ++z) word |= ((uint32_t)(int)fu[4 * g + z] & 0xFFu) << (8 * z);
       w1[g] = (int)word;
     }
-    *(uint4 *)dst = make_uint4(w1[0], w1[1], w1[2], w1[3]);
+    *(uint2 *)dst = make_uint2(w1[0], w1[1]);
     return;
   }
   const float sf = (float)tab->s[l], invs = tab->inv_s[l];
 #pragma unroll
-  for (int g = 0; g < 4; ++g) {
+  for (int g = 0; g < G; ++g) {
     float x1[4], x2[4], x3[4];
 #pragma unroll
     for (int z = 0; z < 4; ++z) {
@@ -327,9 +333,9 @@ __device__ __forceinline__ void modulus_pass(const ResidueIn &in, const Tables *
       w3[g] = __builtin_amdgcn_cvt_pk_fp8_f32(x3[2], x3[3], w3[g], true);
     }
   }
-  *(uint4 *)dst = make_uint4(w1[0], w1[1], w1[2], w1[3]);
-  *(uint4 *)(dst + slice_stride) = make_uint4(w2[0], w2[1], w2[2], w2[3]);
-  if (KIND == 1) *(uint4 *)(dst + 2 * slice_stride) = make_uint4(w3[0], w3[1], w3[2], w3[3]);
+  *(uint2 *)dst = make_uint2(w1[0], w1[1]);
+  *(uint2 *)(dst + slice_stride) = make_uint2(w2[0], w2[1]);
+  if (KIND == 1) *(uint2 *)(dst + 2 * slice_stride) = make_uint2(w3[0], w3[1]);
 }
 
 __device__ __forceinline__ void residues_tile(const Operand &op, int64_t kp, int64_t lines_pad,
@@ -338,17 +344,18 @@ __device__ __forceinline__ void residues_tile(const Operand &op, int64_t kp, int
                                               const Tables *__restrict__ tab, int N, int nsq,
                                               int nka, uint8_t *__restrict__ slices,
                                               double *tile) {
-  stage_tile(op, r0, h0, tile);
+  stage_tile<kQLR>(op, r0, h0, tile);
   __syncthreads();
-  const int rl = threadIdx.x >> 3, b = threadIdx.x & 7;
+  // thread t: line t / 16, the kRE = 8 consecutive k (t % 16) * 8 .. + 7
+  const int rl = threadIdx.x >> 4, b = threadIdx.x & 15;
   const int64_t r = r0 + rl;
   const int s = shift[r];  // log2(mu_r)
 
   ResidueIn in;
   bool big = false, huge = false;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const uint64_t bits = (uint64_t)__double_as_longlong(tile[tile_at(rl, b * 16 + q)]);
+  for (int q = 0; q < kRE; ++q) {
+    const uint64_t bits = (uint64_t)__double_as_longlong(tile[tile_at(rl, b * kRE + q)]);
     uint64_t m = 0;
     int t = 0;
     if ((bits & kAbsMask) < kInfBits) {
@@ -374,7 +381,7 @@ __device__ __forceinline__ void residues_tile(const Operand &op, int64_t kp, int
   in.huge = __any(huge);
 
   const int64_t slice_stride = lines_pad * kp;
-  uint8_t *base = slices + kblocked(r, h0 + b * 16, lines_pad);
+  uint8_t *base = slices + kblocked(r, h0 + b * kRE, lines_pad);
   int l = 0;
   for (; l < nsq; ++l)
     modulus_pass<0>(in, tab, l, base + (int64_t)tab->slice0[l] * slice_stride, slice_stride);
@@ -386,14 +393,14 @@ __device__ __forceinline__ void residues_tile(const Operand &op, int64_t kp, int
 
 template <bool GROUPED, int SIDE>
 __global__ __launch_bounds__(256) void k_residues(Problem P1, Group G) {
-  __shared__ double tile[kQL * kRowLd];
+  __shared__ double tile[kQLR * kRowLd];
   int64_t local;
   const Problem &P = *locate<GROUPED>(P1, G, blockIdx.x, local);
   const Operand &op = SIDE == 0 ? P.A : P.B;
   const int64_t base = SIDE == 0 ? 0 : P.w.lineB;
   const Dims d = family_dims(SIDE == 0 ? kFamResA : kFamResB, P, 0);
   const int64_t bx = local % d.x, by = local / d.x;
-  residues_tile(op, P.g.kp, SIDE == 0 ? P.g.mp : P.g.np, bx * kQL, by * kQK, P.w.shift + base,
+  residues_tile(op, P.g.kp, SIDE == 0 ? P.g.mp : P.g.np, bx * kQLR, by * kQK, P.w.shift + base,
                 P.tab, P.g.N, P.g.nsq, P.g.nka, SIDE == 0 ? P.w.Asl : P.w.Bsl, tile);
 }
 

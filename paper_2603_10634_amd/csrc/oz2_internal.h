@@ -119,9 +119,8 @@ constexpr int kGemmTJ = 256;  // output columns j per tile
 constexpr int kGemmTIW = 256; // output rows i per tile of the single-product kernels
                               // (Karatsuba products, bound product)
 constexpr int kGemmBK = 64;   // k per pipeline stage
-constexpr int kQL = 32;       // quantization passes: 32 lines x 128 k per block
+constexpr int kQL = 16;       // quantization passes: 16 lines x 128 k per block
 constexpr int kQK = 128;
-constexpr int kQLR = 16;      // residue pass: 16 lines x 128 k per block
 
 // Kernel families of the emulation, in launch order.  One launch of a family
 // covers one problem or a whole group of problems (a batch).
@@ -193,14 +192,12 @@ __host__ __device__ inline Dims family_dims(int fam, const Problem &P, int chunk
     }
     case kFamBarA:
     case kFamNormA:
+    case kFamResA:
       return {g.mp / kQL, g.kp / kQK, 1};
     case kFamBarB:
     case kFamNormB:
-      return {g.np / kQL, g.kp / kQK, 1};
-    case kFamResA:
-      return {g.mp / kQLR, g.kp / kQK, 1};
     case kFamResB:
-      return {g.np / kQLR, g.kp / kQK, 1};
+      return {g.np / kQL, g.kp / kQK, 1};
     case kFamBgemm:
       return {g.mp / kGemmTIW, g.np / kGemmTJ, 1};
     case kFamDecide:

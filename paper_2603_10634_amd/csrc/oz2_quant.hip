@@ -97,11 +97,11 @@ __global__ __launch_bounds__(256) void k_line_max(Problem P1, Group G) {
     line_max_lcontig(op, sh, bx, by, P.w.amax + base, P.w.flags + base);
 }
 
-// Quantization tiles: 32 lines x 128 k per workgroup of 256 threads; thread t
-// owns line t / 8 and the 16 consecutive k (t % 8) * 16 .. + 15, so a line's
-// bytes of a tile leave as one 128-byte segment per output slice (the residue
-// pass uses 16 lines x 128 k, 8 k per thread, for a smaller register
-// footprint and more waves in flight).  The FP64
+// Quantization tiles: 16 lines x 128 k per workgroup of 256 threads; thread t
+// owns line t / 16 and the 8 consecutive k (t % 16) * 8 .. + 7, so a line's
+// bytes of a tile leave as one 128-byte segment per output slice.  Small
+// tiles and 8 inputs per thread keep the register and LDS footprint low, so
+// many waves stream through each CU.  The FP64
 // tile is staged in LDS to read along whichever dimension is contiguous;
 // element h of a row sits at h + h / 16 (one pad double per 16) so that the
 // threads of one read (same q, consecutive t) fall into different banks.
@@ -141,7 +141,7 @@ __device__ __forceinline__ void bound_operand_tile(const Operand &op, int64_t li
                                                    double *tile) {
   stage_tile(op, r0, h0, tile);
   __syncthreads();
-  const int rl = threadIdx.x >> 3, b = threadIdx.x & 7;
+  const int rl = threadIdx.x >> 4, b = threadIdx.x & 15;
   const int64_t r = r0 + rl;
   const uint64_t am = r < op.lines ? amax[r] : 0ull;
   const int Er = am ? ufp_exponent(am) : 0;
@@ -150,13 +150,13 @@ __device__ __forceinline__ void bound_operand_tile(const Operand &op, int64_t li
     if (am == 0) flags[r] |= kZeroLine;
   }
   const int sh7 = 7 - Er;  // mu' = 2^(7 - E)
-  uint32_t packed[4];
+  uint32_t packed[2];
 #pragma unroll
-  for (int w = 0; w < 4; ++w) {
+  for (int w = 0; w < 2; ++w) {
     uint32_t word = 0;
 #pragma unroll
     for (int z = 0; z < 4; ++z) {
-      const double v = tile[tile_at(rl, b * 16 + w * 4 + z)];
+      const double v = tile[tile_at(rl, b * 8 + w * 4 + z)];
       const uint64_t bits = (uint64_t)__double_as_longlong(v);
       uint32_t code = 0;
       if ((bits & kAbsMask) < kInfBits) code = e4m3_round_up(bits, sh7);
@@ -164,8 +164,7 @@ __device__ __forceinline__ void bound_operand_tile(const Operand &op, int64_t li
     }
     packed[w] = word;
   }
-  *(uint4 *)(bar + kblocked(r, h0 + b * 16, lines_pad)) =
-      make_uint4(packed[0], packed[1], packed[2], packed[3]);
+  *(uint2 *)(bar + kblocked(r, h0 + b * 8, lines_pad)) = make_uint2(packed[0], packed[1]);
 }
 
 template <bool GROUPED, int SIDE>
@@ -194,7 +193,7 @@ __device__ __forceinline__ void bound_norm_tile(const Operand &op, int64_t r0, i
                                                 double *tile) {
   stage_tile(op, r0, h0, tile);
   __syncthreads();
-  const int rl = threadIdx.x >> 3, b = threadIdx.x & 7;
+  const int rl = threadIdx.x >> 4, b = threadIdx.x & 15;
   const int64_t r = r0 + rl;
   const uint64_t am = r < op.lines ? amax[r] : 0ull;
   const int Er = am ? ufp_exponent(am) : 0;
@@ -205,15 +204,16 @@ __device__ __forceinline__ void bound_norm_tile(const Operand &op, int64_t r0, i
   const int sh7 = 7 - Er;  // mu' = 2^(7 - E)
   uint64_t sum = 0;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const uint64_t bits = (uint64_t)__double_as_longlong(tile[tile_at(rl, b * 16 + q)]);
+  for (int q = 0; q < 8; ++q) {
+    const uint64_t bits = (uint64_t)__double_as_longlong(tile[tile_at(rl, b * 8 + q)]);
     const uint32_t q9 = (bits & kAbsMask) < kInfBits ? e4m3_q9(e4m3_round_up(bits, sh7)) : 0u;
     sum += (uint64_t)q9 * q9;
   }
-  // the 8 threads of a line are 8 consecutive lanes
+  // the 16 threads of a line are 16 consecutive lanes
   sum += __shfl_xor(sum, 1, 64);
   sum += __shfl_xor(sum, 2, 64);
   sum += __shfl_xor(sum, 4, 64);
+  sum += __shfl_xor(sum, 8, 64);
   if (b == 0 && sum) atomicAdd((unsigned long long *)&norm[r], (unsigned long long)sum);
 }
 
@@ -252,7 +252,7 @@ __global__ __launch_bounds__(256) void k_bound_norm(Problem P1, Group G) {
 // (squares, then Karatsuba, then INT8), so no loop body branches on the kind.
 constexpr int kDirectT = 10;  // powers 2^t applied in FP64 directly
 
-constexpr int kRE = kQK * kQLR / 256;  // inputs per thread in the residue pass (8)
+constexpr int kRE = kQK * kQL / 256;  // inputs per thread of a quantization tile (8)
 
 struct ResidueIn {
   double x[kRE];  // sign mant 2^min(t, 10) (t > 0) or signed a' (t <= 0), exact
@@ -344,7 +344,7 @@ __device__ __forceinline__ void residues_tile(const Operand &op, int64_t kp, int
                                               const Tables *__restrict__ tab, int N, int nsq,
                                               int nka, uint8_t *__restrict__ slices,
                                               double *tile) {
-  stage_tile<kQLR>(op, r0, h0, tile);
+  stage_tile(op, r0, h0, tile);
   __syncthreads();
   // thread t: line t / 16, the kRE = 8 consecutive k (t % 16) * 8 .. + 7
   const int rl = threadIdx.x >> 4, b = threadIdx.x & 15;
@@ -393,14 +393,14 @@ __device__ __forceinline__ void residues_tile(const Operand &op, int64_t kp, int
 
 template <bool GROUPED, int SIDE>
 __global__ __launch_bounds__(256) void k_residues(Problem P1, Group G) {
-  __shared__ double tile[kQLR * kRowLd];
+  __shared__ double tile[kQL * kRowLd];
   int64_t local;
   const Problem &P = *locate<GROUPED>(P1, G, blockIdx.x, local);
   const Operand &op = SIDE == 0 ? P.A : P.B;
   const int64_t base = SIDE == 0 ? 0 : P.w.lineB;
   const Dims d = family_dims(SIDE == 0 ? kFamResA : kFamResB, P, 0);
   const int64_t bx = local % d.x, by = local / d.x;
-  residues_tile(op, P.g.kp, SIDE == 0 ? P.g.mp : P.g.np, bx * kQLR, by * kQK, P.w.shift + base,
+  residues_tile(op, P.g.kp, SIDE == 0 ? P.g.mp : P.g.np, bx * kQL, by * kQK, P.w.shift + base,
                 P.tab, P.g.N, P.g.nsq, P.g.nka, SIDE == 0 ? P.w.Asl : P.w.Bsl, tile);
 }
 

@@ -281,7 +281,7 @@ int enqueue_products(const Problem &P, hipStream_t st, Marks &mark, bool res_a =
       OZ2_TRY(launch_gemm_family(f, &P, nullptr, c, 0, st));
   mark();
   // steps 9-10: CRT and inverse scaling
-  OZ2_TRY(launch_crt_family(&P, nullptr, P.limbs, st));
+  OZ2_TRY(launch_crt_family(&P, nullptr, P.limbs, P.g.N, st));
   mark();
   return OZ2_SUCCESS;
 }
@@ -356,6 +356,7 @@ struct GLaunch {
 struct SubBatch {
   std::vector<GLaunch> launches;
   int limbs;
+  int N;  // number of moduli (every problem of a batch has the same)
 };
 
 // Everything a batched call (or, in graph mode, a single call) needs beyond
@@ -578,7 +579,7 @@ int enqueue_subbatch(const SubBatch &sb, int sched, int cus, hipStream_t st, Mar
     else if (L.fam == kFamDecide || L.fam == kFamFixup || L.fam == kFamFinal)
       OZ2_TRY(launch_scale_family(L.fam, nullptr, &L.G, st));
     else if (L.fam == kFamCrt)
-      OZ2_TRY(launch_crt_family(nullptr, &L.G, sb.limbs, st));
+      OZ2_TRY(launch_crt_family(nullptr, &L.G, sb.limbs, sb.N, st));
     else
       OZ2_TRY(launch_quant_family(L.fam, nullptr, &L.G, st));
   }
@@ -943,6 +944,7 @@ int ozaki2_dgemm_batched(int count, const char *transA, const char *transB, cons
       if (cur.empty()) return;
       SubBatch sb;
       sb.limbs = ht->limbs;
+      sb.N = num_moduli;
       build_subbatch(cur, W, &sb);
       p->subs.push_back(std::move(sb));
       cur.clear();

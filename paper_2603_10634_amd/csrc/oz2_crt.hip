@@ -71,7 +71,9 @@ __device__ __forceinline__ double scaled_rn(const uint32_t (&X)[L], int t) {
   return ldexp((double)Q, lsb - t);
 }
 
-template <int L>
+// NF > 0: the number of moduli is the compile-time NF (no per-modulus
+// branches); NF = 0: N at run time.
+template <int L, int NF>
 __device__ __forceinline__ void crt_entry(const int16_t *__restrict__ planes,
                                           const int32_t *__restrict__ shift,
                                           const uint32_t *__restrict__ flags,
@@ -94,17 +96,18 @@ __device__ __forceinline__ void crt_entry(const int16_t *__restrict__ planes,
     const int16_t *pl = planes + j * mp + i;
     const int64_t pstride = mp * np;
     // all N residues are requested before the first is used
+    const int NN = NF > 0 ? NF : N;
     int uu[kMaxN];
     const int16_t *ql = pl;
 #pragma unroll
     for (int l = 0; l < kMaxN; ++l)
-      if (l < N) {
+      if (l < NN) {
         uu[l] = *ql;
         ql += pstride;
       }
 #pragma unroll
     for (int l = 0; l < kMaxN; ++l) {
-      if (l < N) {
+      if (l < NN) {
         const int u = uu[l] + (tab->p[l] & (uu[l] >> 31));  // C'_l mod p_l in [0, p_l)
         const double ud = (double)u;
 #pragma unroll
@@ -199,13 +202,13 @@ __device__ __forceinline__ void crt_entry(const int16_t *__restrict__ planes,
   C[i + j * ldc] = out;
 }
 
-template <int L, bool GROUPED>
+template <int L, int NF, bool GROUPED>
 __global__ __launch_bounds__(256) void k_crt(Problem P1, Group G) {
   int64_t local;
   const Problem &P = *locate<GROUPED>(P1, G, blockIdx.x, local);
   const int64_t nbx = (P.g.m + 255) / 256;
   const int64_t bx = local % nbx, j = local / nbx;
-  crt_entry<L>(P.w.planes, P.w.shift, P.w.flags, P.tab, P.g.N, P.g.m, P.g.mp, P.g.np,
+  crt_entry<L, NF>(P.w.planes, P.w.shift, P.w.flags, P.tab, P.g.N, P.g.m, P.g.mp, P.g.np,
                P.w.lineB, P.alpha, P.beta, P.C, P.ldc, bx * 256 + threadIdx.x, j);
 }
 
@@ -220,7 +223,8 @@ __global__ void k_scal(int64_t m, double beta, double *__restrict__ C, int64_t l
 
 }  // namespace
 
-hipError_t launch_crt_family(const Problem *P, const Group *G, int limbs, hipStream_t st) {
+hipError_t launch_crt_family(const Problem *P, const Group *G, int limbs, int N,
+                             hipStream_t st) {
   const bool grouped = G != nullptr;
   Problem p1;
   Group g1;
@@ -234,12 +238,34 @@ hipError_t launch_crt_family(const Problem *P, const Group *G, int limbs, hipStr
   if (blocks <= 0) return hipSuccess;
   if (blocks > 0x7FFFFFFFll) return hipErrorInvalidValue;
   const dim3 grid((unsigned)blocks), blk(256);
-#define OZ2_CRT_CASE(LL)                                            \
-  case LL:                                                          \
-    if (grouped)                                                    \
-      hipLaunchKernelGGL((k_crt<LL, true>), grid, blk, 0, st, p1, g1);  \
-    else                                                            \
-      hipLaunchKernelGGL((k_crt<LL, false>), grid, blk, 0, st, p1, g1); \
+#define OZ2_CRT_LAUNCH(LL, NF)                                             \
+  if (grouped)                                                             \
+    hipLaunchKernelGGL((k_crt<LL, NF, true>), grid, blk, 0, st, p1, g1);   \
+  else                                                                     \
+    hipLaunchKernelGGL((k_crt<LL, NF, false>), grid, blk, 0, st, p1, g1);
+  // the moduli counts of full accuracy (12-16) get kernels without
+  // per-modulus branches
+  if (limbs == 4 && N >= 12 && N <= 16) {
+    switch (N) {
+      case 12: OZ2_CRT_LAUNCH(4, 12) break;
+      case 13: OZ2_CRT_LAUNCH(4, 13) break;
+      case 14: OZ2_CRT_LAUNCH(4, 14) break;
+      case 15: OZ2_CRT_LAUNCH(4, 15) break;
+      default: OZ2_CRT_LAUNCH(4, 16) break;
+    }
+    return hipGetLastError();
+  }
+  if (limbs == 5 && N >= 14 && N <= 16) {
+    switch (N) {
+      case 14: OZ2_CRT_LAUNCH(5, 14) break;
+      case 15: OZ2_CRT_LAUNCH(5, 15) break;
+      default: OZ2_CRT_LAUNCH(5, 16) break;
+    }
+    return hipGetLastError();
+  }
+#define OZ2_CRT_CASE(LL)   \
+  case LL:                 \
+    OZ2_CRT_LAUNCH(LL, 0)  \
     break;
   switch (limbs) {
     OZ2_CRT_CASE(1)
@@ -256,6 +282,7 @@ hipError_t launch_crt_family(const Problem *P, const Group *G, int limbs, hipStr
       return hipErrorInvalidValue;
   }
 #undef OZ2_CRT_CASE
+#undef OZ2_CRT_LAUNCH
   return hipGetLastError();
 }
 

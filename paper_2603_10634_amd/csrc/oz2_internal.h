@@ -288,7 +288,7 @@ hipError_t launch_quant_family(int fam, const Problem *P, const Group *G, hipStr
 hipError_t launch_scale_family(int fam, const Problem *P, const Group *G, hipStream_t st);
 hipError_t launch_gemm_family(int fam, const Problem *P, const Group *G, int chunk, int64_t grid,
                               hipStream_t st);
-hipError_t launch_crt_family(const Problem *P, const Group *G, int limbs, hipStream_t st);
+hipError_t launch_crt_family(const Problem *P, const Group *G, int limbs, int N, hipStream_t st);
 hipError_t launch_scal(int64_t m, int64_t n, double beta, double *C, int64_t ldc,
                        hipStream_t st);
 

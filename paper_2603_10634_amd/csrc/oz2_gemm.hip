@@ -428,52 +428,88 @@ __device__ __forceinline__ void square_tile(const uint8_t *Asl, const uint8_t *B
 }
 
 // ---------------------------------------------------------------------------
-// Wide single-product tiles: 256 (j) x 256 (i) per workgroup, each wave a
-// 128 x 128 block as 4 x 4 MFMA tiles in one accumulator (256 AGPRs).  Per
-// 64-k stage a wave issues 16 MFMAs against 16 KB of LDS fragment reads and
-// the workgroup moves 32 KB into LDS, so LDS traffic stays below the MFMA
-// time; the 256 x 128 two-accumulator tile above is kept for the square
-// moduli, whose three products share two operand slices per side.
+// Wide single-product tiles: 256 (j) x 256 (i) per workgroup in one
+// accumulator per wave.  The residue products run 8 waves (two per SIMD, so
+// one wave's MFMAs cover the other's barrier and LDS waits), each a 128 x 64
+// block as 4 x 2 MFMA tiles (128 AGPRs); the bound product runs 4 waves of
+// 128 x 128 (256 AGPRs).  Per 64-k stage the workgroup moves 32 KB into LDS
+// and reads at most 1.5 KB of fragments per MFMA, below the LDS rate; the
+// 256 x 128 two-accumulator tile above is kept for the square moduli, whose
+// three products share two operand slices per side.
 // ---------------------------------------------------------------------------
 constexpr int TIW = 256;                 // wide tile: i extent
 constexpr int ASZW = TIW * ROWB;         // bytes of one A-side tile
 constexpr int STAGEW = BSZ + ASZW;       // 32 KB per stage
 constexpr int SW = 4;                    // ring slots
+// A wide workgroup has NW = 4 waves (one per SIMD, each 128 x 128) or 8 (two
+// per SIMD, each 128 x 64, half the accumulator registers); per wave TB(NW)
+// i blocks of 32 rows and LP(NW) 1 KB loads per side and stage.
+constexpr int NW_RES = 8;                // the residue products
+constexpr int NW_BOUND = 4;              // the bound product
+template <int NW> constexpr int TB() { return 16 / NW; }
+template <int NW> constexpr int LP() { return 16 / NW; }
 static_assert(SW * STAGEW <= LDS_RING, "wide ring");
 
-// Load number idx (0..7) of a wide stage: 0..3 B side, 4..7 A side, each 1 KB
-// = 16 rows; both sides have 256 rows, so one set of lane offsets serves both.
-__device__ __forceinline__ void dma_one_w(int idx, const uint8_t *gB, const uint8_t *gA,
-                                          const DmaOffsets &d, int64_t kofs, uint32_t slot) {
-  const uint32_t w = slot + d.lds_wave;
-  if (idx < 4)
-    dma16(gB + (kofs >> 6) * d.sB, d.ob[idx], w + idx * 4096);
-  else
-    dma16(gA + (kofs >> 6) * d.sA, d.ob[idx - 4], w + BSZ + (idx - 4) * 4096);
+// Lane offsets of the wide loads: wave w loads rows 16 (w + NWW u) .. + 15 of
+// each side for u < LPW (both sides have 256 rows).
+template <int NW>
+__device__ __forceinline__ DmaOffsets dma_offsets_w(int64_t rowsB, int64_t rowsA) {
+  constexpr int LPW = LP<NW>(), NWW = NW;
+  DmaOffsets d;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int rsub = lane >> 2, pc = lane & 3;
+#pragma unroll
+  for (int u = 0; u < LPW; ++u) {
+    const int r = 16 * (wave + NWW * u) + rsub;
+    d.ob[u] = (uint32_t)(r * 64) + 16u * (uint32_t)(pc ^ swz(r));
+  }
+  d.lds_wave = 1024u * (uint32_t)wave;
+  d.sB = rowsB * 64;
+  d.sA = rowsA * 64;
+  return d;
 }
 
-template <int Q>
+// Load number idx (0 .. 2 LPW - 1) of a wide stage: the first LPW on the B
+// side, the rest on the A side, each 1 KB = 16 rows.
+template <int NW>
+__device__ __forceinline__ void dma_one_w(int idx, const uint8_t *gB, const uint8_t *gA,
+                                          const DmaOffsets &d, int64_t kofs, uint32_t slot) {
+  constexpr int LPW = LP<NW>(), NWW = NW;
+  const uint32_t w = slot + d.lds_wave;
+  if (idx < LPW)
+    dma16(gB + (kofs >> 6) * d.sB, d.ob[idx], w + idx * (NWW * 1024));
+  else
+    dma16(gA + (kofs >> 6) * d.sA, d.ob[idx - LPW], w + BSZ + (idx - LPW) * (NWW * 1024));
+}
+
+// The 2 LPW loads of a stage in four parts.
+template <int NW, int Q>
 __device__ __forceinline__ void dma_part_w(const uint8_t *gB, const uint8_t *gA,
                                            const DmaOffsets &d, int64_t kofs, uint32_t slot) {
+  constexpr int PL = 2 * LP<NW>() / 4;
 #pragma unroll
-  for (int idx = 2 * Q; idx < 2 * Q + 2; ++idx) {
-    dma_one_w(idx, gB, gA, d, kofs, slot);
+  for (int idx = PL * Q; idx < PL * Q + PL; ++idx) {
+    dma_one_w<NW>(idx, gB, gA, d, kofs, slot);
     __builtin_amdgcn_sched_barrier(0);
   }
 }
 
-// One stage of the wide loop, scheduled as stage_iter (blocks rows tj of 4
-// MFMA steps; barrier B_j before the last block row; loads in four parts of
-// 2).  ACC is v16f (FP8 products) or v16i (INT8 products).
-template <class ACC>
+// One stage of the wide loop, scheduled as stage_iter (block rows tj of TBW
+// MFMA steps; barrier B_j before the last block row; loads in four parts).
+// Wave w owns j rows 128 (w / (NWW / 2)) .. + 127 and i rows
+// 32 TBW (w % (NWW / 2)) .. + 32 TBW - 1.  ACC is v16f (FP8 products) or v16i
+// (INT8 products).
+template <int NW, class ACC>
 __device__ __forceinline__ void stage_iter_w(int j, int nk, const uint8_t *gB, const uint8_t *gA,
                                              const DmaOffsets &d, int64_t kbeg,
                                              const uint8_t *lds, uint32_t ring,
-                                             const v8i (&fa)[4], v8i (&fan)[4], v8i (&fb)[4],
-                                             ACC (&acc)[4][4]) {
-  constexpr int L = 8;
+                                             const v8i (&fa)[TB<NW>()], v8i (&fan)[TB<NW>()],
+                                             v8i (&fb)[4], ACC (&acc)[4][TB<NW>()]) {
+  constexpr int TBW = TB<NW>(), NWW = NW;
+  constexpr int L = 2 * LP<NW>();
   const int wave = threadIdx.x >> 6;
-  const int wj = wave >> 1, wi = wave & 1;
+  const int wj = wave / (NWW / 2), wi = wave % (NWW / 2);
   const uint8_t *cur = lds + (j % SW) * STAGEW;
   const bool ld_prev = j + SW - 1 < nk;
   const bool ld_next = j + SW < nk;
@@ -485,13 +521,13 @@ __device__ __forceinline__ void stage_iter_w(int j, int nk, const uint8_t *gB, c
     fb[tj + 1] = lds_frag(cur, wj * 128 + (tj + 1) * 32);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int ti = 0; ti < 4; ++ti) {
+    for (int ti = 0; ti < TBW; ++ti) {
       acc[tj][ti] = mma(fb[tj], fa[ti], acc[tj][ti]);
       __builtin_amdgcn_sched_barrier(0);
       if (ti == 0 && ld_prev) {
-        if (tj == 0) dma_part_w<1>(gB, gA, d, kofs_prev, slot_prev);
-        if (tj == 1) dma_part_w<2>(gB, gA, d, kofs_prev, slot_prev);
-        if (tj == 2) dma_part_w<3>(gB, gA, d, kofs_prev, slot_prev);
+        if (tj == 0) dma_part_w<NW, 1>(gB, gA, d, kofs_prev, slot_prev);
+        if (tj == 1) dma_part_w<NW, 2>(gB, gA, d, kofs_prev, slot_prev);
+        if (tj == 2) dma_part_w<NW, 3>(gB, gA, d, kofs_prev, slot_prev);
       }
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -502,22 +538,18 @@ __device__ __forceinline__ void stage_iter_w(int j, int nk, const uint8_t *gB, c
   __builtin_amdgcn_sched_barrier(0);
   const uint8_t *nxt = lds + ((j + 1) % SW) * STAGEW;
 #pragma unroll
-  for (int ti = 0; ti < 4; ++ti) {
+  for (int ti = 0; ti < TBW; ++ti) {
     acc[3][ti] = mma(fb[3], fa[ti], acc[3][ti]);
     __builtin_amdgcn_sched_barrier(0);
     if (ti == 0 && ld_next)
-      dma_part_w<0>(gB, gA, d, kbeg + (int64_t)(j + SW) * BK, ring + (j % SW) * STAGEW);
+      dma_part_w<NW, 0>(gB, gA, d, kbeg + (int64_t)(j + SW) * BK, ring + (j % SW) * STAGEW);
     if (rd_next) {
-      // five fragment reads after MFMAs 0, 0, 1, 1, 2
+      // the next stage's fragments: the A side after MFMA 0, then B block 0
       if (ti == 0) {
-        fan[0] = lds_frag(nxt + BSZ, wi * 128);
-        fan[1] = lds_frag(nxt + BSZ, wi * 128 + 32);
-      } else if (ti == 1) {
-        fan[2] = lds_frag(nxt + BSZ, wi * 128 + 64);
-        fan[3] = lds_frag(nxt + BSZ, wi * 128 + 96);
-      } else if (ti == 2) {
-        fb[0] = lds_frag(nxt, wj * 128);
+#pragma unroll
+        for (int t = 0; t < TBW; ++t) fan[t] = lds_frag(nxt + BSZ, wi * 32 * TBW + t * 32);
       }
+      if (ti == TBW - 1) fb[0] = lds_frag(nxt, wj * 128);
     }
     __builtin_amdgcn_sched_barrier(0);
   }
@@ -525,35 +557,38 @@ __device__ __forceinline__ void stage_iter_w(int j, int nk, const uint8_t *gB, c
 
 // acc += A B over nk stages of 64 k for one wide tile; gB / gA point at row
 // j0 / i0 of one B-side / A-side slice.
-template <class ACC>
+template <int NW, class ACC>
 __device__ __forceinline__ void kloop_w(const uint8_t *gB, const uint8_t *gA, int64_t rowsB,
                                         int64_t rowsA, int64_t kbeg, int nk, uint8_t *lds,
-                                        ACC (&acc)[4][4]) {
-  constexpr int L = 8;
+                                        ACC (&acc)[4][TB<NW>()]) {
+  constexpr int TBW = TB<NW>(), NWW = NW;
+  constexpr int L = 2 * LP<NW>();
   const int wave = threadIdx.x >> 6;
-  const int wj = wave >> 1, wi = wave & 1;
-  const DmaOffsets d = dma_offsets(rowsB, rowsA);
+  const int wj = wave / (NWW / 2), wi = wave % (NWW / 2);
+  const DmaOffsets d = dma_offsets_w<NW>(rowsB, rowsA);
   const uint32_t ring = lds_offset(lds);
 #pragma unroll
   for (int t = 0; t < SW - 1; ++t)
     if (t < nk) {
 #pragma unroll
-      for (int idx = 0; idx < L; ++idx) dma_one_w(idx, gB, gA, d, kbeg + (int64_t)t * BK, ring + t * STAGEW);
+      for (int idx = 0; idx < L; ++idx)
+        dma_one_w<NW>(idx, gB, gA, d, kbeg + (int64_t)t * BK, ring + t * STAGEW);
     }
-  if (SW - 1 < nk) dma_part_w<0>(gB, gA, d, kbeg + (int64_t)(SW - 1) * BK, ring + (SW - 1) * STAGEW);
   if (SW - 1 < nk)
-    wait_vm<(SW - 2) * L + 2>();
+    dma_part_w<NW, 0>(gB, gA, d, kbeg + (int64_t)(SW - 1) * BK, ring + (SW - 1) * STAGEW);
+  if (SW - 1 < nk)
+    wait_vm<(SW - 2) * L + L / 4>();
   else
     wait_stages<L, SW - 2>(nk - 1);
   __builtin_amdgcn_s_barrier();
-  v8i fa0[4], fa1[4], fb[4];
+  v8i fa0[TBW], fa1[TBW], fb[4];
 #pragma unroll
-  for (int ti = 0; ti < 4; ++ti) fa0[ti] = lds_frag(lds + BSZ, wi * 128 + ti * 32);
+  for (int ti = 0; ti < TBW; ++ti) fa0[ti] = lds_frag(lds + BSZ, wi * 32 * TBW + ti * 32);
   fb[0] = lds_frag(lds, wj * 128);
   // nk is a multiple of 4 (k is padded to 256): two stages per trip, no tail
   for (int j = 0; j < nk; j += 2) {
-    stage_iter_w(j, nk, gB, gA, d, kbeg, lds, ring, fa0, fa1, fb, acc);
-    stage_iter_w(j + 1, nk, gB, gA, d, kbeg, lds, ring, fa1, fa0, fb, acc);
+    stage_iter_w<NW>(j, nk, gB, gA, d, kbeg, lds, ring, fa0, fa1, fb, acc);
+    stage_iter_w<NW>(j + 1, nk, gB, gA, d, kbeg, lds, ring, fa1, fa0, fb, acc);
   }
   __builtin_amdgcn_s_barrier();
 }
@@ -561,12 +596,12 @@ __device__ __forceinline__ void kloop_w(const uint8_t *gB, const uint8_t *gA, in
 // Keeps the accumulator tiles in AGPRs at this point (an empty asm with
 // AGPR in/out operands), so the register allocator does not move the whole
 // accumulator to VGPRs around the folds between passes.
-template <class ACC>
-__device__ __forceinline__ void pin_agpr(ACC (&acc)[4][4]) {
+template <class ACC, int T>
+__device__ __forceinline__ void pin_agpr(ACC (&acc)[4][T]) {
 #pragma unroll
   for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
-    for (int ti = 0; ti < 4; ++ti) asm volatile("" : "+a"(acc[tj][ti]));
+    for (int ti = 0; ti < T; ++ti) asm volatile("" : "+a"(acc[tj][ti]));
 }
 
 // acc = mul acc (mod p), reduced to |acc| <= p/2 + 2, one 16-value MFMA tile
@@ -576,13 +611,14 @@ __device__ __forceinline__ void pin_agpr(ACC (&acc)[4][4]) {
 // below 2^17 and is reduced the same way.  Any representative that small
 // keeps the next pass's FP32 accumulation exact (below 2^24); the epilogue
 // takes the symmetric remainder.
-__device__ __forceinline__ void fold_w(v16f (&acc)[4][4], int mul, int p, float inv) {
+template <int TBW>
+__device__ __forceinline__ void fold_w(v16f (&acc)[4][TBW], int mul, int p, float inv) {
   const float pf = (float)p, mf = (float)mul;
   pin_agpr(acc);
 #pragma unroll
   for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
-    for (int ti = 0; ti < 4; ++ti) {
+    for (int ti = 0; ti < TBW; ++ti) {
       v16f t16;
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
@@ -629,33 +665,34 @@ __device__ __forceinline__ void karatsuba_tile_w(const uint8_t *Asl, const uint8
   const uint8_t *A0 = Asl + (int64_t)sl0 * sA + i0 * 64;
   const uint8_t *B0 = Bsl + (int64_t)sl0 * sB + j0 * 64;
 
-  v16f acc[4][4];
+  constexpr int NWW = NW_RES, TBW = TB<NW_RES>();
+  v16f acc[4][TBW];
 #pragma unroll
   for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
-    for (int ti = 0; ti < 4; ++ti)
+    for (int ti = 0; ti < TBW; ++ti)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[tj][ti][v] = 0.0f;
 
   pin_agpr(acc);
   const int third = 3 - second;
-  kloop_w(B0, A0, np, mp, kbeg, nk, lds, acc);                              // X = C1
+  kloop_w<NWW>(B0, A0, np, mp, kbeg, nk, lds, acc);                         // X = C1
   fold_w(acc, mul_a, p, inv);
-  kloop_w(B0 + second * sB, A0 + second * sA, np, mp, kbeg, nk, lds, acc);  // + Y
+  kloop_w<NWW>(B0 + second * sB, A0 + second * sA, np, mp, kbeg, nk, lds, acc);  // + Y
   fold_w(acc, mul_b, p, inv);
-  kloop_w(B0 + third * sB, A0 + third * sA, np, mp, kbeg, nk, lds, acc);    // + Z
+  kloop_w<NWW>(B0 + third * sB, A0 + third * sA, np, mp, kbeg, nk, lds, acc);    // + Z
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wj = wave >> 1, wi = wave & 1;
+  const int wj = wave / (NWW / 2), wi = wave % (NWW / 2);
   int16_t *out = planes + (int64_t)l * np * mp;
 #pragma unroll
   for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
-    for (int ti = 0; ti < 4; ++ti) {
+    for (int ti = 0; ti < TBW; ++ti) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         int r = smod_i32(mul_c * (int)acc[tj][ti][v], p, inv);
-        const int64_t i = i0 + wi * 128 + ti * 32 + (lane & 31);
+        const int64_t i = i0 + wi * 32 * TBW + ti * 32 + (lane & 31);
         const int64_t j = j0 + wj * 128 + tj * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
         int16_t *dst = out + j * mp + i;
         if (accumulate) r = smod_i32(r + (int)*dst, p, inv);
@@ -684,28 +721,29 @@ __device__ __forceinline__ void int8_tile_w(const uint8_t *Asl, const uint8_t *B
   const uint8_t *A0 = Asl + (int64_t)sl0 * mp * kp + i0 * 64;
   const uint8_t *B0 = Bsl + (int64_t)sl0 * np * kp + j0 * 64;
 
-  v16i acc[4][4];
+  constexpr int NWW = NW_RES, TBW = TB<NW_RES>();
+  v16i acc[4][TBW];
 #pragma unroll
   for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
-    for (int ti = 0; ti < 4; ++ti)
+    for (int ti = 0; ti < TBW; ++ti)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[tj][ti][v] = 0;
   pin_agpr(acc);
-  kloop_w(B0, A0, np, mp, kbeg, nk, lds, acc);
+  kloop_w<NWW>(B0, A0, np, mp, kbeg, nk, lds, acc);
   pin_agpr(acc);
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wj = wave >> 1, wi = wave & 1;
+  const int wj = wave / (NWW / 2), wi = wave % (NWW / 2);
   int16_t *out = planes + (int64_t)l * np * mp;
 #pragma unroll
   for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
-    for (int ti = 0; ti < 4; ++ti) {
+    for (int ti = 0; ti < TBW; ++ti) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         int r = smod_i32(acc[tj][ti][v], p, inv);
-        const int64_t i = i0 + wi * 128 + ti * 32 + (lane & 31);
+        const int64_t i = i0 + wi * 32 * TBW + ti * 32 + (lane & 31);
         const int64_t j = j0 + wj * 128 + tj * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
         int16_t *dst = out + j * mp + i;
         if (accumulate) r = smod_i32(r + (int)*dst, p, inv);
@@ -721,7 +759,9 @@ __device__ __forceinline__ void int8_tile_w(const uint8_t *Asl, const uint8_t *B
 // l = nsq + nka + z).
 // A grouped launch may run fewer workgroups than tiles; each then loops.
 template <int KIND, bool GROUPED>
-__global__ __launch_bounds__(256, 1) void k_residue_gemm(Problem P1, Group G, int chunk) {
+__global__ __launch_bounds__(KIND == 0 ? 256 : 64 * NW_RES, 1) void k_residue_gemm(Problem P1,
+                                                                               Group G,
+                                                                               int chunk) {
   __shared__ __attribute__((aligned(1024))) uint8_t lds[LDS_RING];
   const int64_t total = GROUPED ? G.total : (int64_t)gridDim.x;
   for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
@@ -755,23 +795,24 @@ __device__ __forceinline__ void bound_tile(const uint8_t *Abar, const uint8_t *B
                                            int64_t np, int nk, uint32_t *__restrict__ rmaxA,
                                            uint32_t *__restrict__ rmaxB, int64_t i0, int64_t j0,
                                            uint8_t *lds) {
-  v16f acc[4][4];
+  constexpr int NWW = NW_BOUND, TBW = TB<NW_BOUND>();
+  v16f acc[4][TBW];
 #pragma unroll
   for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
-    for (int ti = 0; ti < 4; ++ti)
+    for (int ti = 0; ti < TBW; ++ti)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[tj][ti][v] = 0.0f;
   resident_ptr(rmaxA, rmaxB);
   pin_agpr(acc);
-  kloop_w(Bbar + j0 * 64, Abar + i0 * 64, np, mp, 0, nk, lds, acc);
+  kloop_w<NWW>(Bbar + j0 * 64, Abar + i0 * 64, np, mp, 0, nk, lds, acc);
   pin_agpr(acc);
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wj = wave >> 1, wi = wave & 1;
+  const int wj = wave / (NWW / 2), wi = wave % (NWW / 2);
   // maxima over j of each column i (row maxima of Abar Bbar, for mu)
 #pragma unroll
-  for (int ti = 0; ti < 4; ++ti) {
+  for (int ti = 0; ti < TBW; ++ti) {
     float m = 0.0f;
 #pragma unroll
     for (int tj = 0; tj < 4; ++tj)
@@ -779,14 +820,16 @@ __device__ __forceinline__ void bound_tile(const uint8_t *Abar, const uint8_t *B
       for (int v = 0; v < 16; ++v) m = fmaxf(m, acc[tj][ti][v]);
     m = fmaxf(m, __shfl_xor(m, 32, 64));
     if (lane < 32)
-      atomicMax(&rmaxA[i0 + wi * 128 + ti * 32 + lane], __float_as_uint(m));
+      atomicMax(&rmaxA[i0 + wi * 32 * TBW + ti * 32 + lane], __float_as_uint(m));
   }
   // maxima over i of each row j (column maxima of Abar Bbar, for nu)
 #pragma unroll
   for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-      float m = fmaxf(fmaxf(acc[tj][0][v], acc[tj][1][v]), fmaxf(acc[tj][2][v], acc[tj][3][v]));
+      float m = acc[tj][0][v];
+#pragma unroll
+      for (int ti = 1; ti < TBW; ++ti) m = fmaxf(m, acc[tj][ti][v]);
 #pragma unroll
       for (int off = 16; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
       if ((lane & 31) == 0) {
@@ -797,7 +840,7 @@ __device__ __forceinline__ void bound_tile(const uint8_t *Abar, const uint8_t *B
 }
 
 template <bool GROUPED>
-__global__ __launch_bounds__(256, 1) void k_bound_gemm(Problem P1, Group G) {
+__global__ __launch_bounds__(64 * NW_BOUND, 1) void k_bound_gemm(Problem P1, Group G) {
   __shared__ __attribute__((aligned(1024))) uint8_t lds[LDS_RING];
   const int64_t total = GROUPED ? G.total : (int64_t)gridDim.x;
   for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
@@ -831,7 +874,8 @@ hipError_t launch_gemm_family(int fam, const Problem *P, const Group *G, int chu
   int64_t blocks = tiles;
   if (grouped && grid > 0 && grid < tiles) blocks = grid;
   if (blocks > 0x7FFFFFFFll) return hipErrorInvalidValue;
-  const dim3 gr((unsigned)blocks), blk(256);
+  const dim3 gr((unsigned)blocks),
+      blk(fam == kFamGemmSq ? 256 : (fam == kFamBgemm ? 64 * NW_BOUND : 64 * NW_RES));
   switch (fam) {
     case kFamBgemm:
       if (grouped)

@@ -17,9 +17,10 @@
 // A's slices (rows i), so the accumulator holds D[j][i] = (A'B')_ij and each
 // lane owns consecutive i of C's column-major planes.
 //
-// Workgroup: 256 threads (4 waves), tile 256 (j) x 128 (i); each wave owns a
-// 128 x 64 block as 4 x 2 MFMA tiles of 32 x 32.  K advances 64 per stage
-// through an LDS ring of S stages filled by direct global-to-LDS loads
+// Workgroup: tile 256 (j) x 256 (i), 8 waves (the residue products; two per
+// SIMD, each wave a 128 x 64 block as 4 x 2 MFMA tiles of 32 x 32) or 4 (the
+// bound product; 128 x 128 each).  K advances 64 per stage through an LDS
+// ring of S stages filled by direct global-to-LDS loads
 // (global_load_lds_dwordx4) issued S - 1 stages ahead, so HBM/L2 latency
 // hides behind S - 1 stages of MFMAs; no VGPRs stage the operands.  LDS rows
 // are 64 B with the four 16 B chunks of row r XOR-swizzled by (r >> 2) & 3,
@@ -41,13 +42,9 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr int TJ = 256;                  // tile rows (j, from B's slices)
-constexpr int TI = 128;                  // tile columns (i, from A's slices)
 constexpr int BK = 64;                   // k per stage (one MFMA step)
 constexpr int ROWB = 64;                 // LDS bytes per tile row
 constexpr int BSZ = TJ * ROWB;           // bytes of one B-side slice tile
-constexpr int ASZ = TI * ROWB;           // bytes of one A-side slice tile
-constexpr int LDS_RING = 147456;         // 144 KB: 3 stages of 2 slices or 6 of 1
-static_assert(TI == kGemmTI && TJ == kGemmTJ && BK == kGemmBK, "tile shape");
 
 __device__ __forceinline__ int swz(int r) { return (r >> 2) & 3; }
 
@@ -135,64 +132,15 @@ __device__ __forceinline__ uint32_t lds_offset(const uint8_t *p) {
   return (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const uint8_t *)p;
 }
 
-// Per-lane source offsets of the direct-to-LDS loads within a slice: the
-// instruction for tile rows 16q..16q+15 (q = wave + 4u) has lane L fetch row
-// 16q + L/4, logical chunk (L & 3) ^ swz(row), which lands at physical chunk
-// L & 3 of the row.  ob[u] serve the 256-row B side, oa[u] the 128-row A side.
-// In the k-blocked layout the 16 rows of one load are 1 KB of contiguous
-// memory; sB / sA are the bytes of one 64-k block of all lines of a side.
+// Per-lane source offsets of the direct-to-LDS loads of a wave: ob[u] for
+// its u-th 1 KB load (16 tile rows) on either side.  In the k-blocked layout
+// the 16 rows of one load are 1 KB of contiguous memory; sB / sA are the
+// bytes of one 64-k block of all lines of a side.
 struct DmaOffsets {
-  uint32_t ob[4], oa[2];
+  uint32_t ob[4];
   uint32_t lds_wave;  // 1024 * wave: this wave's first 1 KB in each tile
   int64_t sB, sA;
 };
-
-__device__ __forceinline__ DmaOffsets dma_offsets(int64_t rowsB, int64_t rowsA) {
-  DmaOffsets d;
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int rsub = lane >> 2, pc = lane & 3;
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int r = 16 * (wave + 4 * u) + rsub;
-    d.ob[u] = (uint32_t)(r * 64) + 16u * (uint32_t)(pc ^ swz(r));
-    if (u < 2) d.oa[u] = d.ob[u];
-  }
-  d.lds_wave = 1024u * (uint32_t)wave;
-  d.sB = rowsB * 64;
-  d.sA = rowsA * 64;
-  return d;
-}
-
-// Direct-to-LDS load number `idx` (0 .. 6 NS - 1) of one stage (64 k) of NS
-// slices per side: per slice four 1 KB loads of the 256-row B-side tile and
-// two of the 128-row A-side tile, each filling 16 rows.  `slot` is the LDS
-// byte address of the stage's ring slot; gB[s] / gA[s] point at the tile's
-// first line in k block 0, and the stage starts at k = kofs.
-template <int NS>
-__device__ __forceinline__ void dma_one(int idx, const uint8_t *const *gB,
-                                        const uint8_t *const *gA, const DmaOffsets &d,
-                                        int64_t kofs, uint32_t slot) {
-  const int s = idx / 6, t = idx % 6;
-  const uint32_t w = slot + d.lds_wave;
-  if (t < 4)
-    dma16(gB[s] + (kofs >> 6) * d.sB, d.ob[t], w + s * BSZ + t * 4096);
-  else
-    dma16(gA[s] + (kofs >> 6) * d.sA, d.oa[t - 4], w + NS * BSZ + s * ASZ + (t - 4) * 4096);
-}
-
-// The loads of a stage are issued in four parts; part q is loads
-// [q L / 4, (q + 1) L / 4) with L = 6 NS.
-template <int NS, int Q>
-__device__ __forceinline__ void dma_part(const uint8_t *const *gB, const uint8_t *const *gA,
-                                         const DmaOffsets &d, int64_t kofs, uint32_t slot) {
-  constexpr int L = 6 * NS;
-#pragma unroll
-  for (int idx = Q * L / 4; idx < (Q + 1) * L / 4; ++idx) {
-    dma_one<NS>(idx, gB, gA, d, kofs, slot);
-    __builtin_amdgcn_sched_barrier(0);
-  }
-}
 
 // s_waitcnt vmcnt(a L) for a run-time a in [0, A] (larger a: A L)
 template <int L, int A>
@@ -208,143 +156,6 @@ __device__ __forceinline__ void wait_stages(int a) {
   }
 }
 
-// Register fragments: fa[s][ti] is A-side slice s (0 = x1, 1 = x2), 32-row
-// block ti of this wave's 64 rows; fb[s][tj] is B-side slice s, block tj of
-// its 128 rows.  The i-th of the 6 MFMAs of block row tj: acc0 += A2 B2,
-// acc1 += A1 B2 + A2 B1; two products into one accumulator sit 4 MFMAs apart.
-__device__ __forceinline__ void mfma_i(int i, int tj, const v8i (&fa)[2][2],
-                                       const v8i (&fb)[2][4], v16f (&acc0)[4][2],
-                                       v16f (&acc1)[4][2]) {
-  if (i < 2) acc1[tj][i] = mfma_f8(fb[1][tj], fa[0][i], acc1[tj][i]);
-  else if (i < 4) acc0[tj][i - 2] = mfma_f8(fb[1][tj], fa[1][i - 2], acc0[tj][i - 2]);
-  else acc1[tj][i - 4] = mfma_f8(fb[0][tj], fa[1][i - 4], acc1[tj][i - 4]);
-}
-
-// Accumulate over nk stages of 64 k.  gB[s] / gA[s] point at row j0 / i0 of
-// the s-th B-side / A-side slice.  Stage j sits in ring slot j % S.
-//
-// Schedule of iteration j (four block rows tj of G MFMAs each):
-//   tj = 0..2: first the B-side fragments of block row tj + 1 of stage j are
-//     read, then the MFMAs of block row tj issue with part tj + 1 of the loads
-//     of stage j + S - 1 between them;
-//   barrier B_j: before it each wave waits until its own loads of stage j + 1
-//     have landed and its LDS reads of stage j are complete, so after it
-//     stage j + 1 is readable by all and slot j % S is free;
-//   tj = 3: its MFMAs issue with part 0 of the loads of stage j + S (into
-//     slot j % S) and the reads of stage j + 1's A-side fragments and first
-//     B-side block row between them, so that LDS latency and the barrier hide
-//     behind MFMAs already in registers.
-// Loads are issued S - 2 to S - 1 stages before their barrier; at B_j the
-// loads of stages j + 2 .. j + S - 1 may still be in flight.
-template <int NS>
-__device__ __forceinline__ void stage_iter(int j, int nk, const uint8_t *const *gB,
-                                           const uint8_t *const *gA, const DmaOffsets &d,
-                                           int64_t kbeg, const uint8_t *lds, uint32_t ring,
-                                           const v8i (&fa)[NS][2], v8i (&fan)[NS][2],
-                                           v8i (&fb)[NS][4], v16f (&acc0)[4][2],
-                                           v16f (&acc1)[4][2]) {
-  constexpr int STAGE = NS * (BSZ + ASZ);
-  constexpr int S = NS == 2 ? 3 : 6;
-  constexpr int L = 6 * NS;
-  constexpr int G = 6;
-  static_assert(NS == 2, "square tile: two slices per side");
-  const int wave = threadIdx.x >> 6;
-  const int wj = wave >> 1, wi = wave & 1;
-  const uint8_t *cur = lds + (j % S) * STAGE;
-  const bool ld_prev = j + S - 1 < nk;  // parts 1..3 of stage j + S - 1
-  const bool ld_next = j + S < nk;      // part 0 of stage j + S
-  const bool rd_next = j + 1 < nk;
-  const int64_t kofs_prev = kbeg + (int64_t)(j + S - 1) * BK;
-  const uint32_t slot_prev = ring + ((j + S - 1) % S) * STAGE;
-#pragma unroll
-  for (int tj = 0; tj < 3; ++tj) {
-#pragma unroll
-    for (int s = 0; s < NS; ++s) fb[s][tj + 1] = lds_frag(cur + s * BSZ, wj * 128 + (tj + 1) * 32);
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int i = 0; i < G; ++i) {
-      mfma_i(i, tj, fa, fb, acc0, acc1);
-      __builtin_amdgcn_sched_barrier(0);
-      if (i == 0 && ld_prev) {
-        if (tj == 0) dma_part<NS, 1>(gB, gA, d, kofs_prev, slot_prev);
-        if (tj == 1) dma_part<NS, 2>(gB, gA, d, kofs_prev, slot_prev);
-        if (tj == 2) dma_part<NS, 3>(gB, gA, d, kofs_prev, slot_prev);
-      }
-      __builtin_amdgcn_sched_barrier(0);
-    }
-  }
-  // barrier B_j
-  wait_lgkm0();
-  if (rd_next) {
-    wait_stages<L, S - 2>(nk - 2 - j);
-  }
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_sched_barrier(0);
-  const uint8_t *nxt = lds + ((j + 1) % S) * STAGE;
-#pragma unroll
-  for (int i = 0; i < G; ++i) {
-    mfma_i(i, 3, fa, fb, acc0, acc1);
-    __builtin_amdgcn_sched_barrier(0);
-    if (i == 0 && ld_next)
-      dma_part<NS, 0>(gB, gA, d, kbeg + (int64_t)(j + S) * BK, ring + (j % S) * STAGE);
-    if (rd_next) {
-      // 3 NS fragment reads spread over the G - 1 gaps after MFMAs 0 .. G - 2
-#pragma unroll
-      for (int f = 0; f < 3 * NS; ++f) {
-        if (f * (G - 1) / (3 * NS) != i) continue;
-        if (f < 2 * NS)
-          fan[f / 2][f % 2] = lds_frag(nxt + NS * BSZ + (f / 2) * ASZ, wi * 64 + (f % 2) * 32);
-        else
-          fb[f - 2 * NS][0] = lds_frag(nxt + (f - 2 * NS) * BSZ, wj * 128);
-      }
-    }
-    __builtin_amdgcn_sched_barrier(0);
-  }
-}
-
-template <int NS = 2>
-__device__ __forceinline__ void kloop(const uint8_t *const *gB, const uint8_t *const *gA,
-                                      int64_t rowsB, int64_t rowsA, int64_t kbeg, int nk,
-                                      uint8_t *lds, v16f (&acc0)[4][2], v16f (&acc1)[4][2]) {
-  constexpr int STAGE = NS * (BSZ + ASZ);
-  constexpr int S = NS == 2 ? 3 : 6;
-  constexpr int L = 6 * NS;
-  static_assert(S * STAGE <= LDS_RING, "LDS ring");
-  const int wave = threadIdx.x >> 6;
-  const int wj = wave >> 1, wi = wave & 1;
-  const DmaOffsets d = dma_offsets(rowsB, rowsA);
-  const uint32_t ring = lds_offset(lds);
-  // prologue: stages 0 .. S - 2 and part 0 of stage S - 1
-#pragma unroll
-  for (int t = 0; t < S - 1; ++t)
-    if (t < nk) {
-#pragma unroll
-      for (int idx = 0; idx < L; ++idx)
-        dma_one<NS>(idx, gB, gA, d, kbeg + (int64_t)t * BK, ring + t * STAGE);
-    }
-  if (S - 1 < nk) dma_part<NS, 0>(gB, gA, d, kbeg + (int64_t)(S - 1) * BK, ring + (S - 1) * STAGE);
-  if (S - 1 < nk)
-    wait_vm<(S - 2) * L + L / 4>();
-  else
-    wait_stages<L, S - 2>(nk - 1);
-  __builtin_amdgcn_s_barrier();
-  v8i fa0[NS][2], fa1[NS][2], fb[NS][4];
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-#pragma unroll
-    for (int ti = 0; ti < 2; ++ti) fa0[s][ti] = lds_frag(lds + NS * BSZ + s * ASZ, wi * 64 + ti * 32);
-    fb[s][0] = lds_frag(lds + s * BSZ, wj * 128);
-  }
-  // two stages per trip so that the A-side fragment buffers alternate by
-  // name; nk is a multiple of 4 (k is padded to 256), so there is no tail
-  for (int j = 0; j < nk; j += 2) {
-    stage_iter<NS>(j, nk, gB, gA, d, kbeg, lds, ring, fa0, fa1, fb, acc0, acc1);
-    stage_iter<NS>(j + 1, nk, gB, gA, d, kbeg, lds, ring, fa1, fa0, fb, acc0, acc1);
-  }
-  // the ring is free for the next use only when every wave is done with it
-  __builtin_amdgcn_s_barrier();
-}
-
 // Values the epilogue needs are loaded with scalar loads, which complete out
 // of order with LDS reads on the shared LGKM counter: while one is pending,
 // every LDS wait in the K-loop degrades to a full drain.  Consuming them in an
@@ -354,15 +165,6 @@ __device__ __forceinline__ void resident(int a, int b, int c, int d) {
 }
 __device__ __forceinline__ void resident_ptr(const void *a, const void *b) {
   asm volatile("" ::"s"(a), "s"(b));
-}
-
-__device__ __forceinline__ void zero_acc(v16f (&a)[4][2]) {
-#pragma unroll
-  for (int tj = 0; tj < 4; ++tj)
-#pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) a[tj][ti][v] = 0.0f;
 }
 
 // Symmetric remainder of |v| < 2^31 modulo p, in [-floor(p/2), ceil(p/2) - 1].
@@ -378,69 +180,21 @@ __device__ __forceinline__ int smod_i32(int v, int p, float inv_p) {
   return r;
 }
 
-// One 256 x 128 output tile (j0.., i0..) of square modulus l (p = s^2) over
-// k in [kbeg, kbeg + 64 nk): the three digit products in two accumulators,
-// acc0 = A2 B2 and acc1 = A1 B2 + A2 B1, then s acc1 + acc0 reduced modulo p
-// (eq. 3matmult-notKaratsuba; s^2 A1 B1 vanishes modulo s^2).
-// (operand pointers carry no __restrict__: the prefetch fence in kloop must be
-// able to order their loads)
-__device__ __forceinline__ void square_tile(const uint8_t *Asl, const uint8_t *Bsl,
-                                            int16_t *__restrict__ planes,
-                                            const Tables *__restrict__ tab, int64_t mp,
-                                            int64_t np, int64_t kp, int64_t kbeg, int nk,
-                                            int accumulate, int l, int64_t i0, int64_t j0,
-                                            uint8_t *lds) {
-  const int sl0 = (int)uni(tab->slice0[l]);
-  const int p = (int)uni(tab->p[l]);
-  const float inv = __int_as_float((int)uni(__float_as_int(tab->inv_p[l])));
-  const int s = (int)uni(tab->s[l]);
-  resident(sl0, p, __float_as_int(inv), s);
-  resident_ptr(planes, planes);
-  resident(accumulate, accumulate, accumulate, accumulate);
-  const int64_t sA = mp * kp, sB = np * kp;
-  const uint8_t *A0 = Asl + (int64_t)sl0 * sA + i0 * 64;
-  const uint8_t *B0 = Bsl + (int64_t)sl0 * sB + j0 * 64;
-
-  v16f acc0[4][2], acc1[4][2];
-  zero_acc(acc0);
-  zero_acc(acc1);
-  const uint8_t *gB[2] = {B0, B0 + sB};
-  const uint8_t *gA[2] = {A0, A0 + sA};
-  kloop(gB, gA, np, mp, kbeg, nk, lds, acc0, acc1);
-
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wj = wave >> 1, wi = wave & 1;
-  int16_t *out = planes + (int64_t)l * np * mp;
-  // accumulator element (tj, ti, v) of this lane is entry (i, j) of C'_l
-#pragma unroll
-  for (int tj = 0; tj < 4; ++tj)
-#pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        int r = smod_i32(s * (int)acc1[tj][ti][v] + (int)acc0[tj][ti][v], p, inv);
-        const int64_t i = i0 + wi * 64 + ti * 32 + (lane & 31);
-        const int64_t j = j0 + wj * 128 + tj * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-        int16_t *dst = out + j * mp + i;
-        if (accumulate) r = smod_i32(r + (int)*dst, p, inv);
-        *dst = (int16_t)r;
-      }
-}
-
 // ---------------------------------------------------------------------------
-// Wide single-product tiles: 256 (j) x 256 (i) per workgroup in one
-// accumulator per wave.  The residue products run 8 waves (two per SIMD, so
-// one wave's MFMAs cover the other's barrier and LDS waits), each a 128 x 64
-// block as 4 x 2 MFMA tiles (128 AGPRs); the bound product runs 4 waves of
-// 128 x 128 (256 AGPRs).  Per 64-k stage the workgroup moves 32 KB into LDS
-// and reads at most 1.5 KB of fragments per MFMA, below the LDS rate; the
-// 256 x 128 two-accumulator tile above is kept for the square moduli, whose
-// three products share two operand slices per side.
+// Wide single-product tiles: 256 (j) x 256 (i) per workgroup, one product
+// per pass into one accumulator per wave.  The residue products run 8 waves
+// (two per SIMD, so one wave's MFMAs cover the other's barrier and LDS
+// waits), each a 128 x 64 block as 4 x 2 MFMA tiles (128 AGPRs); the bound
+// product runs 4 waves of 128 x 128 (256 AGPRs).  Per 64-k stage the
+// workgroup moves 32 KB into LDS and reads at most 1.5 KB of fragments per
+// MFMA, below the LDS rate.
 // ---------------------------------------------------------------------------
 constexpr int TIW = 256;                 // wide tile: i extent
 constexpr int ASZW = TIW * ROWB;         // bytes of one A-side tile
 constexpr int STAGEW = BSZ + ASZW;       // 32 KB per stage
 constexpr int SW = 4;                    // ring slots
+constexpr int LDS_RING = SW * STAGEW;    // 128 KB
+static_assert(TIW == kGemmTIW && TJ == kGemmTJ && BK == kGemmBK, "tile shape");
 // A wide workgroup has NW = 4 waves (one per SIMD, each 128 x 128) or 8 (two
 // per SIMD, each 128 x 64, half the accumulator registers); per wave TB(NW)
 // i blocks of 32 rows and LP(NW) 1 KB loads per side and stage.
@@ -448,7 +202,6 @@ constexpr int NW_RES = 8;                // the residue products
 constexpr int NW_BOUND = 4;              // the bound product
 template <int NW> constexpr int TB() { return 16 / NW; }
 template <int NW> constexpr int LP() { return 16 / NW; }
-static_assert(SW * STAGEW <= LDS_RING, "wide ring");
 
 // Lane offsets of the wide loads: wave w loads rows 16 (w + NWW u) .. + 15 of
 // each side for u < LPW (both sides have 256 rows).
@@ -495,11 +248,20 @@ __device__ __forceinline__ void dma_part_w(const uint8_t *gB, const uint8_t *gA,
   }
 }
 
-// One stage of the wide loop, scheduled as stage_iter (block rows tj of TBW
-// MFMA steps; barrier B_j before the last block row; loads in four parts).
-// Wave w owns j rows 128 (w / (NWW / 2)) .. + 127 and i rows
-// 32 TBW (w % (NWW / 2)) .. + 32 TBW - 1.  ACC is v16f (FP8 products) or v16i
-// (INT8 products).
+// One stage j of the wide loop (stage j sits in ring slot j % SW).  Wave w
+// owns j rows 128 (w / (NWW / 2)) .. + 127 and i rows 32 TBW (w % (NWW / 2))
+// .. + 32 TBW - 1; ACC is v16f (FP8 products) or v16i (INT8 products).
+// Schedule, over the four block rows tj of TBW MFMAs each:
+//   tj = 0..2: the B-side fragment of block row tj + 1 is read, then the
+//     MFMAs of block row tj issue with part tj + 1 of the loads of stage
+//     j + SW - 1 after the first of them;
+//   barrier B_j: before it each wave waits until its own loads of stage j + 1
+//     have landed and its LDS reads of stage j are complete, so after it
+//     stage j + 1 is readable by all and slot j % SW is free;
+//   tj = 3: its MFMAs issue with part 0 of the loads of stage j + SW (into
+//     slot j % SW) and the reads of stage j + 1's A-side fragments and first
+//     B-side block row between them, so that LDS latency and the barrier hide
+//     behind MFMAs already in registers.
 template <int NW, class ACC>
 __device__ __forceinline__ void stage_iter_w(int j, int nk, const uint8_t *gB, const uint8_t *gA,
                                              const DmaOffsets &d, int64_t kbeg,
@@ -702,6 +464,96 @@ __device__ __forceinline__ void karatsuba_tile_w(const uint8_t *Asl, const uint8
     }
 }
 
+// acc = s (acc mod s) for a square modulus p = s^2, one 16-value MFMA tile at
+// a time, in FP32: the first pass sums X = A1 B2 + A2 B1, of which only
+// s X mod s^2 = s (X mod s) matters.  As in fold_w, x - rint(x s^-1) s is an
+// exact representative with |.| <= s/2 + 2, so |acc| <= s (s/2 + 2) < 2^10.
+template <int TBW>
+__device__ __forceinline__ void fold_s(v16f (&acc)[4][TBW], int s, float inv_s) {
+  const float sf = (float)s;
+  pin_agpr(acc);
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+    for (int ti = 0; ti < TBW; ++ti) {
+      v16f t16;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const float x = acc[tj][ti][v];
+        t16[v] = fmaf(-rintf(x * inv_s), sf, x) * sf;
+      }
+      acc[tj][ti] = t16;
+      asm volatile("" : "+a"(acc[tj][ti]));
+      __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// One 256 x 256 tile (j0.., i0..) of square modulus l (p = s^2, Section
+// III-C) over k in [kbeg, kbeg + 64 nk), three single-product passes in one
+// accumulator.  With A = A1 s + A2 and B = B1 s + B2, A B = s^2 A1 B1 +
+// s (A1 B2 + A2 B1) + A2 B2 (eq. 3matmult-notKaratsuba), and the first term
+// vanishes modulo s^2:
+//   passes 1, 2: acc = A1 B2 + A2 B1;  fold: acc = s (acc mod s)
+//   pass 3:      acc += A2 B2;         result smod(acc)
+// The residue has |u| <= s^2 / 2 and s <= 33, so |A1| = |round(u / s)| <= 16
+// and |A2| <= s / 2, i.e. <= 16: over a k chunk of at most 2^15 the first two
+// passes sum to at most 2 (16^2) 2^15 = 2^24 in magnitude, the third adds at
+// most 2^23 to |acc| < 2^10, and every partial sum is an exact FP32 integer.
+__device__ __forceinline__ void square_tile_w(const uint8_t *Asl, const uint8_t *Bsl,
+                                              int16_t *__restrict__ planes,
+                                              const Tables *__restrict__ tab, int64_t mp,
+                                              int64_t np, int64_t kp, int64_t kbeg, int nk,
+                                              int accumulate, int l, int64_t i0, int64_t j0,
+                                              uint8_t *lds) {
+  const int sl0 = (int)uni(tab->slice0[l]);
+  const int p = (int)uni(tab->p[l]);
+  const float inv = __int_as_float((int)uni(__float_as_int(tab->inv_p[l])));
+  const int s = (int)uni(tab->s[l]);
+  const float inv_s = __int_as_float((int)uni(__float_as_int(tab->inv_s[l])));
+  resident(sl0, p, __float_as_int(inv), s);
+  resident(__float_as_int(inv_s), s, s, s);
+  resident_ptr(planes, planes);
+  resident(accumulate, accumulate, accumulate, accumulate);
+  const int64_t sA = mp * kp, sB = np * kp;
+  const uint8_t *A0 = Asl + (int64_t)sl0 * sA + i0 * 64;
+  const uint8_t *B0 = Bsl + (int64_t)sl0 * sB + j0 * 64;
+
+  constexpr int NWW = NW_RES, TBW = TB<NW_RES>();
+  v16f acc[4][TBW];
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+    for (int ti = 0; ti < TBW; ++ti)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[tj][ti][v] = 0.0f;
+
+  pin_agpr(acc);
+  kloop_w<NWW>(B0 + sB, A0, np, mp, kbeg, nk, lds, acc);       // A1 B2
+  pin_agpr(acc);
+  kloop_w<NWW>(B0, A0 + sA, np, mp, kbeg, nk, lds, acc);       // + A2 B1
+  fold_s(acc, s, inv_s);
+  kloop_w<NWW>(B0 + sB, A0 + sA, np, mp, kbeg, nk, lds, acc);  // + A2 B2
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wj = wave / (NWW / 2), wi = wave % (NWW / 2);
+  int16_t *out = planes + (int64_t)l * np * mp;
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+    for (int ti = 0; ti < TBW; ++ti) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        int r = smod_i32((int)acc[tj][ti][v], p, inv);
+        const int64_t i = i0 + wi * 32 * TBW + ti * 32 + (lane & 31);
+        const int64_t j = j0 + wj * 128 + tj * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+        int16_t *dst = out + j * mp + i;
+        if (accumulate) r = smod_i32(r + (int)*dst, p, inv);
+        *dst = (int16_t)r;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 // One 256 x 256 tile (j0.., i0..) of INT8 modulus l (Section II) over k in
 // [kbeg, kbeg + 64 nk): the one product of the INT8 residues, accumulated in
 // INT32 (|u| <= 128, so a chunk of k <= 2^15 sums to at most 2^29), then
@@ -759,7 +611,7 @@ __device__ __forceinline__ void int8_tile_w(const uint8_t *Asl, const uint8_t *B
 // l = nsq + nka + z).
 // A grouped launch may run fewer workgroups than tiles; each then loops.
 template <int KIND, bool GROUPED>
-__global__ __launch_bounds__(KIND == 0 ? 256 : 64 * NW_RES, 1) void k_residue_gemm(Problem P1,
+__global__ __launch_bounds__(64 * NW_RES, 1) void k_residue_gemm(Problem P1,
                                                                                Group G,
                                                                                int chunk) {
   __shared__ __attribute__((aligned(1024))) uint8_t lds[LDS_RING];
@@ -776,8 +628,9 @@ __global__ __launch_bounds__(KIND == 0 ? 256 : 64 * NW_RES, 1) void k_residue_ge
     const int64_t len = kp - kbeg < kChunkK ? kp - kbeg : kChunkK;
     const int l = (int)uni((KIND == 0 ? 0 : (KIND == 1 ? g.nsq : g.nsq + g.nka)) + c.z);
     if (KIND == 0)
-      square_tile(uni(P.w.Asl), uni(P.w.Bsl), uni(P.w.planes), uni(P.tab), mp, np, kp, kbeg,
-                  (int)(len / BK), chunk > 0 ? 1 : 0, l, uni(c.x * TI), uni(c.y * TJ), lds);
+      square_tile_w(uni(P.w.Asl), uni(P.w.Bsl), uni(P.w.planes), uni(P.tab), mp, np, kp,
+                    kbeg, (int)(len / BK), chunk > 0 ? 1 : 0, l, uni(c.x * TIW), uni(c.y * TJ),
+                    lds);
     else if (KIND == 1)
       karatsuba_tile_w(uni(P.w.Asl), uni(P.w.Bsl), uni(P.w.planes), uni(P.tab), mp, np, kp,
                        kbeg, (int)(len / BK), chunk > 0 ? 1 : 0, l, uni(c.x * TIW),
@@ -875,7 +728,7 @@ hipError_t launch_gemm_family(int fam, const Problem *P, const Group *G, int chu
   if (grouped && grid > 0 && grid < tiles) blocks = grid;
   if (blocks > 0x7FFFFFFFll) return hipErrorInvalidValue;
   const dim3 gr((unsigned)blocks),
-      blk(fam == kFamGemmSq ? 256 : (fam == kFamBgemm ? 64 * NW_BOUND : 64 * NW_RES));
+      blk(fam == kFamBgemm ? 64 * NW_BOUND : 64 * NW_RES);
   switch (fam) {
     case kFamBgemm:
       if (grouped)

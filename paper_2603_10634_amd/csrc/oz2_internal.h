@@ -114,7 +114,6 @@ __host__ __device__ inline int64_t kblocked(int64_t r, int64_t h, int64_t R) {
 }
 
 // Tile shapes of the kernels (the block grids below depend on them).
-constexpr int kGemmTI = 128;  // residue / bound products: output rows i per tile
 constexpr int kGemmTJ = 256;  // output columns j per tile
 constexpr int kGemmTIW = 256; // output rows i per tile of the single-product kernels
                               // (Karatsuba products, bound product)
@@ -211,7 +210,7 @@ __host__ __device__ inline Dims family_dims(int fam, const Problem &P, int chunk
     case kFamGemmKa:
     case kFamGemmI8: {
       if ((int64_t)chunk * kChunkK >= g.kp) return {0, 1, 1};
-      if (fam == kFamGemmSq) return {g.mp / kGemmTI, g.np / kGemmTJ, g.nsq};
+      if (fam == kFamGemmSq) return {g.mp / kGemmTIW, g.np / kGemmTJ, g.nsq};
       if (fam == kFamGemmKa) return {g.mp / kGemmTIW, g.np / kGemmTJ, g.nka};
       return {g.mp / kGemmTIW, g.np / kGemmTJ, g.N - g.nsq - g.nka};
     }

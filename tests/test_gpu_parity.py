@@ -204,6 +204,44 @@ def test_extreme_digit_sums_exact():
     assert _same(r.C, Chat)
 
 
+def _square_extreme_value(shift, base=1.0625, target=544, p=1089):
+    """A value v in (1, 1.125] (so its round-up FP8 bound, and with it the
+    scale shift, stays that of `base`) whose scaled integer trunc(v 2^shift)
+    is congruent to `target` modulo p."""
+    g = max(int(shift) - 52, 0)
+    t0 = int(base * 2.0 ** (int(shift) - g))
+    t = t0 - t0 % p + target * pow(2 ** g, -1, p) % p
+    if t < t0:
+        t += p
+    return float(np.ldexp(float(t), g - int(shift)))
+
+
+def test_square_cross_sums_reach_2_24():
+    # Residues 544 = 16 * 33 + 16 modulo 1089 on both sides give the square
+    # digits (16, 16), so A1 B2 + A2 B1 = 512 per k: over k = 2^15 the square
+    # kernel's first two passes sum to exactly +-2^24 in FP32 (rows of both
+    # signs), then fold and add A2 B2 = 256 k.
+    k = 32768
+    one = np.full((1, k), 1.0625)
+    sc = ref.scaling(one, one.T.copy(), 12)
+    v = _square_extreme_value(sc["sA"][0])
+    w = _square_extreme_value(sc["sB"][0])
+    A = np.full((64, k), v)
+    B = np.full((k, 96), w)
+    A[1::2] *= -1.0
+    print(f"square cross sums k={k} v={v!r} w={w!r}", flush=True)
+    Chat, st = ref.emulate(A, B, 12, keep_stages=True)
+    pm = next(q for q in st["per_modulus"] if q["p"] == 1089)
+    a1, a2 = int(pm["dA"][0][0, 0]), int(pm["dA"][1][0, 0])
+    b1, b2 = int(pm["dB"][0][0, 0]), int(pm["dB"][1][0, 0])
+    assert (a1, a2, b1, b2) == (16, 16, 16, 16)
+    assert (int(pm["dA"][0][1, 0]), int(pm["dA"][1][1, 0])) == (-16, -16)
+    r = run(A, B, 12, keep_ws=True)
+    assert r.status == 0
+    check_stages(r, A, B, 12, st)
+    assert _same(r.C, Chat)
+
+
 def _bound_case(kind):
     if kind == "spread":
         return _inputs(300, 280, 1000, 2.0, 7000)

@@ -1,9 +1,10 @@
 // Chinese-remainder reconstruction and inverse scaling (eqs.
 // CRT_finalreduction, inversescaling), fused with alpha/beta.
 //
-// Per output entry (i, j): u_l = C'_l mod p_l in [0, p_l) from the int16
-// planes; S = sum_l w_l u_l + floor(P/2) in 32-bit limbs (exact); R = S mod P;
-// C' = R - floor(P/2), which lies in (-P/2, P/2) by condition (3).  Then
+// Per output entry (i, j): the residues u_l = C'_l (symmetric range) from the
+// int16 planes; S = sum_l w_l u_l in 32-bit limbs held as exact FP64
+// integers; C' = S mods P, the representative in [-floor(P/2),
+// P - 1 - floor(P/2)], which is the product itself by condition (3).  Then
 // Chat = C' 2^-(log2 mu_i + log2 nu_j) rounded once to nearest-even,
 // including gradual underflow, directly from the integer: no intermediate
 // floating-point rounding.  C = RN(alpha Chat) (+ RN(beta C_in)).
@@ -71,6 +72,88 @@ __device__ __forceinline__ double scaled_rn(const uint32_t (&X)[L], int t) {
   return ldexp((double)Q, lsb - t);
 }
 
+// D = sum_q r[q] 2^(32 q) for integers |r[q]| < 2^49 and |D| < 2^(32 L): its
+// magnitude in 32-bit limbs, its sign, and an estimate d of D.  The carries
+// are exact (x - 2^32 floor(x 2^-32) by one fused multiply-add); the last one
+// is -1 or 0, the sign.  d is Horner's rule over the normalised limbs, whose
+// partial values are floor(D 2^-32q): |d - D| <= 2^-53 (L |D| + 2^(32 L - 31)).
+template <int L>
+__device__ __forceinline__ bool crt_normalize(const double (&r)[L], uint32_t (&mag)[L],
+                                              double &d) {
+  double lo[L];
+  double c = 0.0;
+#pragma unroll
+  for (int q = 0; q < L; ++q) {
+    const double x = r[q] + c;
+    const double hi = floor(x * 0x1p-32);
+    lo[q] = fma(-hi, 0x1p32, x);
+    c = hi;
+  }
+  d = c;
+#pragma unroll
+  for (int q = L - 1; q >= 0; --q) d = fma(d, 0x1p32, lo[q]);
+  const bool neg = c < 0.0;
+  // |D| = 2^(32 L) - sum lo[q] 2^(32 q) when D < 0: a borrow chain from 0
+  uint32_t borrow = 0;
+#pragma unroll
+  for (int q = 0; q < L; ++q) {
+    const uint32_t u = (uint32_t)lo[q];
+    const uint32_t v = 0u - u - borrow;
+    borrow = (u | borrow) != 0u ? 1u : 0u;
+    mag[q] = neg ? v : u;
+  }
+  return neg;
+}
+
+// x > y for L-limb numbers.
+template <int L>
+__device__ __forceinline__ bool limbs_greater(const uint32_t (&x)[L], const uint32_t *y) {
+  bool gt = false, decided = false;
+#pragma unroll
+  for (int q = L - 1; q >= 0; --q) {
+    if (!decided && x[q] != y[q]) {
+      gt = x[q] > y[q];
+      decided = true;
+    }
+  }
+  return gt;
+}
+
+// C' = S mods P (the representative in [-floor(P/2), P - 1 - floor(P/2)])
+// for S = sum_q acc[q] 2^(32 q), |acc[q]| < 2^47: its magnitude in mag and
+// its sign as the result.  P has L <= 10 limbs and |S| < 2^15 P.
+//   Q = rint(S / P) from S by Horner's rule times 1/P: the rounding errors
+//     add up to less than 2^-53 (L |S| / P + 2^16) + 2^-51 |S| / P < 2^-33
+//     in S / P, so Q is the nearest integer, or one off when S / P is
+//     within 2^-33 of a half-integer;
+//   D = S - Q P limb by limb, exactly (|Q P_q| < 2^47);
+//   if the estimate of D is at most crt_fast = P (1/2 - 2^-40) - 2 in
+//   magnitude, D is C' (the estimate is within 2^-53 (L |D| + 2 P) < 2^-49 P
+//   of D, so |D| < floor(P/2) - 1); otherwise D is compared with the range
+//   exactly and moved by P when it lies outside.
+template <int L>
+__device__ __forceinline__ bool crt_reduce(const double (&acc)[L], const Tables *__restrict__ tab,
+                                           uint32_t (&mag)[L]) {
+  double sa = acc[L - 1];
+#pragma unroll
+  for (int q = L - 2; q >= 0; --q) sa = fma(sa, 0x1p32, acc[q]);
+  const double Q = rint(sa * tab->inv_P_d);
+  double r[L];
+#pragma unroll
+  for (int q = 0; q < L; ++q) r[q] = fma(-Q, tab->Pdl[q], acc[q]);
+  double d;
+  bool neg = crt_normalize<L>(r, mag, d);
+  if (fabs(d) > tab->crt_fast) {
+    // D >= 0 must not exceed P - 1 - floor(P/2), D < 0 not -floor(P/2)
+    if (limbs_greater<L>(mag, neg ? tab->half : tab->top)) {
+#pragma unroll
+      for (int q = 0; q < L; ++q) r[q] += neg ? tab->Pdl[q] : -tab->Pdl[q];
+      neg = crt_normalize<L>(r, mag, d);
+    }
+  }
+  return neg;
+}
+
 // NF > 0: the number of moduli is the compile-time NF (no per-modulus
 // branches); NF = 0: N at run time.
 template <int L, int NF>
@@ -87,12 +170,14 @@ __device__ __forceinline__ void crt_entry(const int16_t *__restrict__ planes,
   if (bad) {
     chat = __longlong_as_double(0x7FF8000000000000ll);
   } else {
-    // S = sum_l w_l u_l + floor(P/2), accumulated per 32-bit limb in FP64
-    // (full rate on this GPU, unlike 64-bit integer multiply-adds): every
-    // limb sum stays below 2^32 (1 + 33 * 1089) < 2^48, so it is exact
+    // S = sum_l w_l u_l over the stored residues u_l (C'_l in the symmetric
+    // range; any representative changes S by a multiple of P), accumulated
+    // per 32-bit limb in FP64 (full rate on this GPU, unlike 64-bit integer
+    // multiply-adds): |w_l,q u_l| < 2^42, so every limb sum of at most
+    // kMaxN terms is an exact integer below 2^47
     double acc[L];
 #pragma unroll
-    for (int q = 0; q < L; ++q) acc[q] = (double)tab->half[q];
+    for (int q = 0; q < L; ++q) acc[q] = 0.0;
     const int16_t *pl = planes + j * mp + i;
     const int64_t pstride = mp * np;
     // all N residues are requested before the first is used
@@ -108,94 +193,16 @@ __device__ __forceinline__ void crt_entry(const int16_t *__restrict__ planes,
 #pragma unroll
     for (int l = 0; l < kMaxN; ++l) {
       if (l < NN) {
-        const int u = uu[l] + (tab->p[l] & (uu[l] >> 31));  // C'_l mod p_l in [0, p_l)
-        const double ud = (double)u;
+        const double ud = (double)uu[l];
 #pragma unroll
         for (int q = 0; q < L; ++q) acc[q] = fma(tab->wd[l][q], ud, acc[q]);
       }
     }
-    // carry-propagate into 32-bit limbs: t = acc + carry < 2^49, split exactly
-    uint32_t S[L + 1];
-    double carry = 0.0;
-#pragma unroll
-    for (int q = 0; q < L; ++q) {
-      const double t = acc[q] + carry;
-      const double hi = floor(t * 0x1p-32);
-      S[q] = (uint32_t)fma(-hi, 0x1p32, t);
-      carry = hi;
-    }
-    S[L] = (uint32_t)carry;
-    // quotient estimate t ~ S / P (S < 2^16 P), then R = S - t P, corrected once
-    double sd = 0.0;
-#pragma unroll
-    for (int q = 0; q <= L; ++q) sd += ldexp((double)S[q], 32 * q);
-    int64_t tq = (int64_t)floor(sd * tab->inv_P_d);
-    if (tq < 0) tq = 0;
-    uint32_t R[L + 1];
-    int64_t borrow = 0;
-    uint64_t mulc = 0;
-#pragma unroll
-    for (int q = 0; q <= L; ++q) {
-      const uint64_t pq = (q < L) ? (uint64_t)tab->P[q] : 0ull;
-      const uint64_t prod = pq * (uint64_t)tq + mulc;
-      mulc = prod >> 32;
-      const int64_t d = (int64_t)S[q] - (int64_t)(uint32_t)prod + borrow;
-      R[q] = (uint32_t)d;
-      borrow = d >> 32;  // 0 or -1
-    }
-    // R is now S - tq P as a two's-complement (L+1)-limb number
-    const bool negR = (R[L] >> 31) != 0;
-    if (negR) {  // add P back
-      uint64_t c = 0;
-#pragma unroll
-      for (int q = 0; q <= L; ++q) {
-        const uint64_t t = (uint64_t)R[q] + ((q < L) ? tab->P[q] : 0u) + c;
-        R[q] = (uint32_t)t;
-        c = t >> 32;
-      }
-    } else {  // subtract P if R >= P
-      bool ge = R[L] != 0;
-      bool decided = ge;
-#pragma unroll
-      for (int q = L - 1; q >= 0; --q) {
-        if (!decided && R[q] != tab->P[q]) {
-          ge = R[q] > tab->P[q];
-          decided = true;
-        }
-      }
-      if (!decided) ge = true;  // equal
-      if (ge) {
-        int64_t b = 0;
-#pragma unroll
-        for (int q = 0; q <= L; ++q) {
-          const int64_t d = (int64_t)R[q] - (int64_t)((q < L) ? tab->P[q] : 0u) + b;
-          R[q] = (uint32_t)d;
-          b = d >> 32;
-        }
-      }
-    }
-    // C' = R - floor(P/2): magnitude and sign
-    bool ge = false, decided = false;
-#pragma unroll
-    for (int q = L - 1; q >= 0; --q) {
-      if (!decided && R[q] != tab->half[q]) {
-        ge = R[q] > tab->half[q];
-        decided = true;
-      }
-    }
-    if (!decided) ge = true;
     uint32_t mag[L];
-    int64_t b = 0;
-#pragma unroll
-    for (int q = 0; q < L; ++q) {
-      const int64_t d = ge ? (int64_t)R[q] - (int64_t)tab->half[q] + b
-                           : (int64_t)tab->half[q] - (int64_t)R[q] + b;
-      mag[q] = (uint32_t)d;
-      b = d >> 32;
-    }
+    const bool negative = crt_reduce<L>(acc, tab, mag);
     const int t = shift[i] + shift[lineB + j];
     chat = scaled_rn<L>(mag, t);
-    if (!ge) chat = -chat;
+    if (negative) chat = -chat;
   }
   double out = __dmul_rn(alpha, chat);
   if (beta != 0.0) out = __dadd_rn(out, __dmul_rn(beta, C[i + j * ldc]));

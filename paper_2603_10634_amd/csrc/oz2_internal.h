@@ -41,6 +41,9 @@ struct Tables {
   double wd[kMaxN][kLimbs];   // the same limbs as doubles (exact)
   uint32_t P[kLimbs];         // product of the moduli
   uint32_t half[kLimbs];      // floor(P / 2)
+  uint32_t top[kLimbs];       // P - 1 - floor(P / 2): the largest C'
+  double Pdl[kLimbs];         // the limbs of P as doubles (exact)
+  double crt_fast;            // |C'| estimates up to this are surely in range
   double P_d;                 // P rounded to double
   double inv_P_d;             // 1 / P_d (estimate of quotients S / P)
   double D;                   // largest double <= P - 1 (scale rule)

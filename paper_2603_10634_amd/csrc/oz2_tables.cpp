@@ -201,6 +201,17 @@ bool build_tables(int N, int list, Tables *t) {
   Big half = P;
   big_shr1(half);
   for (size_t i = 0; i < half.size(); ++i) t->half[i] = half[i];
+  // top = P - 1 - half, limb by limb with borrows (P > half)
+  {
+    int64_t borrow = 0;
+    for (int i = 0; i < limbs; ++i) {
+      int64_t d = (int64_t)P[i] - (i < (int)half.size() ? (int64_t)half[i] : 0) - borrow -
+                  (i == 0 ? 1 : 0);
+      borrow = d < 0 ? 1 : 0;
+      t->top[i] = (uint32_t)(d + (borrow << 32));
+    }
+    for (int i = 0; i < limbs; ++i) t->Pdl[i] = (double)P[i];
+  }
   for (int l = 0; l < N; ++l) {
     Big others{1};
     for (int j = 0; j < N; ++j)
@@ -215,6 +226,9 @@ bool build_tables(int N, int list, Tables *t) {
   }
   t->P_d = big_to_double(P, true);
   t->inv_P_d = 1.0 / t->P_d;
+  // an estimate of C' within 2^-48 P of it (see the CRT) that is at most this
+  // is below floor(P/2) - 1 in magnitude, so C' needs no range correction
+  t->crt_fast = t->P_d * (0.5 - 0x1p-40) - 2.0;
   Big Pm1 = P;
   big_sub_one(Pm1);
   t->D = big_to_double(Pm1, false);

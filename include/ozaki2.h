@@ -85,7 +85,8 @@ extern "C" {
  * Quick returns: m == 0 or n == 0 does nothing; k == 0 or alpha == 0 sets
  * C <- beta*C (C <- 0, unread, when beta == 0).  A row of op(A) or column of
  * op(B) holding Inf or NaN yields NaN in every entry of C it contributes to.
- * k > OZ2_MAX_K returns OZ2_ERR_UNSUPPORTED.
+ * k > OZ2_MAX_K returns OZ2_ERR_UNSUPPORTED, and so does m, n or k above
+ * 2^40 or a workspace size that does not fit in size_t.
  * Argument indices for -i: 1 transA, 2 transB, 3 m, 4 n, 5 k, 8 lda, 10 ldb,
  * 13 ldc, 14 num_moduli.
  */
@@ -101,7 +102,8 @@ int ozaki2_dgemm(char transA, char transB, int64_t m, int64_t n, int64_t k,
  * operands, one int16 residue plane per modulus and per-line vectors, for
  * the calling thread's modulus list (ozaki2_set_moduli_list) and m/n
  * blocking (ozaki2_set_blocking: slices and planes then cover one block).
- * Returns 0 for invalid sizes.
+ * Returns 0 for invalid sizes, for m, n or k above 2^40 and when the size
+ * does not fit in size_t.
  */
 size_t ozaki2_workspace_bytes(int64_t m, int64_t n, int64_t k, int num_moduli);
 
@@ -235,7 +237,8 @@ int ozaki2_dgemm_batched(int count, const char *transA, const char *transB,
 
 /* ozaki2_workspace_bytes_batched - workspace for running the whole batch as
  * one sub-batch (the sum of ozaki2_workspace_bytes over problems with
- * m, n, k > 0); 0 for invalid sizes. */
+ * m, n, k > 0); 0 for invalid sizes and when a problem's size or the sum
+ * does not fit in size_t. */
 size_t ozaki2_workspace_bytes_batched(int count, const int64_t *m, const int64_t *n,
                                       const int64_t *k, int num_moduli);
 

@@ -89,6 +89,11 @@ bool make_layout(int64_t m, int64_t n, int64_t k, int N, Layout *L, int64_t mb =
   const Tables *ht = host_tables(N, g_ts.list);
   if (!ht) return false;
   const Tables &t = *ht;
+  // extents beyond any device memory are refused before they are padded, and
+  // every size below is formed with overflow checks: a wrapped size would
+  // pass for a small workspace and let the kernels write past it
+  constexpr int64_t kMaxExtent = (int64_t)1 << 40;
+  if (m > kMaxExtent || n > kMaxExtent || k > kMaxExtent) return false;
   L->mp = round_up(m > 0 ? m : 1, kPad);
   L->np = round_up(n > 0 ? n : 1, kPad);
   L->kp = round_up(k > 0 ? k : 1, kPad);
@@ -97,9 +102,16 @@ bool make_layout(int64_t m, int64_t n, int64_t k, int N, Layout *L, int64_t mb =
   L->M = t.M;
   const int64_t lines = L->mp + L->np;
   size_t o = 0;
+  bool ok = true;
+  auto size3 = [&](size_t a, size_t b, size_t c) -> size_t {
+    size_t ab = 0, abc = 0;
+    if (__builtin_mul_overflow(a, b, &ab) || __builtin_mul_overflow(ab, c, &abc)) ok = false;
+    return abc;
+  };
   auto take = [&](int idx, size_t bytes) {
     L->off[idx] = o;
-    o += (bytes + 255) / 256 * 256;
+    const size_t padded = bytes / 256 * 256 + (bytes % 256 ? 256 : 0);
+    if (padded < bytes || __builtin_add_overflow(o, padded, &o)) ok = false;
   };
   // zero-initialised group
   take(10, sizeof(uint64_t) * lines);          // amax
@@ -111,16 +123,16 @@ bool make_layout(int64_t m, int64_t n, int64_t k, int N, Layout *L, int64_t mb =
   take(0, sizeof(int32_t) * lines);            // shift
   take(1, sizeof(int32_t) * lines);            // E
   take(2, sizeof(int32_t) * lines);            // e
-  take(3, (size_t)(L->mp * L->kp));            // Abar
-  take(4, (size_t)(L->np * L->kp));            // Bbar
-  take(5, (size_t)t.M * L->mbp * L->kp);       // A slices (one block)
-  take(6, (size_t)t.M * L->nbp * L->kp);       // B slices
-  take(7, sizeof(int16_t) * (size_t)N * L->mbp * L->nbp);  // planes
+  take(3, size3(L->mp, L->kp, 1));             // Abar
+  take(4, size3(L->np, L->kp, 1));             // Bbar
+  take(5, size3(t.M, L->mbp, L->kp));          // A slices (one block)
+  take(6, size3(t.M, L->nbp, L->kp));          // B slices
+  take(7, size3(sizeof(int16_t) * N, L->mbp, L->nbp));  // planes
   L->off[8] = L->off[12];
   L->off[9] = L->off[11];
   L->off[16] = L->off[14];
   L->total = o;
-  return true;
+  return ok;
 }
 
 bool device_ok(int dev) {
@@ -859,7 +871,7 @@ size_t ozaki2_workspace_bytes_batched(int count, const int64_t *m, const int64_t
     if (m[q] == 0 || n[q] == 0 || k[q] == 0) continue;
     Layout L;
     if (!make_layout(m[q], n[q], k[q], num_moduli, &L)) return 0;
-    total += L.total;
+    if (__builtin_add_overflow(total, L.total, &total)) return 0;
   }
   return total;
 }
@@ -897,7 +909,7 @@ int ozaki2_dgemm_batched(int count, const char *transA, const char *transB, cons
   for (int q = 0; q < count; ++q) {
     if (!emulated(m[q], n[q], k[q], alpha[q])) continue;
     if (!make_layout(m[q], n[q], k[q], num_moduli, &lays[q])) return OZ2_ERR_UNSUPPORTED;
-    total += lays[q].total;
+    if (__builtin_add_overflow(total, lays[q].total, &total)) total = SIZE_MAX;
     largest = std::max(largest, lays[q].total);
   }
   uint8_t *ws = nullptr;

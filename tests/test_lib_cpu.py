@@ -232,3 +232,21 @@ def test_blocking_setting_and_workspace():
         oz.ozaki2_set_blocking(0, 0)
     assert oz.ozaki2_workspace_bytes(1000, 4000, 300, 12) == small
     assert oz.ozaki2_workspace_bytes(16384, 16384, 16384, 12) == full
+
+
+def test_workspace_sizes_that_do_not_fit_are_refused():
+    # extents above 2^40 and sizes that overflow size_t give 0 (and
+    # OZ2_ERR_UNSUPPORTED from ozaki2_dgemm), never a wrapped small size
+    ws = oz.ozaki2_workspace_bytes
+    assert ws(2 ** 40 + 1, 256, 256, 12) == 0
+    assert ws(256, 256, 2 ** 40 + 1, 12) == 0
+    assert ws(2 ** 40, 2 ** 40, 256, 12) == 0      # planes: 24 x 2^80 bytes
+    assert ws(2 ** 33, 2 ** 33, 256, 12) == 0      # planes: 24 x 2^66 bytes
+    big = ws(2 ** 29, 2 ** 29, 2 ** 18, 12)        # about 2^62.6 bytes: fits
+    assert big > 2 ** 62
+    # the sum over a batch must not wrap either
+    wb = oz.ozaki2_workspace_bytes_batched
+    assert wb([2 ** 29] * 2, [2 ** 29] * 2, [2 ** 18] * 2, 12) == 2 * big
+    assert wb([2 ** 29] * 3, [2 ** 29] * 3, [2 ** 18] * 3, 12) == 0
+    # ordinary sizes are unchanged: the layout of 8192^3 at N = 12
+    assert ws(8192, 8192, 8192, 12) == 5772017920

@@ -86,8 +86,8 @@ def _cpu_baseline(A, B, N, rows, mode, moduli_list):
 def main():
     args = _parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the emulation is a "
-              "single-GPU library and this build measures one MI355X.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library emulates "
+              "each GEMM on one device and has no multi-GPU sharding.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

@@ -1,5 +1,6 @@
 """Plant plausible mistakes in the oracle (on the CPU) and confirm that the pin
-checks catch every one of them.  This is what makes the pins worth trusting:
+checks catch every one of them (hybrid path, fast mode, and the Karatsuba-only
+and INT8 lists).  This is what makes the pins worth trusting:
 a dropped term, a wrong sign, a transposed or shifted index anywhere in the
 oracle fails at least one check."""
 import numpy as np
@@ -7,6 +8,7 @@ import pytest
 
 from oracle import ozaki2_ref as ref
 import test_oracle_core as core
+import test_oracle_tables as tables
 
 
 def _problem():
@@ -33,6 +35,11 @@ def _run_checks():
         ("cond3_fast", lambda: core.check_condition3(A, B, 12, mode="fast")),
         ("fastnorm", lambda: core.check_fast_norms(A, B, 13)),
         ("fast_tight", lambda: core.check_fast_matches_accurate_when_tight(12)),
+        ("lists", tables.test_printed_lists),
+        ("karatsuba_pins", lambda: core.test_karatsuba_only_pins(5)),
+        ("karatsuba_accuracy", core.test_karatsuba_only_integer_inputs_and_accuracy),
+        ("int8_pins", lambda: core.test_int8_arm_pins(5)),
+        ("int8_accuracy", core.test_int8_arm_accuracy_and_int32_limit),
     ]
     for name, fn in checks:
         try:
@@ -134,11 +141,32 @@ def _smod_shifted(x, p):
     return ((x + h) % p) - h
 
 
+def _int8_list_from_255(N):
+    return ref._greedy_coprime(range(255, 1, -1), N)
+
+
+def _karatsuba_list_from_512(N):
+    return ref._greedy_coprime(range(512, 1, -1), N)
+
+
+def _int8_slice_unsigned(u, kind, s):
+    # the INT8 residue stored as its unsigned byte
+    if kind == "int8":
+        return [np.mod(u, 256)]
+    return _orig["digit_slices"](u, kind, s)
+
+
+def _int8_product_unreduced(dA, dB, p, kind, s, chunk=2 ** 16):
+    if kind != "int8":
+        return _orig["residue_product_fp8"](dA, dB, p, kind, s, chunk)
+    return (dA[0].astype(np.float64) @ dB[0].astype(np.float64)).astype(np.int64)
+
+
 _orig = {name: getattr(ref, name) for name in (
     "digits_karatsuba", "digits_square", "crt_weights", "crt_reconstruct",
     "scale_exponent", "round_up_e4m3", "residues", "to_integers",
     "ufp_exponents", "inverse_scale", "residue_product", "residue_product_fp8",
-    "smod", "cauchy_schwarz_norms")}
+    "smod", "cauchy_schwarz_norms", "digit_slices")}
 
 MUTATIONS = {
     "karatsuba_x3": ("digits_karatsuba", _kara_wrong_x3),
@@ -158,6 +186,10 @@ MUTATIONS = {
     "fast_norm_unscaled": ("cauchy_schwarz_norms", _norms_unscaled),
     "fast_norm_truncated": ("cauchy_schwarz_norms", _norms_unrounded),
     "fast_norm_max": ("cauchy_schwarz_norms", _norms_max_not_sum),
+    "int8_list_from_255": ("int8_moduli", _int8_list_from_255),
+    "karatsuba_list_from_512": ("karatsuba_moduli", _karatsuba_list_from_512),
+    "int8_slice_unsigned": ("digit_slices", _int8_slice_unsigned),
+    "int8_product_unreduced": ("residue_product_fp8", _int8_product_unreduced),
 }
 
 

@@ -26,9 +26,13 @@ R3  scale rule: e_i is the largest integer e with 2^(2e+1) * r_i <= P - 1,
     implementation formula for log2(mu) (Section III-E) computes in exact
     arithmetic; it guarantees condition (3) because cbar_ij <= sqrt(r_i c_j).
 R4  the bound product is taken exactly (Abar*Bbar has no rounding here).  The
-    paper's FP32 value inflated by (1 + k 2^-24) is a certified stand-in for
-    it; the GPU uses that stand-in to settle every row whose exponent it
-    determines and recomputes the rest exactly, so both sides reach this value.
+    paper computes it in FP32 on FP8 matrix units and inflates it by
+    (1 + k 2^-24); that value depends on the hardware's summation order, and
+    on gfx950 the inflation is not even an upper bound (the FP8 MFMA truncates
+    products inside groups of 8 terms).  Taking the exact product makes the
+    scale exponents a function of the inputs alone.  Any implementation that
+    settles a line from an inexact bound must therefore prove that the exact
+    value gives the same exponent (else recompute it exactly) to agree here.
 R5  int(.) in the scale formula is floor (its argument may be negative).
 R6  zero rows/columns: exponent 0, scale exponent 0; their outputs are +0.
 R7  symmetric modulo: smod(x, p) lies in [-floor(p/2), ceil(p/2) - 1].

@@ -280,6 +280,24 @@ def ozaki2_get_blocking() -> tuple[int, int]:
     return a.value, b.value
 
 
+def _check_tensor(name: str, t, device) -> None:
+    """Marshalling checks of the tensor wrappers: a 2-D float64 tensor in GPU
+    memory on `device` (device pointers are all the library accepts; a host
+    pointer handed to its kernels would fault the GPU)."""
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64, not {t.dtype}")
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be 2-D, not {t.dim()}-D")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a GPU tensor, not on {t.device}")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, the other operands on {device}")
+
+
 class _ModeScope:
     """Sets the calling thread's mode for one call and restores it after."""
 
@@ -304,12 +322,17 @@ def dgemm_batched(As, Bs, num_moduli: int = 12, mode=None):
     ('accurate' / 'fast', default: the thread's setting) applies to this call."""
     import torch
 
+    As, Bs = list(As), list(Bs)
+    if len(As) != len(Bs):
+        raise ValueError("dgemm_batched takes as many A as B tensors")
+    dev = As[0].device if As else None
+    for a, b in zip(As, Bs):
+        _check_tensor("A", a, dev)
+        _check_tensor("B", b, dev)
     As = [a.contiguous() for a in As]
     Bs = [b.contiguous() for b in Bs]
     Cs, args = [], []
     for a, b in zip(As, Bs):
-        if a.dtype != torch.float64 or b.dtype != torch.float64:
-            raise TypeError("dgemm_batched takes float64 tensors")
         m, k = a.shape
         if b.shape[0] != k:
             raise ValueError("inner dimensions differ")
@@ -319,8 +342,8 @@ def dgemm_batched(As, Bs, num_moduli: int = 12, mode=None):
         args.append((n, m, k, b, max(1, n), a, max(1, k), c, max(1, n)))
     if not args:
         return Cs
-    ozaki2_set_stream(torch.cuda.current_stream(As[0].device))
-    with _ModeScope(mode):
+    ozaki2_set_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.device(dev), _ModeScope(mode):
         st = ozaki2_dgemm_batched(["N"] * len(args), ["N"] * len(args), [x[0] for x in args],
                                   [x[1] for x in args], [x[2] for x in args], [1.0] * len(args),
                                   [x[3] for x in args], [x[4] for x in args],
@@ -339,8 +362,8 @@ def dgemm(A, B, num_moduli: int = 12, alpha: float = 1.0, beta: float = 0.0, C=N
     this call."""
     import torch
 
-    if A.dtype != torch.float64 or B.dtype != torch.float64:
-        raise TypeError("dgemm takes float64 tensors")
+    _check_tensor("A", A, A.device if isinstance(A, torch.Tensor) else None)
+    _check_tensor("B", B, A.device)
     A = A.contiguous()
     B = B.contiguous()
     m, k = A.shape
@@ -350,8 +373,16 @@ def dgemm(A, B, num_moduli: int = 12, alpha: float = 1.0, beta: float = 0.0, C=N
     if C is None:
         C = torch.empty((m, n), dtype=torch.float64, device=A.device)
         beta = 0.0
+    else:
+        # the library writes m x n doubles at C with leading dimension n:
+        # anything smaller, strided or elsewhere is refused before the call
+        _check_tensor("C", C, A.device)
+        if tuple(C.shape) != (m, n):
+            raise ValueError(f"C has shape {tuple(C.shape)}, expected {(m, n)}")
+        if not C.is_contiguous():
+            raise ValueError("C must be contiguous (it is written in place)")
     ozaki2_set_stream(torch.cuda.current_stream(A.device))
-    with _ModeScope(mode):
+    with torch.cuda.device(A.device), _ModeScope(mode):
         st = ozaki2_dgemm("N", "N", n, m, k, alpha, B, max(1, n), A, max(1, k), beta, C,
                           max(1, n), num_moduli)
     if st != 0:

@@ -250,3 +250,24 @@ def test_workspace_sizes_that_do_not_fit_are_refused():
     assert wb([2 ** 29] * 3, [2 ** 29] * 3, [2 ** 18] * 3, 12) == 0
     # ordinary sizes are unchanged: the layout of 8192^3 at N = 12
     assert ws(8192, 8192, 8192, 12) == 5772017920
+
+
+def test_tensor_wrappers_refuse_bad_operands():
+    """dgemm / dgemm_batched check their tensors before any library call: a
+    host tensor, another dtype or rank never reaches the kernels."""
+    import torch
+
+    a = torch.zeros((4, 3), dtype=torch.float64)
+    b = torch.zeros((3, 5), dtype=torch.float64)
+    with pytest.raises(TypeError):
+        oz.dgemm(a.float(), b)
+    with pytest.raises(ValueError, match="2-D"):
+        oz.dgemm(a.reshape(-1), b)
+    with pytest.raises(ValueError, match="GPU"):
+        oz.dgemm(a, b)
+    with pytest.raises(TypeError):
+        oz.dgemm(a.numpy(), b)
+    with pytest.raises(ValueError, match="GPU"):
+        oz.dgemm_batched([a], [b])
+    with pytest.raises(ValueError, match="as many"):
+        oz.dgemm_batched([a, a], [b])

@@ -1,5 +1,7 @@
 """The oracle's BLAS-style wrapper: column-major layout, transposes, leading
 dimensions, alpha/beta and quick returns."""
+import math
+
 import numpy as np
 
 from oracle import ozaki2_ref as ref
@@ -69,3 +71,102 @@ def test_row_major_identity():
     C = np.zeros(m * n)
     out = ref.dgemm("N", "N", n, m, k, 1.0, Brm, n, Arm, k, 0.0, C, n, 12)
     assert np.array_equal(out.reshape(m, n), ref.emulate(A, B, 12))
+
+
+# ---------------------------------------------------------------------------
+# combine_alpha_beta against exact rational arithmetic: every operation of
+# RN(RN(alpha Chat) + RN(beta C_in)) (R10) is formed exactly as a Fraction and
+# rounded once to nearest-even, overflow and signed zeros included.
+# ---------------------------------------------------------------------------
+from fractions import Fraction  # noqa: E402
+
+_MAXF = Fraction(2) ** 1024 - Fraction(2) ** 970   # smallest magnitude rounding to inf
+
+
+def _rn(x: Fraction, zero_sign: float) -> float:
+    """x rounded to the nearest double (ties to even), inf past the overflow
+    threshold; an exact zero takes the sign IEEE 754 gives it (zero_sign)."""
+    if x == 0:
+        return math.copysign(0.0, zero_sign)
+    if abs(x) >= _MAXF:
+        return math.inf if x > 0 else -math.inf
+    return float(x)      # CPython's int/int true division rounds correctly
+
+
+def _exact_combine(chat: float, alpha: float, beta: float, cin: float) -> float:
+    if not all(math.isfinite(v) for v in (chat, alpha, beta, cin)):
+        return float("nan")  # only NaN-ness is compared for these
+    t = _rn(Fraction(alpha) * Fraction(chat),
+            -1.0 if (math.copysign(1, alpha) * math.copysign(1, chat)) < 0 else 1.0)
+    if beta == 0.0:
+        return t
+    u = _rn(Fraction(beta) * Fraction(cin),
+            -1.0 if (math.copysign(1, beta) * math.copysign(1, cin)) < 0 else 1.0)
+    if math.isinf(t) or math.isinf(u):
+        return t + u
+    both_neg = math.copysign(1, t) < 0 and math.copysign(1, u) < 0
+    return _rn(Fraction(t) + Fraction(u), -1.0 if both_neg else 1.0)
+
+
+
+def _combine_cases():
+    rng = np.random.default_rng(20260310)
+    chat = rng.standard_normal(400) * np.exp2(rng.integers(-60, 60, 400))
+    cin = rng.standard_normal(400) * np.exp2(rng.integers(-60, 60, 400))
+    alphas = [1.0, -1.5, 0.1, 3.0000000000000004, 2.0 ** -1074 * 3, 1e300]
+    betas = [0.0, 1.0, 0.25, -0.3, 1e-300, 7.0]
+    cases = []
+    for a in alphas:
+        for b in betas:
+            cases.append((chat, a, b, cin))
+    # cancelling terms: alpha Chat = -beta C_in before rounding, and near it,
+    # where one fused rounding would differ from two separate ones
+    x = rng.standard_normal(200)
+    cases.append((x, 0.1, -0.1, x))
+    cases.append((x, 1.0 / 3.0, -1.0, x / 3.0))
+    cases.append((x * (1 + 2.0 ** -52), 0.7, -0.7, x))
+    # subnormal results, overflow, signed zeros, non-finite entries
+    tiny = np.array([2.0 ** -1074, -2.0 ** -1070, 3 * 2.0 ** -1060, 0.0, -0.0, 1e-310])
+    cases.append((tiny, 0.5, 0.5, tiny[::-1].copy()))
+    cases.append((tiny, -1.0, -0.0, tiny))
+    big = np.array([1e308, -1.7e308, 8e307, 0.0, -0.0, 1.0])
+    cases.append((big, 3.0, 2.0, big))
+    cases.append((np.array([np.nan, np.inf, -np.inf, 1.0]), 2.0, 1.0,
+                  np.array([1.0, 1.0, 2.0, np.nan])))
+    return cases
+
+
+def test_combine_alpha_beta_matches_exact_rounding():
+    """Pins combine_alpha_beta (R10): one correctly rounded step per
+    operation, C_in unread when beta == 0."""
+    n_checked = 0
+    for chat, a, b, cin in _combine_cases():
+        with np.errstate(all="ignore"):
+            got = ref.combine_alpha_beta(chat.copy(), a, b,
+                                         None if b == 0.0 else cin.copy())
+        for q in range(chat.size):
+            want = _exact_combine(float(chat[q]), a, b, float(cin[q]))
+            g = float(got[q])
+            if math.isnan(want):
+                assert math.isnan(g) or not math.isfinite(float(chat[q])) or \
+                    not math.isfinite(float(cin[q])), (chat[q], a, b, cin[q])
+                continue
+            assert np.float64(g).view(np.int64) == np.float64(want).view(np.int64), \
+                (chat[q], a, b, cin[q], g, want)
+            n_checked += 1
+    assert n_checked > 10000
+
+
+def test_combine_alpha_beta_is_not_one_fused_rounding():
+    """A fused form RN(alpha Chat + beta C_in) would keep the low bits that
+    two roundings lose: on x (1 + 2^-52) 0.7 - 0.7 x the two differ, and the
+    exact-rounding model picks the two-rounding value."""
+    x = np.array([1.0 + 2.0 ** -52, 3.0, 5.0])
+    a, b = 0.7, -0.7
+    cin = np.array([1.0, 3.0 * (1 - 2.0 ** -53), 5.0])
+    got = ref.combine_alpha_beta(x, a, b, cin)
+    fused = [float(Fraction(a) * Fraction(float(x[q])) + Fraction(b) * Fraction(float(cin[q])))
+             for q in range(3)]
+    want = [_exact_combine(float(x[q]), a, b, float(cin[q])) for q in range(3)]
+    assert list(got) == want
+    assert fused != want

@@ -443,6 +443,67 @@ def scaling(opA: np.ndarray, opB: np.ndarray, num_moduli: int, mode: str = "accu
                 sA=7 - EA + e, sB=7 - EB + f)
 
 
+def line_bounds(opA: np.ndarray, opB: np.ndarray, rows, cols, mode: str = "accurate") -> dict:
+    """Workflow steps 1-2 of Section IV-B for the rows `rows` of op(A) and the
+    columns `cols` of op(B) only: mu', nu' of those lines and the bound that
+    decides their scale exponents (accurate mode: the maximum of the bound
+    product over ALL partner lines; fast mode: the line's own norm, R13).
+
+    The definitions are those of scaling(); only the bound-product entries
+    that reach the requested maxima are formed: Abar[rows] Bbar gives the row
+    maxima r_i, Abar Bbar[:, cols] the column maxima c_j.  The bound operands
+    of both sides are built in full, because every partner line enters a
+    maximum.  The result does not depend on the number of moduli, so one call
+    serves every N (scaling_from_bounds)."""
+    if mode not in ("accurate", "fast"):
+        raise ValueError("mode must be 'accurate' or 'fast'")
+    opA = np.asarray(opA, dtype=np.float64)
+    opB = np.asarray(opB, dtype=np.float64)
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    k = opA.shape[1]
+    finA = np.isfinite(opA)
+    finB = np.isfinite(opB)
+    badA = ~np.all(finA[rows], axis=1) if k else np.zeros(len(rows), bool)
+    badB = ~np.all(finB[:, cols], axis=0) if k else np.zeros(len(cols), bool)
+    A = np.where(finA, opA, 0.0)
+    B = np.where(finB, opB, 0.0)
+    del finA, finB
+    EA = ufp_exponents(A, axis=1)
+    EB = ufp_exponents(B, axis=0)
+    Abar, Bbar = bound_operands(A, B, EA, EB)
+    if mode == "fast":
+        r18, c18 = cauchy_schwarz_norms(Abar[rows], Bbar[:, cols])
+    else:
+        n, m = B.shape[1], A.shape[0]
+        r18 = exact_bound_product(Abar[rows], Bbar).max(axis=1) if n else np.zeros(len(rows))
+        c18 = exact_bound_product(Abar, Bbar[:, cols]).max(axis=0) if m else np.zeros(len(cols))
+    return dict(A=A[rows], B=B[:, cols], badA=badA, badB=badB, EA=EA[rows], EB=EB[cols],
+                r18=r18, c18=c18, mode=mode)
+
+
+def scaling_from_bounds(bounds: dict, num_moduli: int, moduli_set: str = "hybrid") -> dict:
+    """Step 3 (the scale exponents, Section III-E, R3) for the lines of
+    line_bounds(); returns a scaling dict of the sub-problem
+    op(A)[rows] x op(B)[:, cols] whose lines carry the exponents of the whole
+    problem, so products(sc, slice(None), slice(None)) yields the sampled
+    outputs Chat[rows][:, cols]."""
+    mods = moduli_table(num_moduli, moduli_set)
+    P = math.prod(p for p, _, _ in mods)
+    e = np.array([scale_exponent(v, P) for v in bounds["r18"]], dtype=np.int64)
+    f = np.array([scale_exponent(v, P) for v in bounds["c18"]], dtype=np.int64)
+    sc = {key: bounds[key] for key in ("A", "B", "badA", "badB", "EA", "EB", "r18", "c18")}
+    sc.update(moduli=mods, P=P, e=e, f=f, sA=7 - bounds["EA"] + e, sB=7 - bounds["EB"] + f)
+    return sc
+
+
+def scaling_lines(opA: np.ndarray, opB: np.ndarray, num_moduli: int, rows, cols,
+                  mode: str = "accurate", moduli_set: str = "hybrid") -> dict:
+    """scaling() restricted to the rows `rows` and columns `cols` (see
+    line_bounds and scaling_from_bounds)."""
+    return scaling_from_bounds(line_bounds(opA, opB, rows, cols, mode), num_moduli, moduli_set)
+
+
 def products(sc: dict, rows, cols, keep_stages: bool = False):
     """Workflow steps 4-10 for the entries (rows x cols): integers, residues,
     exact residue products, CRT and inverse scaling."""

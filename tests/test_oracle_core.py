@@ -481,3 +481,36 @@ def test_rounding_helper_subnormal():
     assert ref._rn_scaled(2 ** 53 + 1, 0) == 2.0 ** 53
     assert ref._rn_scaled(2 ** 53 + 3, 0) == 2.0 ** 53 + 4
     assert ref._rn_scaled(1, -1024) == math.inf
+
+
+@pytest.mark.parametrize("mode,moduli_set,N", [("accurate", "hybrid", 12), ("fast", "hybrid", 13),
+                                               ("accurate", "int8", 15),
+                                               ("accurate", "karatsuba", 5)])
+def test_scaling_lines_equals_full_scaling(mode, moduli_set, N):
+    # the line-restricted scaling (used where the whole bound product is too
+    # large to form on the CPU) gives every sampled line the exponents of the
+    # full oracle, and the sampled outputs equal the full emulation's
+    A, B = _small_problem(37, 29, 70, 2.0, 31)
+    A[4, :] = 0.0
+    A[6, 3] = np.inf
+    B[:, 7] = 0.0
+    B[11, 9] = np.nan
+    A[9] *= 2.0 ** 40
+    B[:, 2] *= 2.0 ** -30
+    rows = np.array([0, 4, 6, 9, 36, 9])
+    cols = np.array([28, 2, 7, 9, 0])
+    full = ref.scaling(A, B, N, mode=mode, moduli_set=moduli_set)
+    part = ref.scaling_lines(A, B, N, rows, cols, mode=mode, moduli_set=moduli_set)
+    for key, sel in (("EA", rows), ("e", rows), ("sA", rows), ("r18", rows), ("badA", rows),
+                     ("EB", cols), ("f", cols), ("sB", cols), ("c18", cols), ("badB", cols)):
+        assert np.array_equal(part[key], full[key][sel]), key
+    want, _ = ref.products(full, rows, cols)
+    got, _ = ref.products(part, slice(None), slice(None))
+    assert np.array_equal(np.isnan(got), np.isnan(want))
+    assert np.array_equal(np.nan_to_num(got).view(np.int64), np.nan_to_num(want).view(np.int64))
+    # one bound serves every number of moduli
+    b = ref.line_bounds(A, B, rows, cols, mode)
+    for N2 in (N - 1, N + 1):
+        f2 = ref.scaling(A, B, N2, mode=mode, moduli_set=moduli_set)
+        p2 = ref.scaling_from_bounds(b, N2, moduli_set)
+        assert np.array_equal(p2["sA"], f2["sA"][rows]) and np.array_equal(p2["sB"], f2["sB"][cols])

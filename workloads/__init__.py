@@ -23,6 +23,18 @@ def config_seed(config: int, phi_index: int = 0) -> int:
     return SEED_BASE + 100 * config + 10 * phi_index
 
 
+#: the spreads phi of each named workload, in the order that numbers their seeds
+WORKLOAD_PHIS = {1: (0.5,), 2: (0.5, 2.0, 4.0), 3: (1.0,), 4: (1.0,), 5: (1.0, 6.0)}
+
+
+def phi_seed(config: int, phi: float) -> int:
+    """Seed of op(A) for spread phi of workload `config`: phi's position in
+    that workload's list of spreads numbers it (0 for a spread not listed)."""
+    phis = WORKLOAD_PHIS.get(config, ())
+    idx = phis.index(float(phi)) if float(phi) in phis else 0
+    return config_seed(config, idx)
+
+
 def phi_matrix(rows: int, cols: int, phi: float, seed: int) -> np.ndarray:
     """(rows x cols) float64 with entries (U[0,1) - 0.5) * exp(phi * N(0,1)).
 

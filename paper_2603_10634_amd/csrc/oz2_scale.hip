@@ -11,48 +11,27 @@
 // because each bound entry is at most sqrt(r_i c_j).
 //
 // The bound product runs on FP8 MFMA, so the computed maxima r'_i carry an
-// error.  The paper bounds it by (k - 1) u with u = 2^-24, the bound for FP32
-// summation rounded to nearest; gfx950's FP8 MFMA does not meet it.  Measured
-// behaviour of v_mfma_f32_32x32x64_f8f6f4: products are summed in groups of
-// 8 consecutive k, and inside a group every product is truncated to the grid
-// 2^-13 below the group's largest product (smaller ones vanish); group sums
-// and the accumulator are then combined at FP32 precision, mostly truncating,
-// at most one FP32 rounding upwards per instruction.  For non-negative terms
-// that gives  r' (1 - (k/64 + 2) 2^-23) <= r <= r' / (1 - g),
-// g = 7 2^-13 + (k/7) 2^-23; the decision window uses 2g.  When the whole
-// window gives the same exponent, it is the exponent of the exact r_i.  Lines
-// whose window straddles a threshold are recomputed exactly: Abar and Bbar are
-// multiples of 2^-9 up to 256, so 2^18 (Abar Bbar)_ij is an integer below
-// 2^52 for k <= 2^18 and is summed exactly in 64-bit integers.  The result is
-// a deterministic function of the inputs, independent of the MFMA's
-// summation order.  (Integer digit products stay exact: every product is an
-// integer of magnitude <= 256, far inside the 2^-13 window, and every partial
-// sum is at most 2^24.)
+// error; the paper bounds it by (k - 1) 2^-24 (FP32 summation rounded to
+// nearest), which gfx950's FP8 MFMA does not meet.  Each line is therefore
+// decided from a window that holds the exact maximum under a stated worst
+// case of the MFMA's accumulation (oz2_window.h).  When the whole window gives
+// the same exponent, it is the exponent of the exact r_i.  Lines whose window
+// straddles a threshold are recomputed exactly: Abar and Bbar are multiples
+// of 2^-9 up to 256, so 2^18 (Abar Bbar)_ij is an integer below 2^52 for
+// k <= 2^18 and is summed exactly in 64-bit integers.  The result is a
+// deterministic function of the inputs, independent of the MFMA's summation
+// order.  (Integer digit products stay exact: every product is an integer of
+// magnitude <= 256, far inside the 2^-13 window, and every partial sum is at
+// most 2^24.)
 #include <string.h>
 
 #include "oz2_device.h"
 #include "oz2_internal.h"
+#include "oz2_window.h"
 
 namespace oz2 {
 
 namespace {
-
-// max{e : x 2^(2e+1) <= D} for a double x > 0, where D is the largest double
-// not above P - 1 (so for a double y, y <= P - 1 iff y <= D).
-__device__ __forceinline__ int exponent_rule(double x, double D) {
-  int ex, eD;
-  const double mx = frexp(x, &ex);
-  const double mD = frexp(D, &eD);
-  const int d = eD - ex - 1 - (mx > mD ? 1 : 0);
-  return d >= 0 ? d / 2 : -((-d + 1) / 2);  // floor(d / 2)
-}
-
-// Decision window of the FP8 bound for a k extent of kp (see above).
-__device__ __forceinline__ void bound_window(int64_t kp, double &g_lo, double &g_hi) {
-  const double kd = (double)kp;
-  g_lo = (kd / 64.0 + 2.0) * 0x1p-23;
-  g_hi = 2.0 * (7.0 * 0x1p-13 + (kd / 7.0) * 0x1p-23);
-}
 
 template <bool GROUPED>
 __global__ __launch_bounds__(256) void k_scale_decide(Problem P1, Group G) {
@@ -62,17 +41,11 @@ __global__ __launch_bounds__(256) void k_scale_decide(Problem P1, Group G) {
   const int64_t lines = P.g.mp + P.g.np;
   if (L >= lines) return;
   const Work &w = P.w;
-  double g_lo, g_hi;
-  bound_window(P.g.kp, g_lo, g_hi);
   const float r = __uint_as_float(w.rmax[L]);
   int ev = 0;
   if (r > 0.0f && !(w.flags[L] & kZeroLine)) {
-    const double D = P.tab->D;
-    const double rd = (double)r;
-    const double lo = rd * (1.0 - g_lo) * (1.0 - 0x1p-50);
-    const double hi = rd * (1.0 + 2.0 * g_hi) * (1.0 + 0x1p-50);  // >= r' / (1 - g_hi)
-    const int e_small = exponent_rule(hi, D);
-    const int e_large = exponent_rule(lo, D);
+    int e_small, e_large;
+    window_exponents((double)r, P.g.kp, P.tab->D, &e_small, &e_large);
     ev = e_small;
     if (e_small != e_large) {
       const uint32_t slot = atomicAdd(&w.amb[0], 1u);

@@ -259,8 +259,9 @@ def _bound_case(kind):
 @pytest.mark.parametrize("kind", ["spread", "wide", "dominant"])
 def test_bound_maxima_within_window(kind):
     # the GPU's FP32 line maxima of the bound product against the exact ones:
-    # within the error the library's decision window assumes (a window 8
-    # times wider is what the library uses, so this checks its margin)
+    # within the deviations of the stated worst case the library's decision
+    # window is derived from (oz2_window.h; the window itself is twice as
+    # wide on each side), and the measured hardware's narrower behaviour
     A, B = _bound_case(kind)
     r = run(A, B, 12, keep_ws=True)
     assert r.status == 0
@@ -268,10 +269,14 @@ def test_bound_maxima_within_window(kind):
     assert _same(r.C, Chat)
     rA, rB = r.lines(8, np.uint32)
     kp = r.pads["kp"]
-    # measured MFMA behaviour: underestimate by at most 7 2^-13 + (k/7) 2^-23,
-    # overestimate by at most (k/64 + 2) 2^-23
-    down = 7 * 2.0 ** -13 + kp / 7 * 2.0 ** -23
-    up = (kp / 64 + 2) * 2.0 ** -23
+    Q = (kp + 7) // 8
+    # worst case (W): under by at most 7 2^-13 + Q 2^-23, over by at most
+    # 7 2^-13 + 1.02 Q 2^-23
+    down = 7 * 2.0 ** -13 + Q * 2.0 ** -23
+    up = 7 * 2.0 ** -13 + 1.02 * Q * 2.0 ** -23
+    # measured behaviour: truncation inside groups of 8, at most one upward
+    # FP32 rounding per instruction of 64 k
+    hw_up = (kp / 64 + 2) * 2.0 ** -23
     worst_down = worst_up = 0.0
     for g32, exact18 in ((rA, st["r18"]), (rB, st["c18"])):
         g = g32.view(np.float32).astype(np.float64)
@@ -280,10 +285,11 @@ def test_bound_maxima_within_window(kind):
         rel = g[nz] / exact[nz] - 1.0
         worst_down = max(worst_down, float(-rel.min()))
         worst_up = max(worst_up, float(rel.max()))
-    print(f"bound {kind}: worst under {worst_down:.3e} (model {down:.3e}), worst over "
-          f"{worst_up:.3e} (model {up:.3e}), paper's (k-1) 2^-24 = {(kp - 1) * 2.0 ** -24:.3e}, "
-          f"exact fix-ups {r.fixups()}", flush=True)
+    print(f"bound {kind}: worst under {worst_down:.3e} (worst case {down:.3e}), worst over "
+          f"{worst_up:.3e} (worst case {up:.3e}, measured model {hw_up:.3e}), paper's "
+          f"(k-1) 2^-24 = {(kp - 1) * 2.0 ** -24:.3e}, exact fix-ups {r.fixups()}", flush=True)
     assert worst_down <= down and worst_up <= up
+    assert worst_up <= hw_up
 
 
 def test_deterministic_and_stream():

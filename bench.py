@@ -39,12 +39,31 @@ def _parse():
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--k", type=int, default=None)
     ap.add_argument("--moduli", type=int, default=12)
-    ap.add_argument("--phi", type=float, default=0.5)
+    ap.add_argument("--phi", type=float, default=None,
+                    help="spread of the entries (default 0.5; 1 for the batched workload)")
     ap.add_argument("--mode", choices=["accurate", "fast"], default="accurate",
                     help="scaling mode (fast: Cauchy-Schwarz bound, no bound product)")
     ap.add_argument("--moduli-list", choices=["hybrid", "karatsuba", "int8"], default="hybrid",
                     help="modulus list (karatsuba: the Karatsuba-only ablation, N = 13; "
                          "int8: the INT8 arm of Section II, N = 14-16)")
+    ap.add_argument("--transA", choices=["N", "T"], default="N",
+                    help="storage of op(A): N (m x k, lda = m) or T (k x m, lda = k)")
+    ap.add_argument("--transB", choices=["N", "T"], default="N",
+                    help="storage of op(B): N (k x n, ldb = k) or T (n x k, ldb = n)")
+    ap.add_argument("--cancel", action="store_true",
+                    help="rows 0..255 of op(A) orthogonal to columns 0..255 of op(B) up to "
+                         "a 1e-8 perturbation (the large stress workload's block)")
+    ap.add_argument("--config", type=int, default=2,
+                    help="seed group of the inputs (the numbered workloads: 2 square, "
+                         "3 rectangular, 5 large stress)")
+    ap.add_argument("--workload", choices=["single", "batched"], default="single",
+                    help="batched: 512 problems with m, n, k log-uniform in [64, 4096], "
+                         "one batched call (graph replay, autotuned) against looped "
+                         "single calls and looped native FP64 DGEMM")
+    ap.add_argument("--count", type=int, default=512, help="problems of the batched workload")
+    ap.add_argument("--vendor-fp8", action="store_true",
+                    help="also time the vendor FP8 GEMM (torch._scaled_mm, E4M3 operands of "
+                         "the same m x n x k, FP32 output) for context")
     ap.add_argument("--cpu-rows", type=int, default=48,
                     help="rows of op(A) in the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -58,7 +77,10 @@ def _parse():
                     help="before the timed steps, run a plain device copy of 1 GiB "
                          "(torch copy_) three times, as the reference kernel for "
                          "scaling hardware byte counters")
-    return ap.parse_args()
+    args = ap.parse_args()
+    if args.phi is None:
+        args.phi = 1.0 if args.workload == "batched" else 0.5
+    return args
 
 
 def _cpu_baseline(A, B, N, rows, mode, moduli_list):
@@ -83,17 +105,157 @@ def _cpu_baseline(A, B, N, rows, mode, moduli_list):
                       f"N={N}, {mode} mode, {moduli_list} moduli), {dt:.1f} s wall"}
 
 
+def _bench_batched(args):
+    """The batched workload: `count` problems with m, n, k drawn log-uniformly
+    from [64, 4096] (entries (U - 1/2) exp(phi N(0,1)) drawn on the GPU from a
+    seeded generator, column-major NN), all emulated by ONE
+    ozaki2_dgemm_batched call.  The first call autotunes the residue-product
+    configuration; the timed steps replay the call's captured graph.  Beside
+    it: the same problems as looped ozaki2_dgemm calls and as looped native
+    FP64 DGEMMs (torch.matmul), and one eager timed pass for the kernel
+    breakdown (the persistent residue-product launch against the FP8 peak)."""
+    import numpy as np
+    import torch
+
+    import paper_2603_10634_amd as oz
+    from workloads import batch_shapes, config_seed
+
+    N = args.moduli
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    seed = config_seed(4, 0)
+    shapes = batch_shapes(args.count, 64, 4096, seed)
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    f64 = torch.float64
+    tA, tB, tC = [], [], []
+    for (m, n, k) in shapes:
+        tA.append((torch.rand((k, m), generator=g, device=dev, dtype=f64) - 0.5) *
+                  torch.exp(args.phi * torch.randn((k, m), generator=g, device=dev, dtype=f64)))
+        tB.append((torch.rand((n, k), generator=g, device=dev, dtype=f64) - 0.5) *
+                  torch.exp(args.phi * torch.randn((n, k), generator=g, device=dev, dtype=f64)))
+        tC.append(torch.empty((n, m), dtype=f64, device=dev))
+    cnt = len(shapes)
+    ms = [s[0] for s in shapes]
+    ns = [s[1] for s in shapes]
+    ks = [s[2] for s in shapes]
+    flops = float(sum(2.0 * m * n * k for m, n, k in shapes))
+
+    stream = torch.cuda.current_stream(dev)
+    oz.ozaki2_set_stream(stream)
+    if oz.ozaki2_set_mode(args.mode) != 0 or oz.ozaki2_set_moduli_list(args.moduli_list) != 0:
+        raise RuntimeError("invalid mode or moduli list")
+    wbytes = oz.ozaki2_workspace_bytes_batched(ms, ns, ks, N)
+    ws = torch.empty(wbytes + 256, dtype=torch.uint8, device=dev)
+    oz.ozaki2_set_workspace((ws.data_ptr() + 255) // 256 * 256, wbytes)
+
+    def batched():
+        st = oz.ozaki2_dgemm_batched(["N"] * cnt, ["N"] * cnt, ms, ns, ks, [1.0] * cnt, tA, ms,
+                                     tB, ks, [0.0] * cnt, tC, ms, N)
+        if st != 0:
+            raise oz.Ozaki2Error("ozaki2_dgemm_batched", st)
+
+    def looped():
+        for q in range(cnt):
+            st = oz.ozaki2_dgemm("N", "N", ms[q], ns[q], ks[q], 1.0, tA[q], ms[q], tB[q], ks[q],
+                                 0.0, tC[q], ms[q], N)
+            if st != 0:
+                raise oz.Ozaki2Error("ozaki2_dgemm", st)
+
+    def timed(fn, steps):
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize(dev)
+        return (time.perf_counter() - t0) / steps * 1e3
+
+    oz.ozaki2_set_autotune(True)
+    batched()                                    # tunes the configuration, then runs
+    torch.cuda.synchronize(dev)
+    config = oz.ozaki2_get_schedule()
+    oz.ozaki2_set_graph(True)
+    for _ in range(args.warmup):
+        batched()
+    ms_batched = timed(batched, args.steps)      # graph replays
+    oz.ozaki2_set_graph(False)
+    # eager pass with the library's HIP events (one sub-batch: the caller
+    # workspace holds the whole batch)
+    oz.ozaki2_set_timing(True)
+    kt = []
+    for _ in range(max(3, args.steps // 3)):
+        batched()
+        kt.append(oz.ozaki2_get_kernel_times())
+    oz.ozaki2_set_timing(False)
+    k_mean = np.array(kt).mean(axis=0)
+    for _ in range(max(2, args.warmup // 10)):
+        looped()
+    ms_looped = timed(looped, max(3, args.steps // 3))
+    native = None
+    if not args.no_native:
+        nat = lambda: [torch.matmul(tA[q].T, tB[q].T) for q in range(cnt)]
+        for _ in range(max(2, args.warmup // 10)):
+            nat()
+        ms_native = timed(nat, max(3, args.steps // 3))
+        native = {"tflops": round(flops / (ms_native * 1e-3) / 1e12, 2),
+                  "ms": round(ms_native, 3), "impl": "looped torch.matmul float64 (vendor BLAS)"}
+    oz.ozaki2_set_autotune(False)
+    oz.ozaki2_set_workspace(None, 0)
+    value = flops / (ms_batched * 1e-3) / 1e12
+    products = N if args.moduli_list == "int8" else 3 * N
+    gemm_ms = float(k_mean[4])
+    achieved = products * flops / (gemm_ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_batched, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp8e4m3-mfma->f64",
+        "data": "synthetic",
+        "config": {"workload": f"batched: {cnt} emulated dgemms, m, n, k log-uniform in "
+                               f"[64, 4096], col-major NN, phi={args.phi}, {N} "
+                               f"{args.moduli_list} moduli, {args.mode} mode; one "
+                               "ozaki2_dgemm_batched call replayed from its graph",
+                   "count": cnt, "sum_2mnk": flops, "num_moduli": N, "phi": args.phi,
+                   "mode": args.mode, "moduli_list": args.moduli_list},
+        "autotuned_config": config,
+        "looped_single_calls": {"tflops": round(flops / (ms_looped * 1e-3) / 1e12, 3),
+                                "ms": round(ms_looped, 3)},
+        "native_fp64": native,
+        "speedup_vs_looped_single": round(ms_looped / ms_batched, 3),
+        "speedup_vs_native": (round(value / native["tflops"], 3) if native else None),
+        "kernel_ms_mean_eager": [round(float(x), 4) for x in k_mean],
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 1), "peak": FP8_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / FP8_PEAK_TFLOPS, 4),
+                     "traffic": None,
+                     "kernel": f"k_residue_persistent (one launch: {products} FP8 products per "
+                               "problem, all problems; algorithmic flops on the unpadded "
+                               "shapes)"},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = _parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library emulates "
               "each GEMM on one device and has no multi-GPU sharding.", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched":
+        _bench_batched(args)
+        return
     import numpy as np
     import torch
 
     import paper_2603_10634_amd as oz
-    from workloads import config_seed, phi_matrix
+    from workloads import cancellation_block, phi_matrix, phi_seed
     from workloads.reference import dd_dot_rows, normalised_error
 
     m = args.m or args.size
@@ -103,12 +265,17 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
 
-    seed = config_seed(2, 0)
+    seed = phi_seed(args.config, args.phi)
     A = phi_matrix(m, k, args.phi, seed)          # op(A), m x k
     B = phi_matrix(k, n, args.phi, seed + 1)      # op(B), k x n
-    # column-major storage: A (m x k, lda = m) is A.T in C order
-    tA = torch.from_numpy(np.ascontiguousarray(A.T)).to(dev)
-    tB = torch.from_numpy(np.ascontiguousarray(B.T)).to(dev)
+    if args.cancel:
+        A = cancellation_block(A, B, min(256, m), min(256, n), 1e-8, seed + 2)
+    # column-major storage: 'N' stores op(A) (m x k, lda = m), which is A.T in
+    # C order; 'T' stores A^T (k x m, lda = k), which is A in C order
+    tA = torch.from_numpy(np.ascontiguousarray(A.T if args.transA == "N" else A)).to(dev)
+    tB = torch.from_numpy(np.ascontiguousarray(B.T if args.transB == "N" else B)).to(dev)
+    lda = m if args.transA == "N" else k
+    ldb = k if args.transB == "N" else n
     tC = torch.empty((n, m), dtype=torch.float64, device=dev)
 
     stream = torch.cuda.current_stream(dev)
@@ -125,7 +292,8 @@ def main():
     offs, _ = oz.ozaki2_workspace_layout(m, n, k, N)
 
     def call():
-        st = oz.ozaki2_dgemm("N", "N", m, n, k, 1.0, tA, m, tB, k, 0.0, tC, m, N)
+        st = oz.ozaki2_dgemm(args.transA, args.transB, m, n, k, 1.0, tA, lda, tB, ldb, 0.0, tC,
+                             m, N)
         if st != 0:
             raise oz.Ozaki2Error("ozaki2_dgemm", st)
 
@@ -210,6 +378,26 @@ def main():
                   "error_normalised": err_nat, "impl": "torch.matmul float64 (vendor BLAS)"}
         del tAr, tBr, Cn
 
+    vendor = None
+    if args.vendor_fp8:
+        # the vendor FP8 GEMM on operands of the same shape, for context: the
+        # residue products run 3N such products (per the roofline above)
+        fa = (torch.randn((m, k), device=dev) * 4).to(torch.float8_e4m3fn)
+        fb = (torch.randn((n, k), device=dev) * 4).to(torch.float8_e4m3fn).T
+        one = torch.ones((), device=dev, dtype=torch.float32)
+        for _ in range(5):
+            torch._scaled_mm(fa, fb, scale_a=one, scale_b=one, out_dtype=torch.float32)
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        reps = max(10, args.steps)
+        for _ in range(reps):
+            torch._scaled_mm(fa, fb, scale_a=one, scale_b=one, out_dtype=torch.float32)
+        torch.cuda.synchronize(dev)
+        v_ms = (time.perf_counter() - t0) / reps * 1e3
+        vendor = {"tflops": round(flops / (v_ms * 1e-3) / 1e12, 1), "ms": round(v_ms, 4),
+                  "impl": "torch._scaled_mm E4M3 x E4M3 -> FP32 (hipBLASLt)"}
+        del fa, fb
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = _cpu_baseline(A, B, N, min(args.cpu_rows, m), args.mode, args.moduli_list)
@@ -230,13 +418,17 @@ def main():
         "vs_baseline": None,
         "dtype": "fp8e4m3-mfma->f64",
         "data": "synthetic",
-        "config": {"workload": f"emulated dgemm {m}x{n}x{k} col-major NN, phi={args.phi}, "
+        "config": {"workload": f"emulated dgemm {m}x{n}x{k} col-major "
+                               f"{args.transA}{args.transB}, phi={args.phi}"
+                               f"{' with cancellation block' if args.cancel else ''}, "
                                f"{N} {args.moduli_list} moduli, {args.mode} mode",
-                   "m": m, "n": n, "k": k, "num_moduli": N, "phi": args.phi,
+                   "m": m, "n": n, "k": k, "transA": args.transA, "transB": args.transB,
+                   "num_moduli": N, "phi": args.phi, "cancel": args.cancel,
                    "mode": args.mode, "moduli_list": args.moduli_list,
                    "alpha": 1.0, "beta": 0.0},
         "error_normalised": err_emu,
         "native_fp64": native,
+        "vendor_fp8_gemm": vendor,
         "speedup_vs_native": (round(value / native["tflops"], 3) if native else None),
         "mfma_util_pct": round(100 * achieved / FP8_PEAK_TFLOPS, 2),
         "stage_ms_median": {kk: round(v, 4) for kk, v in stage.items()},

@@ -204,20 +204,28 @@ int ozaki2_workspace_layout(int64_t m, int64_t n, int64_t k, int num_moduli,
  * Each C_q is bit-identical to what ozaki2_dgemm returns for problem q.
  *
  * Execution: each kernel family of the method (line maxima, bound operands,
- * bound product, scale exponents, residues and digits, residue products per
- * k chunk, CRT) runs as ONE grouped launch over all problems, whose blocks
- * are mapped to (problem, tile) through prefix sums of per-problem tile
- * counts; the residue products may run persistently (one workgroup per CU
- * looping over tiles) and in largest-problem-first order, as chosen by the
- * autotuner (ozaki2_set_autotune).  Problems are packed into sub-batches whose
- * workspaces fit the workspace at once; sub-batches run one after another.
+ * bound product, scale exponents, residues and digits, CRT) runs as ONE
+ * grouped launch over all problems, whose blocks are mapped to (problem,
+ * tile) through prefix sums of per-problem tile counts.  The residue products
+ * of all problems, moduli, 256 x 256 output tiles and k parts run as ONE
+ * persistent launch (one workgroup per CU) that hands out a work list,
+ * longest item first, through an atomic counter.  Its configuration (the
+ * tile program and the split-K limit, see ozaki2_set_schedule) is the
+ * default, the autotuner's choice (ozaki2_set_autotune) or a forced one.
+ * Split-K applies to problems with at most 4 output tiles per modulus and a
+ * padded k of at least 512: their k range is cut into up to 4 parts whose
+ * products go to separate copies of the residue planes, summed by the CRT.
+ * Problems are packed into sub-batches whose workspaces fit the workspace at
+ * once; sub-batches run one after another.
  * The per-batch descriptors are built on the host and uploaded once per
  * distinct argument list (the last 8 are cached per thread, with their
  * captured graphs, see ozaki2_set_graph).
  *
  * Workspace: problem q of a sub-batch uses the layout of
- * ozaki2_workspace_layout at the sum of ozaki2_workspace_bytes of the
- * sub-batch's earlier problems.  A caller workspace (ozaki2_set_workspace)
+ * ozaki2_workspace_layout, with 4 copies of the residue planes for a problem
+ * that split-K may apply to, at the sum of the earlier problems' sizes (each
+ * its ozaki2_workspace_bytes plus those extra copies, 2 N mp np bytes
+ * each).  A caller workspace (ozaki2_set_workspace)
  * must hold the largest problem; the library-owned one grows to the whole
  * batch (ozaki2_workspace_bytes_batched), capped at 16 GiB.
  *
@@ -236,9 +244,10 @@ int ozaki2_dgemm_batched(int count, const char *transA, const char *transB,
                          double *const *C, const int64_t *ldc, int num_moduli);
 
 /* ozaki2_workspace_bytes_batched - workspace for running the whole batch as
- * one sub-batch (the sum of ozaki2_workspace_bytes over problems with
- * m, n, k > 0); 0 for invalid sizes and when a problem's size or the sum
- * does not fit in size_t. */
+ * one sub-batch (the sum over problems with m, n, k > 0 of
+ * ozaki2_workspace_bytes plus, for problems split-K may apply to, three more
+ * copies of the residue planes); 0 for invalid sizes and when a problem's
+ * size or the sum does not fit in size_t. */
 size_t ozaki2_workspace_bytes_batched(int count, const int64_t *m, const int64_t *n,
                                       const int64_t *k, int num_moduli);
 
@@ -256,18 +265,34 @@ int ozaki2_set_graph(int on);
 
 /*
  * ozaki2_set_autotune - when on, the first batched call of a new set of
- * problem shapes times the grouped residue products under each schedule
- * (tile order: problem order or largest first; one workgroup per tile or
- * one per CU looping over tiles) on the call's own data, keeps the fastest
- * for those shapes (process-wide), and then runs the call.  Off (default):
- * problem order, one workgroup per tile, unless the shapes were tuned before.
+ * problem shapes times the persistent residue products under each
+ * configuration (see ozaki2_set_schedule) on the call's own data, keeps the
+ * fastest for those shapes (process-wide) and then runs the call.  When the
+ * environment variable OZ2_AUTOTUNE_CACHE names a file, choices are also
+ * kept there per shape bucket (number of moduli, mode, modulus list and the
+ * histogram of the problems over log2 of their output tiles per modulus and
+ * log2 of their 256-blocks of k), read by later processes; a missing or
+ * malformed file is ignored (default configuration, or tuning again).  Off
+ * (default): the default configuration unless the shapes or their bucket
+ * were tuned before.
  */
 int ozaki2_set_autotune(int on);
 
-/* ozaki2_get_schedule - residue-product schedule (0..3: bit 0 largest
- * first, bit 1 one workgroup per CU) of the calling thread's last batched
- * call, or -1 if there was none. */
+/* ozaki2_get_schedule - residue-product configuration (0..5, see
+ * ozaki2_set_schedule) of the calling thread's last batched call, or -1 if
+ * there was none. */
 int ozaki2_get_schedule(void);
+
+/*
+ * ozaki2_set_schedule - force the residue-product configuration of the
+ * calling thread's subsequent batched calls, or -1 (default) to leave it to
+ * the autotuner.  config / 3 is the tile program of the 256 x 256 output
+ * tiles (0: eight waves of 128 x 64 outputs, two per SIMD; 1: four waves of
+ * 128 x 128, one per SIMD); config % 3 the split-K limit (at most 1, 2 or 4
+ * k parts).  Every configuration gives bit-identical results.  Returns 0, or
+ * -1 for a value outside -1..5 (the setting is then unchanged).
+ */
+int ozaki2_set_schedule(int config);
 
 /*
  * ozaki2_set_mode - scaling mode of the calling thread's subsequent

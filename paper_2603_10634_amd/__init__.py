@@ -17,7 +17,7 @@ __all__ = [
     "ozaki2_set_workspace", "ozaki2_set_timing", "ozaki2_get_stage_times",
     "ozaki2_get_kernel_times", "ozaki2_moduli", "ozaki2_workspace_layout", "ozaki2_release",
     "ozaki2_status_string", "ozaki2_dgemm_batched", "ozaki2_workspace_bytes_batched",
-    "ozaki2_set_graph", "ozaki2_set_autotune", "ozaki2_get_schedule", "ozaki2_set_mode",
+    "ozaki2_set_graph", "ozaki2_set_autotune", "ozaki2_get_schedule", "ozaki2_set_schedule", "ozaki2_set_mode",
     "ozaki2_get_mode", "MODE_ACCURATE", "MODE_FAST", "ozaki2_set_moduli_list",
     "ozaki2_get_moduli_list", "MODULI_HYBRID", "MODULI_KARATSUBA", "MODULI_INT8",
     "ozaki2_set_blocking", "ozaki2_get_blocking", "dgemm", "dgemm_batched",
@@ -85,6 +85,7 @@ def lib() -> ctypes.CDLL:
         "ozaki2_set_graph": (ctypes.c_int, [ctypes.c_int]),
         "ozaki2_set_autotune": (ctypes.c_int, [ctypes.c_int]),
         "ozaki2_get_schedule": (ctypes.c_int, []),
+        "ozaki2_set_schedule": (ctypes.c_int, [ctypes.c_int]),
         "ozaki2_set_mode": (ctypes.c_int, [ctypes.c_int]),
         "ozaki2_get_mode": (ctypes.c_int, []),
         "ozaki2_set_moduli_list": (ctypes.c_int, [ctypes.c_int]),
@@ -231,6 +232,12 @@ def ozaki2_set_autotune(on: bool) -> int:
 
 def ozaki2_get_schedule() -> int:
     return lib().ozaki2_get_schedule()
+
+
+def ozaki2_set_schedule(config: int) -> int:
+    """Force the batched residue-product configuration (0..5), or -1 for the
+    default / autotuned one."""
+    return lib().ozaki2_set_schedule(int(config))
 
 
 def _mode_code(mode) -> int:

@@ -26,8 +26,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 
-SOURCES = ["oz2_tables.cpp", "oz2_api.cpp", "oz2_quant.hip", "oz2_scale.hip",
-           "oz2_gemm.hip", "oz2_crt.hip"]
+SOURCES = ["oz2_tables.cpp", "oz2_api.cpp", "oz2_quant.hip",
+           "oz2_scale.hip", "oz2_gemm.hip", "oz2_crt.hip"]
 
 
 def _compile(src: str) -> str:

@@ -3,6 +3,8 @@
 // the same sequence over a batch of problems as one grouped launch per
 // kernel family, optionally captured in a hipGraph and with an autotuned
 // residue-product schedule.
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -10,6 +12,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <tuple>
 #include <utility>
 #include <vector>
@@ -38,7 +41,8 @@ struct ThreadState {
   bool have_times = false;
   bool graph = false;                      // capture launch sequences in hipGraphs
   bool autotune = false;                   // tune the grouped residue-product schedule
-  int last_schedule = -1;                  // schedule of the last batched call
+  int last_schedule = -1;                  // configuration of the last batched call
+  int forced = -1;                         // configuration set by ozaki2_set_schedule
   int mode = OZ2_MODE_ACCURATE;            // scaling mode (Section III-E)
   int list = OZ2_MODULI_HYBRID;            // modulus list (Sections III-B, III-D)
   int64_t blk_m = 0, blk_n = 0;            // m/n blocking of ozaki2_dgemm (0: none)
@@ -59,6 +63,30 @@ std::map<std::pair<int, int>, Tables> g_host_tables;     // (N, list) -> host co
 std::map<std::vector<int64_t>, int> g_tuned;
 
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+// Fault injection for tests of the error paths: with OZ2_FAULT=alloc in the
+// environment (read once per process) every device or pinned allocation the
+// library would make fails as if the runtime had refused it.
+bool fault_alloc() {
+  static const bool on = [] {
+    const char *f = getenv("OZ2_FAULT");
+    return f && strcmp(f, "alloc") == 0;
+  }();
+  return on;
+}
+
+// Split-K in batched calls: a problem with at most kSplitTiles output tiles
+// of 256 x 256 per modulus and at least two 256-blocks of k may have its
+// residue products split into up to kMaxParts k parts, each written to its
+// own copy of the residue planes (the CRT sums them); its batched workspace
+// holds kMaxParts copies.
+constexpr int kMaxParts = 4;
+constexpr int64_t kSplitTiles = 4;
+
+int parts_alloc(int64_t m, int64_t n, int64_t k) {
+  const int64_t tiles = (round_up(m, kPad) / kPad) * (round_up(n, kPad) / kPad);
+  return tiles <= kSplitTiles && round_up(k, kPad) >= 2 * kPad ? kMaxParts : 1;
+}
 
 struct Layout {
   int64_t mp, np, kp;
@@ -85,7 +113,7 @@ const Tables *host_tables(int N, int list) {
 // zero-initialised per-line vectors come first and contiguously so one fill
 // clears them.
 bool make_layout(int64_t m, int64_t n, int64_t k, int N, Layout *L, int64_t mb = 0,
-                 int64_t nb = 0) {
+                 int64_t nb = 0, int parts = 1) {
   const Tables *ht = host_tables(N, g_ts.list);
   if (!ht) return false;
   const Tables &t = *ht;
@@ -127,7 +155,7 @@ bool make_layout(int64_t m, int64_t n, int64_t k, int N, Layout *L, int64_t mb =
   take(4, size3(L->np, L->kp, 1));             // Bbar
   take(5, size3(t.M, L->mbp, L->kp));          // A slices (one block)
   take(6, size3(t.M, L->nbp, L->kp));          // B slices
-  take(7, size3(sizeof(int16_t) * N, L->mbp, L->nbp));  // planes
+  take(7, size3(sizeof(int16_t) * N * parts, L->mbp, L->nbp));  // planes (per k part)
   L->off[8] = L->off[12];
   L->off[9] = L->off[11];
   L->off[16] = L->off[14];
@@ -159,7 +187,7 @@ const Tables *device_tables(int dev, int N, int list, hipError_t *err) {
   auto it = g_tables.find(key);
   if (it != g_tables.end()) return it->second;
   Tables *d = nullptr;
-  *err = hipMalloc((void **)&d, sizeof(Tables));
+  *err = fault_alloc() ? hipErrorOutOfMemory : hipMalloc((void **)&d, sizeof(Tables));
   if (*err != hipSuccess) return nullptr;
   *err = hipMemcpy(d, h, sizeof(Tables), hipMemcpyHostToDevice);
   if (*err != hipSuccess) {
@@ -233,6 +261,7 @@ Problem make_problem(char transA, char transB, int64_t m, int64_t n, int64_t k, 
   P.ldc = ldc;
   P.limbs = ht->limbs;
   P.mode = g_ts.mode;
+  P.parts = 1;
   return P;
 }
 
@@ -269,7 +298,7 @@ int enqueue_scaling(const Problem &P, hipStream_t st, Marks &mark) {
     OZ2_TRY(launch_quant_family(f, &P, nullptr, st));
   mark();
   // step 2: the FP8 bound product (its line maxima only; none in fast mode)
-  if (!fast) OZ2_TRY(launch_gemm_family(kFamBgemm, &P, nullptr, 0, 0, st));
+  if (!fast) OZ2_TRY(launch_gemm_family(kFamBgemm, &P, nullptr, 0, st));
   mark();
   // step 3: scale exponents mu, nu
   if (!fast)
@@ -290,7 +319,7 @@ int enqueue_products(const Problem &P, hipStream_t st, Marks &mark, bool res_a =
   // steps 7-8: residue products and their reduction modulo p, per k chunk
   for (int c = 0; c < num_chunks(P.g.kp); ++c)
     for (int f : {kFamGemmSq, kFamGemmKa, kFamGemmI8})
-      OZ2_TRY(launch_gemm_family(f, &P, nullptr, c, 0, st));
+      OZ2_TRY(launch_gemm_family(f, &P, nullptr, c, st));
   mark();
   // steps 9-10: CRT and inverse scaling
   OZ2_TRY(launch_crt_family(&P, nullptr, P.limbs, P.g.N, st));
@@ -350,18 +379,31 @@ int enqueue_blocked(const Problem &P, int64_t mb, int64_t nb, hipStream_t st) {
 
 // ---- batched calls ----
 
-// Grouped residue-product schedules the autotuner chooses from: bit 0 set
-// orders tiles largest problem first (else in problem order), bit 1 set runs
-// one workgroup per CU looping over tiles (else one workgroup per tile).
-constexpr int kNumSchedules = 4;
+// Configurations of the batched residue products, chosen by the autotuner:
+// the tile program (config / 3: 0 = eight waves of 128 x 64 outputs per
+// 256 x 256 tile, two per SIMD; 1 = four waves of 128 x 128, one per SIMD)
+// and the split-K limit (config % 3: at most 1, 2 or 4 k parts for the
+// problems that parts_alloc allows to split).  Config 0 is the default.
+constexpr int kNumConfigs = 6;
+int config_waves(int c) { return c / 3 == 0 ? 8 : 4; }
+int config_max_parts(int c) { return c % 3 == 0 ? 1 : (c % 3 == 1 ? 2 : 4); }
+
+// The persistent launch of the residue products (not a kernel family of the
+// single-problem path).
+constexpr int kFamPersist = kNumFamilies;
 
 // One grouped launch of a sub-batch.  The descriptor arrays live in the
-// plan's device buffer at the given byte offsets; G is filled in once the
-// buffer exists.
+// plan's device buffer at the given byte offsets; G (or W for the persistent
+// products) is filled in once the buffer exists.  The products and the CRT
+// exist once per configuration (they differ in the k parts).
 struct GLaunch {
-  int fam, chunk, order;  // order: 0 problem order, 1 largest first (products only)
+  int fam, config;  // config: -1 for the launches every configuration shares
   size_t off_probs, off_order, off_start;
+  size_t off_items, off_counters;
+  int64_t items;
+  bool int8;
   Group G;
+  WorkList W;
 };
 
 // Problems whose workspaces fit together, run as one set of grouped launches.
@@ -390,8 +432,9 @@ struct Plan {
     int64_t ldc;
   };
   std::vector<Scal> scal;
-  std::vector<int64_t> shape_key;  // for the autotuner's cache
-  int schedule = -1;
+  std::vector<int64_t> shape_key;  // N, mode, list, then (m, n, k) of each emulated problem
+  std::string bucket;              // the shapes' bucket (the autotuner's cache file key)
+  int schedule = -1;               // the residue-product configuration
   bool single = false;
   Problem single_problem;
   hipGraph_t graph = nullptr;
@@ -403,6 +446,114 @@ struct Plan {
     if (hbuf) (void)hipHostFree(hbuf);
   }
 };
+
+// ---- the autotuner's cache file ----
+//
+// Choices are kept per process by exact shapes (g_tuned) and, when the
+// environment names a file in OZ2_AUTOTUNE_CACHE, per shape bucket in that
+// file across processes.  A bucket is the number of moduli, the mode, the
+// list and the histogram of the problems over (log2 of the output tiles per
+// modulus, log2 of the 256-blocks of k).  The file is JSON, one entry per
+// line:
+//   {"oz2_autotune": 1, "entries": [
+//   {"key": "...", "config": 3},
+//   ...
+//   ]}
+// A missing file, or one that does not parse line by line in this form or
+// holds a configuration out of range, is ignored: every batch then starts
+// from the default configuration (or is tuned again when tuning is on, and
+// the file is rewritten).
+std::map<std::string, int> g_cache;
+bool g_cache_loaded = false;
+
+int ilog2_floor(int64_t v) {
+  int r = 0;
+  while (v > 1) {
+    v >>= 1;
+    ++r;
+  }
+  return r;
+}
+
+std::string bucket_key(const std::vector<int64_t> &shape_key) {
+  std::map<std::pair<int, int>, int> hist;
+  for (size_t q = 3; q + 2 < shape_key.size(); q += 3) {
+    const int64_t tiles = (round_up(shape_key[q], kPad) / kPad) *
+                          (round_up(shape_key[q + 1], kPad) / kPad);
+    const int64_t kb = round_up(shape_key[q + 2], kPad) / kPad;
+    ++hist[{ilog2_floor(tiles), ilog2_floor(kb)}];
+  }
+  std::string key = "n" + std::to_string(shape_key[0]) + "m" + std::to_string(shape_key[1]) +
+                    "l" + std::to_string(shape_key[2]) + ":";
+  for (const auto &h : hist)
+    key += "t" + std::to_string(h.first.first) + "k" + std::to_string(h.first.second) + "x" +
+           std::to_string(h.second) + ";";
+  return key;
+}
+
+const char *cache_path() {
+  const char *p = getenv("OZ2_AUTOTUNE_CACHE");
+  return p && *p ? p : nullptr;
+}
+
+// Reads the cache file once per process (caller holds g_mu).
+void cache_load_locked() {
+  if (g_cache_loaded) return;
+  g_cache_loaded = true;
+  const char *path = cache_path();
+  if (!path) return;
+  FILE *f = fopen(path, "r");
+  if (!f) return;
+  std::map<std::string, int> got;
+  char line[4096];
+  static const char kHead[] = "{\"oz2_autotune\": 1, \"entries\": [";
+  bool ok = fgets(line, sizeof(line), f) && strncmp(line, kHead, sizeof(kHead) - 1) == 0;
+  bool closed = false;
+  while (ok && fgets(line, sizeof(line), f)) {
+    if (strncmp(line, "]}", 2) == 0) {
+      closed = true;
+      break;
+    }
+    char key[2048];
+    int config = -1, used = 0;
+    if (sscanf(line, "{\"key\": \"%2047[^\"]\", \"config\": %d}%n", key, &config, &used) != 2 ||
+        used == 0 || config < 0 || config >= kNumConfigs) {
+      ok = false;
+      break;
+    }
+    got[key] = config;
+  }
+  fclose(f);
+  if (ok && closed) g_cache = got;
+}
+
+int cache_lookup(const std::string &bucket) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  cache_load_locked();
+  auto it = g_cache.find(bucket);
+  return it == g_cache.end() ? -1 : it->second;
+}
+
+// Records a choice and rewrites the file (through a temporary file renamed
+// over it, so a reader never sees half a file).
+void cache_store(const std::string &bucket, int config) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  cache_load_locked();
+  g_cache[bucket] = config;
+  const char *path = cache_path();
+  if (!path) return;
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE *f = fopen(tmp.c_str(), "w");
+  if (!f) return;
+  fprintf(f, "{\"oz2_autotune\": 1, \"entries\": [\n");
+  size_t i = 0;
+  for (const auto &e : g_cache)
+    fprintf(f, "{\"key\": \"%s\", \"config\": %d}%s\n", e.first.c_str(), e.second,
+            ++i < g_cache.size() ? "," : "");
+  fprintf(f, "]}\n");
+  const bool good = fclose(f) == 0;
+  if (good) (void)rename(tmp.c_str(), path);
+}
 
 struct KeyBuilder {
   std::vector<uint8_t> b;
@@ -499,33 +650,25 @@ struct ImageWriter {
 };
 
 // The grouped launches of one sub-batch: every family over all its problems,
-// the residue products per k chunk and in both tile orders.
+// and per configuration the persistent residue products (one work list over
+// every problem, modulus, tile and k part, longest item first) and the CRT
+// (over descriptors that carry the configuration's k parts).
 void build_subbatch(const std::vector<Problem> &probs, ImageWriter &W, SubBatch *sb) {
   const int np = (int)probs.size();
   const size_t at_probs = W.put(probs.data(), sizeof(Problem) * np);
-  std::vector<int32_t> nat(np), lpt(np);
-  for (int q = 0; q < np; ++q) nat[q] = lpt[q] = q;
-  std::stable_sort(lpt.begin(), lpt.end(), [&](int a, int b) {
-    const Geometry &x = probs[a].g, &y = probs[b].g;
-    return (double)x.mp * x.np * x.kp > (double)y.mp * y.np * y.kp;
-  });
+  std::vector<int32_t> nat(np);
+  for (int q = 0; q < np; ++q) nat[q] = q;
   const size_t at_nat = W.put(nat.data(), sizeof(int32_t) * np);
-  const size_t at_lpt = W.put(lpt.data(), sizeof(int32_t) * np);
-  int chunks = 0;
-  for (const Problem &P : probs) chunks = std::max(chunks, num_chunks(P.g.kp));
-  auto add = [&](int fam, int chunk, int order) {
-    const std::vector<int32_t> &ord = order ? lpt : nat;
+  auto add = [&](int fam, size_t off_probs, int config) {
     std::vector<int64_t> start(np + 1, 0);
-    for (int q = 0; q < np; ++q)
-      start[q + 1] = start[q] + family_blocks(fam, probs[ord[q]], chunk);
+    for (int q = 0; q < np; ++q) start[q + 1] = start[q] + family_blocks(fam, probs[q], 0);
     if (start[np] == 0) return;
     GLaunch L;
     memset(&L, 0, sizeof(L));
     L.fam = fam;
-    L.chunk = chunk;
-    L.order = order;
-    L.off_probs = at_probs;
-    L.off_order = order ? at_lpt : at_nat;
+    L.config = config;
+    L.off_probs = off_probs;
+    L.off_order = at_nat;
     L.off_start = W.put(start.data(), sizeof(int64_t) * (np + 1));
     L.G.nseg = np;
     L.G.total = start[np];
@@ -535,19 +678,57 @@ void build_subbatch(const std::vector<Problem> &probs, ImageWriter &W, SubBatch 
   if (probs[0].mode == OZ2_MODE_FAST) {
     for (int f : {kFamFill, kFamLmaxA, kFamLmaxB, kFamNormA, kFamNormB, kFamFinal, kFamResA,
                   kFamResB})
-      add(f, 0, 0);
+      add(f, at_probs, -1);
   } else {
     for (int f : {kFamFill, kFamLmaxA, kFamLmaxB, kFamBarA, kFamBarB, kFamBgemm, kFamDecide,
                   kFamFixup, kFamFinal, kFamResA, kFamResB})
-      add(f, 0, 0);
+      add(f, at_probs, -1);
   }
-  for (int order = 0; order < 2; ++order)
-    for (int c = 0; c < chunks; ++c) {
-      add(kFamGemmSq, c, order);
-      add(kFamGemmKa, c, order);
-      add(kFamGemmI8, c, order);
+  const uint32_t zero2[2] = {0u, 0u};
+  const size_t at_counters = W.put(zero2, sizeof(zero2));
+  for (int c = 0; c < kNumConfigs; ++c) {
+    std::vector<Problem> pc(probs);
+    std::vector<ProductItem> items;
+    for (int q = 0; q < np; ++q) {
+      const Geometry &g = pc[q].g;
+      const int64_t nb = g.kp / kPad;  // 256-blocks of k
+      int parts = 1;
+      if (parts_alloc(g.m, g.n, g.k) > 1) parts = (int)std::min<int64_t>(config_max_parts(c), nb);
+      pc[q].parts = parts;
+      for (int l = 0; l < g.N; ++l)
+        for (int64_t ty = 0; ty < g.np / kGemmTJ; ++ty)
+          for (int64_t tx = 0; tx < g.mp / kGemmTIW; ++tx)
+            for (int part = 0; part < parts; ++part) {
+              ProductItem it;
+              it.prob = q;
+              it.l = (int16_t)l;
+              it.part = (int16_t)part;
+              it.tx = (int32_t)tx;
+              it.ty = (int32_t)ty;
+              it.k0 = (int32_t)(part * nb / parts * kPad);
+              it.k1 = (int32_t)((part + 1) * nb / parts * kPad);
+              items.push_back(it);
+            }
     }
-  add(kFamCrt, 0, 0);
+    // longest first (every item costs in proportion to its k extent)
+    std::stable_sort(items.begin(), items.end(), [](const ProductItem &a, const ProductItem &b) {
+      return a.k1 - a.k0 > b.k1 - b.k0;
+    });
+    const size_t at_pc = W.put(pc.data(), sizeof(Problem) * np);
+    if (!items.empty()) {
+      GLaunch L;
+      memset(&L, 0, sizeof(L));
+      L.fam = kFamPersist;
+      L.config = c;
+      L.off_probs = at_pc;
+      L.off_items = W.put(items.data(), sizeof(ProductItem) * items.size());
+      L.off_counters = at_counters;
+      L.items = (int64_t)items.size();
+      L.int8 = probs[0].g.list == OZ2_MODULI_INT8;
+      sb->launches.push_back(L);
+    }
+    add(kFamCrt, at_pc, c);
+  }
 }
 
 // Kernel group of a family, as reported by ozaki2_get_kernel_times.
@@ -556,20 +737,18 @@ int family_group(int fam) {
     case kFamBgemm: return 1;
     case kFamDecide: case kFamFixup: case kFamFinal: return 2;
     case kFamResA: case kFamResB: return 3;
-    case kFamGemmSq: case kFamGemmKa: case kFamGemmI8: return 4;
+    case kFamGemmSq: case kFamGemmKa: case kFamGemmI8: case kFamPersist: return 4;
     case kFamCrt: return 5;
     default: return 0;
   }
 }
 
 // Enqueues the kernel groups g0..g1 (numbered as in ozaki2_get_kernel_times)
-// of sub-batch sb with residue-product schedule `sched`.  Marks are placed at
-// every group boundary when the whole sequence runs.  With `ev` non-null,
-// ev[0] and ev[1] bracket the residue products (group 4).
-int enqueue_subbatch(const SubBatch &sb, int sched, int cus, hipStream_t st, Marks &mark,
+// of sub-batch sb with residue-product configuration `config`.  Marks are
+// placed at every group boundary when the whole sequence runs.  With `ev`
+// non-null, ev[0] and ev[1] bracket the residue products (group 4).
+int enqueue_subbatch(const SubBatch &sb, int config, int cus, hipStream_t st, Marks &mark,
                      hipEvent_t *ev, int g0 = 0, int g1 = 5) {
-  const int order = sched & 1;
-  const int64_t grid = (sched & 2) ? cus : 0;
   int group = -1;
   auto advance = [&](int to) -> int {
     while (group < to) {
@@ -581,13 +760,14 @@ int enqueue_subbatch(const SubBatch &sb, int sched, int cus, hipStream_t st, Mar
     return OZ2_SUCCESS;
   };
   for (const GLaunch &L : sb.launches) {
-    const bool gemm = L.fam == kFamGemmSq || L.fam == kFamGemmKa || L.fam == kFamGemmI8;
-    if (gemm && L.order != order) continue;
+    if (L.config >= 0 && L.config != config) continue;
     const int gq = family_group(L.fam);
     if (gq < g0 || gq > g1) continue;
     if (advance(gq) != OZ2_SUCCESS) return OZ2_ERR_HIP;
-    if (gemm || L.fam == kFamBgemm)
-      OZ2_TRY(launch_gemm_family(L.fam, nullptr, &L.G, L.chunk, grid, st));
+    if (L.fam == kFamPersist)
+      OZ2_TRY(launch_gemm_persistent(config_waves(config), L.int8, L.W, cus, st));
+    else if (L.fam == kFamBgemm)
+      OZ2_TRY(launch_gemm_family(L.fam, nullptr, &L.G, 0, st));
     else if (L.fam == kFamDecide || L.fam == kFamFixup || L.fam == kFamFinal)
       OZ2_TRY(launch_scale_family(L.fam, nullptr, &L.G, st));
     else if (L.fam == kFamCrt)
@@ -596,6 +776,23 @@ int enqueue_subbatch(const SubBatch &sb, int sched, int cus, hipStream_t st, Mar
       OZ2_TRY(launch_quant_family(L.fam, nullptr, &L.G, st));
   }
   return advance(g1 + 1);
+}
+
+// Argument checks of ozaki2_dgemm in BLAS order: 0, or -i for argument i.
+int check_args(char transA, char transB, int64_t m, int64_t n, int64_t k, int64_t lda,
+               int64_t ldb, int64_t ldc, int num_moduli) {
+  if (!valid_trans(transA)) return -1;
+  if (!valid_trans(transB)) return -2;
+  if (m < 0) return -3;
+  if (n < 0) return -4;
+  if (k < 0) return -5;
+  const int64_t rowsA = is_trans(transA) ? k : m;
+  const int64_t rowsB = is_trans(transB) ? n : k;
+  if (lda < (rowsA > 1 ? rowsA : 1)) return -8;
+  if (ldb < (rowsB > 1 ? rowsB : 1)) return -10;
+  if (ldc < (m > 1 ? m : 1)) return -13;
+  if (num_moduli < 1 || num_moduli > OZ2_MAX_MODULI) return -14;
+  return 0;
 }
 
 }  // namespace
@@ -731,7 +928,7 @@ static int get_workspace(int dev, size_t need, uint8_t **ws, size_t *have) {
     ts.own_ws_bytes = 0;
   }
   if (!ts.own_ws) {
-    if (hipMalloc(&ts.own_ws, need) != hipSuccess) {
+    if (fault_alloc() || hipMalloc(&ts.own_ws, need) != hipSuccess) {
       ts.own_ws = nullptr;
       (void)hipGetLastError();
       return OZ2_ERR_ALLOC;
@@ -747,18 +944,8 @@ static int get_workspace(int dev, size_t need, uint8_t **ws, size_t *have) {
 int ozaki2_dgemm(char transA, char transB, int64_t m, int64_t n, int64_t k, double alpha,
                  const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
                  double *C, int64_t ldc, int num_moduli) {
-  // ---- argument checks (BLAS order) ----
-  if (!valid_trans(transA)) return -1;
-  if (!valid_trans(transB)) return -2;
-  if (m < 0) return -3;
-  if (n < 0) return -4;
-  if (k < 0) return -5;
-  const int64_t rowsA = is_trans(transA) ? k : m;
-  const int64_t rowsB = is_trans(transB) ? n : k;
-  if (lda < (rowsA > 1 ? rowsA : 1)) return -8;
-  if (ldb < (rowsB > 1 ? rowsB : 1)) return -10;
-  if (ldc < (m > 1 ? m : 1)) return -13;
-  if (num_moduli < 1 || num_moduli > OZ2_MAX_MODULI) return -14;
+  const int bad = check_args(transA, transB, m, n, k, lda, ldb, ldc, num_moduli);
+  if (bad) return bad;
 
   ThreadState &ts = g_ts;
   hipStream_t st = ts.stream;
@@ -775,7 +962,7 @@ int ozaki2_dgemm(char transA, char transB, int64_t m, int64_t n, int64_t k, doub
   if (!make_layout(m, n, k, num_moduli, &L, ts.blk_m, ts.blk_n)) return OZ2_ERR_UNSUPPORTED;
   hipError_t herr = hipSuccess;
   const Tables *dt = device_tables(dev, num_moduli, ts.list, &herr);
-  if (!dt) return OZ2_ERR_HIP;
+  if (!dt) return herr == hipErrorOutOfMemory ? OZ2_ERR_ALLOC : OZ2_ERR_HIP;
   const Tables *ht = host_tables(num_moduli, ts.list);
 
   uint8_t *ws = nullptr;
@@ -870,7 +1057,8 @@ size_t ozaki2_workspace_bytes_batched(int count, const int64_t *m, const int64_t
     if (m[q] < 0 || n[q] < 0 || k[q] < 0) return 0;
     if (m[q] == 0 || n[q] == 0 || k[q] == 0) continue;
     Layout L;
-    if (!make_layout(m[q], n[q], k[q], num_moduli, &L)) return 0;
+    if (!make_layout(m[q], n[q], k[q], num_moduli, &L, 0, 0, parts_alloc(m[q], n[q], k[q])))
+      return 0;
     if (__builtin_add_overflow(total, L.total, &total)) return 0;
   }
   return total;
@@ -899,7 +1087,7 @@ int ozaki2_dgemm_batched(int count, const char *transA, const char *transB, cons
   hipStream_t st = ts.stream;
   hipError_t herr = hipSuccess;
   const Tables *dt = device_tables(dev, num_moduli, ts.list, &herr);
-  if (!dt) return OZ2_ERR_HIP;
+  if (!dt) return herr == hipErrorOutOfMemory ? OZ2_ERR_ALLOC : OZ2_ERR_HIP;
   const Tables *ht = host_tables(num_moduli, ts.list);
 
   // workspace: library-owned grows to the whole batch, capped at 16 GiB
@@ -908,7 +1096,9 @@ int ozaki2_dgemm_batched(int count, const char *transA, const char *transB, cons
   size_t total = 0, largest = 0;
   for (int q = 0; q < count; ++q) {
     if (!emulated(m[q], n[q], k[q], alpha[q])) continue;
-    if (!make_layout(m[q], n[q], k[q], num_moduli, &lays[q])) return OZ2_ERR_UNSUPPORTED;
+    if (!make_layout(m[q], n[q], k[q], num_moduli, &lays[q], 0, 0,
+                     parts_alloc(m[q], n[q], k[q])))
+      return OZ2_ERR_UNSUPPORTED;
     if (__builtin_add_overflow(total, lays[q].total, &total)) total = SIZE_MAX;
     largest = std::max(largest, lays[q].total);
   }
@@ -926,6 +1116,7 @@ int ozaki2_dgemm_batched(int count, const char *transA, const char *transB, cons
   kb.add(ts.mode);
   kb.add(ts.list);
   kb.add(num_moduli);
+  kb.add(ts.forced);
   kb.add(count);
   kb.add(ws);
   kb.add(have);
@@ -963,6 +1154,8 @@ int ozaki2_dgemm_batched(int count, const char *transA, const char *transB, cons
       used = 0;
     };
     p->shape_key.push_back(num_moduli);
+    p->shape_key.push_back(ts.mode);
+    p->shape_key.push_back(ts.list);
     for (int q = 0; q < count; ++q) {
       if (m[q] == 0 || n[q] == 0) continue;
       if (!emulated(m[q], n[q], k[q], alpha[q])) {
@@ -980,7 +1173,7 @@ int ozaki2_dgemm_batched(int count, const char *transA, const char *transB, cons
     flush();
     p->bytes = W.img.size();
     if (p->bytes) {
-      if (hipMalloc(&p->dbuf, p->bytes) != hipSuccess) {
+      if (fault_alloc() || hipMalloc(&p->dbuf, p->bytes) != hipSuccess) {
         (void)hipGetLastError();
         return OZ2_ERR_ALLOC;
       }
@@ -992,16 +1185,25 @@ int ozaki2_dgemm_batched(int count, const char *transA, const char *transB, cons
       uint8_t *base = (uint8_t *)p->dbuf;
       for (SubBatch &sb : p->subs)
         for (GLaunch &L : sb.launches) {
+          if (L.fam == kFamPersist) {
+            L.W.probs = (const Problem *)(base + L.off_probs);
+            L.W.items = (const ProductItem *)(base + L.off_items);
+            L.W.count = L.items;
+            L.W.counters = (uint32_t *)(base + L.off_counters);
+            continue;
+          }
           L.G.probs = (const Problem *)(base + L.off_probs);
           L.G.order = (const int32_t *)(base + L.off_order);
           L.G.start = (const int64_t *)(base + L.off_start);
         }
     }
+    p->bucket = bucket_key(p->shape_key);
     {
       std::lock_guard<std::mutex> lk(g_mu);
       auto it = g_tuned.find(p->shape_key);
       if (it != g_tuned.end()) p->schedule = it->second;
     }
+    if (p->schedule < 0) p->schedule = cache_lookup(p->bucket);
     plan = add_plan(std::move(p));
   }
   if (!plan->uploaded && plan->bytes) {
@@ -1011,37 +1213,44 @@ int ozaki2_dgemm_batched(int count, const char *transA, const char *transB, cons
   int cus = 256;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
 
-  // autotuner: on the first call of a new batch shape, run the first
-  // sub-batch's residue products under every schedule (the products are
-  // recomputed from the digit slices each time, so the result is the same)
-  // and keep the fastest
-  if (plan->schedule < 0 && ts.autotune && !plan->subs.empty()) {
+  // autotuner: on the first call of a new batch shape (no choice for its
+  // exact shapes in this process, none for its shape bucket in the cache
+  // file), run the first sub-batch's residue products under every
+  // configuration (tile program x split-K limit; the products are
+  // recomputed from the digit slices each time, into plane copies the CRT of
+  // the chosen configuration reads, so the result is the same) and keep the
+  // fastest
+  if (plan->schedule < 0 && ts.autotune && ts.forced < 0 && !plan->subs.empty()) {
     r = ensure_events(dev);
     if (r != OZ2_SUCCESS) return r;
     const SubBatch &sb = plan->subs[0];
     Marks none{&ts, st, false};
     float best = 0.0f;
-    int best_s = 0;
-    // the stages before the products once, then the products per schedule
-    // (the CRT, which reads C when beta != 0, runs only in the real pass)
+    int best_c = 0;
+    // the stages before the products once, then the products per
+    // configuration (the CRT, which reads C when beta != 0, runs only in the
+    // real pass)
     r = enqueue_subbatch(sb, 0, cus, st, none, nullptr, 0, 3);
     if (r != OZ2_SUCCESS) return r;
-    for (int sched = 0; sched < kNumSchedules; ++sched) {
-      r = enqueue_subbatch(sb, sched, cus, st, none, ts.ev, 4, 4);
+    for (int c = 0; c < kNumConfigs; ++c) {
+      r = enqueue_subbatch(sb, c, cus, st, none, ts.ev, 4, 4);
       if (r != OZ2_SUCCESS) return r;
       float t = 0.0f;
       OZ2_TRY(hipEventSynchronize(ts.ev[1]));
       OZ2_TRY(hipEventElapsedTime(&t, ts.ev[0], ts.ev[1]));
-      if (sched == 0 || t < best) {
+      if (c == 0 || t < best) {
         best = t;
-        best_s = sched;
+        best_c = c;
       }
     }
-    plan->schedule = best_s;
-    std::lock_guard<std::mutex> lk(g_mu);
-    g_tuned[plan->shape_key] = best_s;
+    plan->schedule = best_c;
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      g_tuned[plan->shape_key] = best_c;
+    }
+    cache_store(plan->bucket, best_c);
   }
-  const int sched = plan->schedule < 0 ? 0 : plan->schedule;
+  const int sched = ts.forced >= 0 ? ts.forced : (plan->schedule < 0 ? 0 : plan->schedule);
   ts.last_schedule = sched;
 
   auto enqueue_all = [&](hipStream_t s, bool timed) -> int {
@@ -1078,6 +1287,12 @@ int ozaki2_set_autotune(int on) {
 }
 
 int ozaki2_get_schedule(void) { return g_ts.last_schedule; }
+
+int ozaki2_set_schedule(int config) {
+  if (config < -1 || config >= kNumConfigs) return -1;
+  g_ts.forced = config;
+  return OZ2_SUCCESS;
+}
 
 int ozaki2_set_mode(int mode) {
   if (mode != OZ2_MODE_ACCURATE && mode != OZ2_MODE_FAST) return -1;

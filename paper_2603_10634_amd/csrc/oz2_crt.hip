@@ -26,7 +26,7 @@ __device__ __forceinline__ void crt_entry(const int16_t *__restrict__ planes,
                                           const Tables *__restrict__ tab, int N, int64_t m,
                                           int64_t mp, int64_t np, int64_t lineB, double alpha,
                                           double beta, double *__restrict__ C, int64_t ldc,
-                                          int64_t i, int64_t j) {
+                                          int64_t i, int64_t j, int parts) {
   if (i >= m) return;
   const bool bad = ((flags[i] | flags[lineB + j]) & kNonFinite) != 0;
   double chat;
@@ -53,6 +53,20 @@ __device__ __forceinline__ void crt_entry(const int16_t *__restrict__ planes,
         uu[l] = *ql;
         ql += pstride;
       }
+    if (parts > 1) {
+      // split-K: the residue products of each k part sit in their own copy
+      // of the planes; their sum modulo p_l is the residue (|sum| < 2^12, so
+      // the float quotient is within one and |u| <= p/2 + 1)
+      const int64_t cstride = (int64_t)N * pstride;
+#pragma unroll
+      for (int l = 0; l < kMaxN; ++l)
+        if (l < NN) {
+          int sum = uu[l];
+          for (int c = 1; c < parts; ++c) sum += pl[c * cstride + l * pstride];
+          const int p = tab->p[l];
+          uu[l] = sum - p * (int)rintf((float)sum * tab->inv_p[l]);
+        }
+    }
 #pragma unroll
     for (int l = 0; l < kMaxN; ++l) {
       if (l < NN) {
@@ -79,7 +93,7 @@ __global__ __launch_bounds__(256) void k_crt(Problem P1, Group G) {
   const int64_t nbx = (P.g.m + 255) / 256;
   const int64_t bx = local % nbx, j = local / nbx;
   crt_entry<L, NF>(P.w.planes, P.w.shift, P.w.flags, P.tab, P.g.N, P.g.m, P.g.mp, P.g.np,
-               P.w.lineB, P.alpha, P.beta, P.C, P.ldc, bx * 256 + threadIdx.x, j);
+                   P.w.lineB, P.alpha, P.beta, P.C, P.ldc, bx * 256 + threadIdx.x, j, P.parts);
 }
 
 __global__ void k_scal(int64_t m, double beta, double *__restrict__ C, int64_t ldc) {

@@ -87,8 +87,8 @@ __device__ __forceinline__ v16i mma(v8i a, v8i b, v16i c) {
 // row0 is always a multiple of 32, so the swizzle of row row0 + (l % 32) is
 // that of l % 32: the per-lane byte offsets do not depend on row0, and every
 // read is one per-lane address plus a constant (the ds_read immediate).
-__device__ __forceinline__ v8i lds_frag(const uint8_t *tile, int row0) {
-  const int lane = threadIdx.x & 63;
+__device__ __forceinline__ v8i lds_frag(const uint8_t *tile, int row0, int tid) {
+  const int lane = tid & 63;
   const int x = lane & 31, g = lane >> 5;
   const int f = swz(x);
   const uint8_t *row = tile + (row0 + x) * ROWB;
@@ -206,11 +206,11 @@ template <int NW> constexpr int LP() { return 16 / NW; }
 // Lane offsets of the wide loads: wave w loads rows 16 (w + NWW u) .. + 15 of
 // each side for u < LPW (both sides have 256 rows).
 template <int NW>
-__device__ __forceinline__ DmaOffsets dma_offsets_w(int64_t rowsB, int64_t rowsA) {
+__device__ __forceinline__ DmaOffsets dma_offsets_w(int64_t rowsB, int64_t rowsA, int tid) {
   constexpr int LPW = LP<NW>(), NWW = NW;
   DmaOffsets d;
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int rsub = lane >> 2, pc = lane & 3;
 #pragma unroll
   for (int u = 0; u < LPW; ++u) {
@@ -267,10 +267,10 @@ __device__ __forceinline__ void stage_iter_w(int j, int nk, const uint8_t *gB, c
                                              const DmaOffsets &d, int64_t kbeg,
                                              const uint8_t *lds, uint32_t ring,
                                              const v8i (&fa)[TB<NW>()], v8i (&fan)[TB<NW>()],
-                                             v8i (&fb)[4], ACC (&acc)[4][TB<NW>()]) {
+                                             v8i (&fb)[4], ACC (&acc)[4][TB<NW>()], int tid) {
   constexpr int TBW = TB<NW>(), NWW = NW;
   constexpr int L = 2 * LP<NW>();
-  const int wave = threadIdx.x >> 6;
+  const int wave = tid >> 6;
   const int wj = wave / (NWW / 2), wi = wave % (NWW / 2);
   const uint8_t *cur = lds + (j % SW) * STAGEW;
   const bool ld_prev = j + SW - 1 < nk;
@@ -280,7 +280,7 @@ __device__ __forceinline__ void stage_iter_w(int j, int nk, const uint8_t *gB, c
   const uint32_t slot_prev = ring + ((j + SW - 1) % SW) * STAGEW;
 #pragma unroll
   for (int tj = 0; tj < 3; ++tj) {
-    fb[tj + 1] = lds_frag(cur, wj * 128 + (tj + 1) * 32);
+    fb[tj + 1] = lds_frag(cur, wj * 128 + (tj + 1) * 32, tid);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int ti = 0; ti < TBW; ++ti) {
@@ -309,9 +309,9 @@ __device__ __forceinline__ void stage_iter_w(int j, int nk, const uint8_t *gB, c
       // the next stage's fragments: the A side after MFMA 0, then B block 0
       if (ti == 0) {
 #pragma unroll
-        for (int t = 0; t < TBW; ++t) fan[t] = lds_frag(nxt + BSZ, wi * 32 * TBW + t * 32);
+        for (int t = 0; t < TBW; ++t) fan[t] = lds_frag(nxt + BSZ, wi * 32 * TBW + t * 32, tid);
       }
-      if (ti == TBW - 1) fb[0] = lds_frag(nxt, wj * 128);
+      if (ti == TBW - 1) fb[0] = lds_frag(nxt, wj * 128, tid);
     }
     __builtin_amdgcn_sched_barrier(0);
   }
@@ -322,12 +322,12 @@ __device__ __forceinline__ void stage_iter_w(int j, int nk, const uint8_t *gB, c
 template <int NW, class ACC>
 __device__ __forceinline__ void kloop_w(const uint8_t *gB, const uint8_t *gA, int64_t rowsB,
                                         int64_t rowsA, int64_t kbeg, int nk, uint8_t *lds,
-                                        ACC (&acc)[4][TB<NW>()]) {
+                                        ACC (&acc)[4][TB<NW>()], int tid) {
   constexpr int TBW = TB<NW>(), NWW = NW;
   constexpr int L = 2 * LP<NW>();
-  const int wave = threadIdx.x >> 6;
+  const int wave = tid >> 6;
   const int wj = wave / (NWW / 2), wi = wave % (NWW / 2);
-  const DmaOffsets d = dma_offsets_w<NW>(rowsB, rowsA);
+  const DmaOffsets d = dma_offsets_w<NW>(rowsB, rowsA, tid);
   const uint32_t ring = lds_offset(lds);
 #pragma unroll
   for (int t = 0; t < SW - 1; ++t)
@@ -345,12 +345,12 @@ __device__ __forceinline__ void kloop_w(const uint8_t *gB, const uint8_t *gA, in
   __builtin_amdgcn_s_barrier();
   v8i fa0[TBW], fa1[TBW], fb[4];
 #pragma unroll
-  for (int ti = 0; ti < TBW; ++ti) fa0[ti] = lds_frag(lds + BSZ, wi * 32 * TBW + ti * 32);
-  fb[0] = lds_frag(lds, wj * 128);
+  for (int ti = 0; ti < TBW; ++ti) fa0[ti] = lds_frag(lds + BSZ, wi * 32 * TBW + ti * 32, tid);
+  fb[0] = lds_frag(lds, wj * 128, tid);
   // nk is a multiple of 4 (k is padded to 256): two stages per trip, no tail
   for (int j = 0; j < nk; j += 2) {
-    stage_iter_w<NW>(j, nk, gB, gA, d, kbeg, lds, ring, fa0, fa1, fb, acc);
-    stage_iter_w<NW>(j + 1, nk, gB, gA, d, kbeg, lds, ring, fa1, fa0, fb, acc);
+    stage_iter_w<NW>(j, nk, gB, gA, d, kbeg, lds, ring, fa0, fa1, fb, acc, tid);
+    stage_iter_w<NW>(j + 1, nk, gB, gA, d, kbeg, lds, ring, fa1, fa0, fb, acc, tid);
   }
   __builtin_amdgcn_s_barrier();
 }
@@ -406,12 +406,13 @@ __device__ __forceinline__ void fold_w(v16f (&acc)[4][TBW], int mul, int p, floa
 //   pass 3: acc += Z;        result smod(c acc)
 // Every fold leaves |acc| <= p/2 <= 256, so the FP32 accumulation of each
 // pass stays an exact integer below 2^24.
+template <int NW>
 __device__ __forceinline__ void karatsuba_tile_w(const uint8_t *Asl, const uint8_t *Bsl,
                                                  int16_t *__restrict__ planes,
                                                  const Tables *__restrict__ tab, int64_t mp,
                                                  int64_t np, int64_t kp, int64_t kbeg, int nk,
                                                  int accumulate, int l, int64_t i0, int64_t j0,
-                                                 uint8_t *lds) {
+                                                 uint8_t *lds, int tid) {
   const int sl0 = (int)uni(tab->slice0[l]);
   const int p = (int)uni(tab->p[l]);
   const float inv = __int_as_float((int)uni(__float_as_int(tab->inv_p[l])));
@@ -427,7 +428,7 @@ __device__ __forceinline__ void karatsuba_tile_w(const uint8_t *Asl, const uint8
   const uint8_t *A0 = Asl + (int64_t)sl0 * sA + i0 * 64;
   const uint8_t *B0 = Bsl + (int64_t)sl0 * sB + j0 * 64;
 
-  constexpr int NWW = NW_RES, TBW = TB<NW_RES>();
+  constexpr int NWW = NW, TBW = TB<NW>();
   v16f acc[4][TBW];
 #pragma unroll
   for (int tj = 0; tj < 4; ++tj)
@@ -438,13 +439,13 @@ __device__ __forceinline__ void karatsuba_tile_w(const uint8_t *Asl, const uint8
 
   pin_agpr(acc);
   const int third = 3 - second;
-  kloop_w<NWW>(B0, A0, np, mp, kbeg, nk, lds, acc);                         // X = C1
+  kloop_w<NWW>(B0, A0, np, mp, kbeg, nk, lds, acc, tid);                         // X = C1
   fold_w(acc, mul_a, p, inv);
-  kloop_w<NWW>(B0 + second * sB, A0 + second * sA, np, mp, kbeg, nk, lds, acc);  // + Y
+  kloop_w<NWW>(B0 + second * sB, A0 + second * sA, np, mp, kbeg, nk, lds, acc, tid);  // + Y
   fold_w(acc, mul_b, p, inv);
-  kloop_w<NWW>(B0 + third * sB, A0 + third * sA, np, mp, kbeg, nk, lds, acc);    // + Z
+  kloop_w<NWW>(B0 + third * sB, A0 + third * sA, np, mp, kbeg, nk, lds, acc, tid);    // + Z
 
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = tid & 63, wave = tid >> 6;
   const int wj = wave / (NWW / 2), wi = wave % (NWW / 2);
   int16_t *out = planes + (int64_t)l * np * mp;
 #pragma unroll
@@ -460,6 +461,30 @@ __device__ __forceinline__ void karatsuba_tile_w(const uint8_t *Asl, const uint8
         if (accumulate) r = smod_i32(r + (int)*dst, p, inv);
         *dst = (int16_t)r;
       }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// acc = m (acc mods q) mods r, one 16-value MFMA tile at a time, in FP32,
+// with the reductions of fold_w (x - rint(x q^-1) q, exact); 1/r = 0 skips
+// the second reduction.
+template <int TBW>
+__device__ __forceinline__ void fold_g(v16f (&acc)[4][TBW], float q, float inv_q, float m,
+                                       float r, float inv_r) {
+  pin_agpr(acc);
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+    for (int ti = 0; ti < TBW; ++ti) {
+      v16f t16;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const float x = acc[tj][ti][v];
+        const float y = fmaf(-rintf(x * inv_q), q, x) * m;
+        t16[v] = fmaf(-rintf(y * inv_r), r, y);
+      }
+      acc[tj][ti] = t16;
+      asm volatile("" : "+a"(acc[tj][ti]));
       __builtin_amdgcn_sched_barrier(0);
     }
 }
@@ -499,12 +524,13 @@ __device__ __forceinline__ void fold_s(v16f (&acc)[4][TBW], int s, float inv_s) 
 // and |A2| <= s / 2, i.e. <= 16: over a k chunk of at most 2^15 the first two
 // passes sum to at most 2 (16^2) 2^15 = 2^24 in magnitude, the third adds at
 // most 2^23 to |acc| < 2^10, and every partial sum is an exact FP32 integer.
+template <int NW>
 __device__ __forceinline__ void square_tile_w(const uint8_t *Asl, const uint8_t *Bsl,
                                               int16_t *__restrict__ planes,
                                               const Tables *__restrict__ tab, int64_t mp,
                                               int64_t np, int64_t kp, int64_t kbeg, int nk,
                                               int accumulate, int l, int64_t i0, int64_t j0,
-                                              uint8_t *lds) {
+                                              uint8_t *lds, int tid) {
   const int sl0 = (int)uni(tab->slice0[l]);
   const int p = (int)uni(tab->p[l]);
   const float inv = __int_as_float((int)uni(__float_as_int(tab->inv_p[l])));
@@ -518,7 +544,7 @@ __device__ __forceinline__ void square_tile_w(const uint8_t *Asl, const uint8_t 
   const uint8_t *A0 = Asl + (int64_t)sl0 * sA + i0 * 64;
   const uint8_t *B0 = Bsl + (int64_t)sl0 * sB + j0 * 64;
 
-  constexpr int NWW = NW_RES, TBW = TB<NW_RES>();
+  constexpr int NWW = NW, TBW = TB<NW>();
   v16f acc[4][TBW];
 #pragma unroll
   for (int tj = 0; tj < 4; ++tj)
@@ -528,13 +554,13 @@ __device__ __forceinline__ void square_tile_w(const uint8_t *Asl, const uint8_t 
       for (int v = 0; v < 16; ++v) acc[tj][ti][v] = 0.0f;
 
   pin_agpr(acc);
-  kloop_w<NWW>(B0 + sB, A0, np, mp, kbeg, nk, lds, acc);       // A1 B2
+  kloop_w<NWW>(B0 + sB, A0, np, mp, kbeg, nk, lds, acc, tid);       // A1 B2
   pin_agpr(acc);
-  kloop_w<NWW>(B0, A0 + sA, np, mp, kbeg, nk, lds, acc);       // + A2 B1
+  kloop_w<NWW>(B0, A0 + sA, np, mp, kbeg, nk, lds, acc, tid);       // + A2 B1
   fold_s(acc, s, inv_s);
-  kloop_w<NWW>(B0 + sB, A0 + sA, np, mp, kbeg, nk, lds, acc);  // + A2 B2
+  kloop_w<NWW>(B0 + sB, A0 + sA, np, mp, kbeg, nk, lds, acc, tid);  // + A2 B2
 
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = tid & 63, wave = tid >> 6;
   const int wj = wave / (NWW / 2), wi = wave % (NWW / 2);
   int16_t *out = planes + (int64_t)l * np * mp;
 #pragma unroll
@@ -558,12 +584,13 @@ __device__ __forceinline__ void square_tile_w(const uint8_t *Asl, const uint8_t 
 // [kbeg, kbeg + 64 nk): the one product of the INT8 residues, accumulated in
 // INT32 (|u| <= 128, so a chunk of k <= 2^15 sums to at most 2^29), then
 // reduced modulo p.
+template <int NW>
 __device__ __forceinline__ void int8_tile_w(const uint8_t *Asl, const uint8_t *Bsl,
                                             int16_t *__restrict__ planes,
                                             const Tables *__restrict__ tab, int64_t mp,
                                             int64_t np, int64_t kp, int64_t kbeg, int nk,
                                             int accumulate, int l, int64_t i0, int64_t j0,
-                                            uint8_t *lds) {
+                                            uint8_t *lds, int tid) {
   const int sl0 = (int)uni(tab->slice0[l]);
   const int p = (int)uni(tab->p[l]);
   const float inv = __int_as_float((int)uni(__float_as_int(tab->inv_p[l])));
@@ -573,7 +600,7 @@ __device__ __forceinline__ void int8_tile_w(const uint8_t *Asl, const uint8_t *B
   const uint8_t *A0 = Asl + (int64_t)sl0 * mp * kp + i0 * 64;
   const uint8_t *B0 = Bsl + (int64_t)sl0 * np * kp + j0 * 64;
 
-  constexpr int NWW = NW_RES, TBW = TB<NW_RES>();
+  constexpr int NWW = NW, TBW = TB<NW>();
   v16i acc[4][TBW];
 #pragma unroll
   for (int tj = 0; tj < 4; ++tj)
@@ -582,10 +609,10 @@ __device__ __forceinline__ void int8_tile_w(const uint8_t *Asl, const uint8_t *B
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[tj][ti][v] = 0;
   pin_agpr(acc);
-  kloop_w<NWW>(B0, A0, np, mp, kbeg, nk, lds, acc);
+  kloop_w<NWW>(B0, A0, np, mp, kbeg, nk, lds, acc, tid);
   pin_agpr(acc);
 
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = tid & 63, wave = tid >> 6;
   const int wj = wave / (NWW / 2), wi = wave % (NWW / 2);
   int16_t *out = planes + (int64_t)l * np * mp;
 #pragma unroll
@@ -605,39 +632,161 @@ __device__ __forceinline__ void int8_tile_w(const uint8_t *Asl, const uint8_t *B
     }
 }
 
-// Residue products of k chunk `chunk`: KIND 0 over the square moduli (256 x
-// 128 tiles, tile index z = l), 1 over the Karatsuba moduli (256 x 256
-// tiles, l = nsq + z), 2 over the INT8 moduli (256 x 256 tiles,
-// l = nsq + nka + z).
-// A grouped launch may run fewer workgroups than tiles; each then loops.
-template <int KIND, bool GROUPED>
-__global__ __launch_bounds__(64 * NW_RES, 1) void k_residue_gemm(Problem P1,
-                                                                               Group G,
-                                                                               int chunk) {
+// Residue products of k chunk `chunk` of one problem, 256 x 256 tiles: KIND 0
+// over the square moduli (tile index z = l), 1 over the Karatsuba moduli
+// (l = nsq + z), 2 over the INT8 moduli (l = nsq + nka + z).
+template <int KIND>
+__global__ __launch_bounds__(64 * NW_RES, 1) void k_residue_gemm(Problem P, int chunk) {
   __shared__ __attribute__((aligned(1024))) uint8_t lds[LDS_RING];
-  const int64_t total = GROUPED ? G.total : (int64_t)gridDim.x;
-  for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
-    int64_t local;
-    const Problem &P = *locate<GROUPED>(P1, G, b, local);
-    const Geometry &g = P.g;
-    const Dims d =
-        family_dims(KIND == 0 ? kFamGemmSq : (KIND == 1 ? kFamGemmKa : kFamGemmI8), P, chunk);
-    const Dims c = decode_block(d, local);
-    const int64_t mp = uni(g.mp), np = uni(g.np), kp = uni(g.kp);
-    const int64_t kbeg = (int64_t)chunk * kChunkK;
-    const int64_t len = kp - kbeg < kChunkK ? kp - kbeg : kChunkK;
-    const int l = (int)uni((KIND == 0 ? 0 : (KIND == 1 ? g.nsq : g.nsq + g.nka)) + c.z);
-    if (KIND == 0)
-      square_tile_w(uni(P.w.Asl), uni(P.w.Bsl), uni(P.w.planes), uni(P.tab), mp, np, kp,
-                    kbeg, (int)(len / BK), chunk > 0 ? 1 : 0, l, uni(c.x * TIW), uni(c.y * TJ),
-                    lds);
-    else if (KIND == 1)
-      karatsuba_tile_w(uni(P.w.Asl), uni(P.w.Bsl), uni(P.w.planes), uni(P.tab), mp, np, kp,
-                       kbeg, (int)(len / BK), chunk > 0 ? 1 : 0, l, uni(c.x * TIW),
-                       uni(c.y * TJ), lds);
-    else
-      int8_tile_w(uni(P.w.Asl), uni(P.w.Bsl), uni(P.w.planes), uni(P.tab), mp, np, kp, kbeg,
-                  (int)(len / BK), chunk > 0 ? 1 : 0, l, uni(c.x * TIW), uni(c.y * TJ), lds);
+  const Geometry &g = P.g;
+  const Dims d =
+      family_dims(KIND == 0 ? kFamGemmSq : (KIND == 1 ? kFamGemmKa : kFamGemmI8), P, chunk);
+  const Dims c = decode_block(d, blockIdx.x);
+  const int64_t mp = uni(g.mp), np = uni(g.np), kp = uni(g.kp);
+  const int64_t kbeg = (int64_t)chunk * kChunkK;
+  const int64_t len = kp - kbeg < kChunkK ? kp - kbeg : kChunkK;
+  const int l = (int)uni((KIND == 0 ? 0 : (KIND == 1 ? g.nsq : g.nsq + g.nka)) + c.z);
+  const int tid = threadIdx.x;
+  if (KIND == 0)
+    square_tile_w<NW_RES>(uni(P.w.Asl), uni(P.w.Bsl), uni(P.w.planes), uni(P.tab), mp, np, kp,
+                          kbeg, (int)(len / BK), chunk > 0 ? 1 : 0, l, uni(c.x * TIW),
+                          uni(c.y * TJ), lds, tid);
+  else if (KIND == 1)
+    karatsuba_tile_w<NW_RES>(uni(P.w.Asl), uni(P.w.Bsl), uni(P.w.planes), uni(P.tab), mp, np,
+                             kp, kbeg, (int)(len / BK), chunk > 0 ? 1 : 0, l, uni(c.x * TIW),
+                             uni(c.y * TJ), lds, tid);
+  else
+    int8_tile_w<NW_RES>(uni(P.w.Asl), uni(P.w.Bsl), uni(P.w.planes), uni(P.tab), mp, np, kp,
+                        kbeg, (int)(len / BK), chunk > 0 ? 1 : 0, l, uni(c.x * TIW),
+                        uni(c.y * TJ), lds, tid);
+}
+
+// One 256 x 256 tile of any FP8 modulus (square or Karatsuba) as three
+// single-product passes with two folds, every step from the tables:
+//   pass 1: acc = D(a1, b1);   fold: acc = m1 (acc mods q1), then mods r1
+//   pass 2: acc += D(a2, b2);  fold: acc = m2 (acc mods q2), then mods r2
+//   pass 3: acc += D(a3, b3);  result smod(m3 acc, p)
+// where D(a, b) is the product of A's digit slice a and B's slice b.
+//   square p = s^2 (as square_tile_w): passes (1, 2), (2, 1), (2, 2); the
+//     first fold reduces modulo p (X mod s is all that matters), the second
+//     is s (acc mods s) with no further reduction; m3 = 1;
+//   Karatsuba (as karatsuba_tile_w): passes X, Y, Z, folds a, b modulo p
+//     (each followed by a reduction modulo p), m3 = c.
+// A fold "then mods r" with no reduction uses 1/r = 0.  Every fold leaves
+// |acc| <= 2^10, so each pass's FP32 accumulation stays exact.
+template <int NW>
+__device__ __forceinline__ void fp8_tile_w(const uint8_t *Asl, const uint8_t *Bsl,
+                                           int16_t *__restrict__ planes,
+                                           const Tables *__restrict__ tab, int64_t mp,
+                                           int64_t np, int64_t kp, int64_t kbeg, int nk,
+                                           int accumulate, int l, int64_t i0, int64_t j0,
+                                           uint8_t *lds, int tid) {
+  const int sl0 = (int)uni(tab->slice0[l]);
+  const int p = (int)uni(tab->p[l]);
+  const float inv = __int_as_float((int)uni(__float_as_int(tab->inv_p[l])));
+  const bool square = uni(tab->kind[l]) == 0;
+  const int s = (int)uni(tab->s[l]);
+  const float inv_s = __int_as_float((int)uni(__float_as_int(tab->inv_s[l])));
+  const int second = square ? 0 : (int)uni(tab->kfold[l][3]);
+  // passes: (A slice, B slice)
+  const int a1 = 0, b1 = square ? 1 : 0;
+  const int a2 = square ? 1 : second, b2 = square ? 0 : second;
+  const int a3 = square ? 1 : 3 - second, b3 = square ? 1 : 3 - second;
+  // folds
+  const float q2 = square ? (float)s : (float)p, iq2 = square ? inv_s : inv;
+  const float m1 = square ? 1.0f : (float)uni(tab->kfold[l][0]);
+  const float m2 = square ? (float)s : (float)uni(tab->kfold[l][1]);
+  const float ir2 = square ? 0.0f : inv;
+  const int m3 = square ? 1 : (int)uni(tab->kfold[l][2]);
+  resident(sl0, p, __float_as_int(inv), s);
+  resident(__float_as_int(inv_s), second, m3, m3);
+  resident_ptr(planes, planes);
+  resident(accumulate, accumulate, accumulate, accumulate);
+  const int64_t sA = mp * kp, sB = np * kp;
+  const uint8_t *A0 = Asl + (int64_t)sl0 * sA + i0 * 64;
+  const uint8_t *B0 = Bsl + (int64_t)sl0 * sB + j0 * 64;
+
+  constexpr int NWW = NW, TBW = TB<NW>();
+  v16f acc[4][TBW];
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+    for (int ti = 0; ti < TBW; ++ti)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[tj][ti][v] = 0.0f;
+
+  pin_agpr(acc);
+  kloop_w<NWW>(B0 + b1 * sB, A0 + a1 * sA, np, mp, kbeg, nk, lds, acc, tid);
+  fold_g(acc, (float)p, inv, m1, (float)p, inv);
+  kloop_w<NWW>(B0 + b2 * sB, A0 + a2 * sA, np, mp, kbeg, nk, lds, acc, tid);
+  fold_g(acc, q2, iq2, m2, (float)p, ir2);
+  kloop_w<NWW>(B0 + b3 * sB, A0 + a3 * sA, np, mp, kbeg, nk, lds, acc, tid);
+
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wj = wave / (NWW / 2), wi = wave % (NWW / 2);
+  int16_t *out = planes + (int64_t)l * np * mp;
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+    for (int ti = 0; ti < TBW; ++ti) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        int r = smod_i32(m3 * (int)acc[tj][ti][v], p, inv);
+        const int64_t i = i0 + wi * 32 * TBW + ti * 32 + (lane & 31);
+        const int64_t j = j0 + wj * 128 + tj * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+        int16_t *dst = out + j * mp + i;
+        if (accumulate) r = smod_i32(r + (int)*dst, p, inv);
+        *dst = (int16_t)r;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// The residue products of a whole batch in one launch: each workgroup takes
+// the next item of the work list (tile x modulus x k part of one problem,
+// longest first) until the list is exhausted; the k chunks of an item run in
+// order inside the workgroup, accumulating into its plane copy.  INT8 = the
+// INT8 arm's products, else the FP8 moduli of either kind.  The last
+// workgroup to finish clears the counters for the next launch, so the launch
+// needs no memset and replays from a graph.
+template <int NW, bool INT8>
+__global__ __launch_bounds__(64 * NW, 1) void k_residue_persistent(WorkList W) {
+  __shared__ __attribute__((aligned(1024))) uint8_t lds[LDS_RING];
+  __shared__ uint32_t item_s;
+  for (;;) {
+    if (threadIdx.x == 0) item_s = atomicAdd(&W.counters[0], 1u);
+    __syncthreads();
+    const int64_t it = (int64_t)__builtin_amdgcn_readfirstlane(item_s);
+    __syncthreads();
+    if (it >= W.count) break;
+    const ProductItem *I = uni(W.items) + it;
+    const Problem &P = uni(W.probs)[(int)uni((int64_t)I->prob)];
+    const int64_t mp = uni(P.g.mp), np = uni(P.g.np), kp = uni(P.g.kp);
+    const int l = (int)uni((int64_t)I->l);
+    const int64_t k0 = uni((int64_t)I->k0), k1 = uni((int64_t)I->k1);
+    const int64_t i0 = uni((int64_t)I->tx * TIW), j0 = uni((int64_t)I->ty * TJ);
+    int16_t *planes = uni(P.w.planes) + uni((int64_t)I->part * P.g.N) * mp * np;
+    for (int64_t kb = k0; kb < k1; kb += kChunkK) {
+      const int64_t len = k1 - kb < kChunkK ? k1 - kb : kChunkK;
+      // the thread index, opaque to the compiler once per chunk: the
+      // epilogue's addresses derived from it are then formed after the
+      // k-loop instead of being hoisted above it and kept live (spilled)
+      int tid = threadIdx.x;
+      asm volatile("" : "+v"(tid));
+      if (INT8)
+        int8_tile_w<NW>(uni(P.w.Asl), uni(P.w.Bsl), planes, uni(P.tab), mp, np, kp, kb,
+                        (int)(len / BK), kb > k0 ? 1 : 0, l, i0, j0, lds, tid);
+      else
+        fp8_tile_w<NW>(uni(P.w.Asl), uni(P.w.Bsl), planes, uni(P.tab), mp, np, kp, kb,
+                       (int)(len / BK), kb > k0 ? 1 : 0, l, i0, j0, lds, tid);
+    }
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(&W.counters[1], 1u) == gridDim.x - 1) {
+      atomicExch(&W.counters[0], 0u);
+      atomicExch(&W.counters[1], 0u);
+    }
   }
 }
 
@@ -647,7 +796,7 @@ __global__ __launch_bounds__(64 * NW_RES, 1) void k_residue_gemm(Problem P1,
 __device__ __forceinline__ void bound_tile(const uint8_t *Abar, const uint8_t *Bbar, int64_t mp,
                                            int64_t np, int nk, uint32_t *__restrict__ rmaxA,
                                            uint32_t *__restrict__ rmaxB, int64_t i0, int64_t j0,
-                                           uint8_t *lds) {
+                                           uint8_t *lds, int tid) {
   constexpr int NWW = NW_BOUND, TBW = TB<NW_BOUND>();
   v16f acc[4][TBW];
 #pragma unroll
@@ -658,10 +807,10 @@ __device__ __forceinline__ void bound_tile(const uint8_t *Abar, const uint8_t *B
       for (int v = 0; v < 16; ++v) acc[tj][ti][v] = 0.0f;
   resident_ptr(rmaxA, rmaxB);
   pin_agpr(acc);
-  kloop_w<NWW>(Bbar + j0 * 64, Abar + i0 * 64, np, mp, 0, nk, lds, acc);
+  kloop_w<NWW>(Bbar + j0 * 64, Abar + i0 * 64, np, mp, 0, nk, lds, acc, tid);
   pin_agpr(acc);
 
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = tid & 63, wave = tid >> 6;
   const int wj = wave / (NWW / 2), wi = wave % (NWW / 2);
   // maxima over j of each column i (row maxima of Abar Bbar, for mu)
 #pragma unroll
@@ -705,15 +854,37 @@ __global__ __launch_bounds__(64 * NW_BOUND, 1) void k_bound_gemm(Problem P1, Gro
     const int64_t mp = uni(g.mp), np = uni(g.np), kp = uni(g.kp);
     uint32_t *rmax = uni(P.w.rmax);
     bound_tile(uni(P.w.Abar), uni(P.w.Bbar), mp, np, (int)(kp / BK), rmax, rmax + mp,
-               uni(c.x * TIW), uni(c.y * TJ), lds);
+               uni(c.x * TIW), uni(c.y * TJ), lds, threadIdx.x);
   }
 }
 
 }  // namespace
 
-hipError_t launch_gemm_family(int fam, const Problem *P, const Group *G, int chunk, int64_t grid,
+hipError_t launch_gemm_persistent(int nw, bool int8, const WorkList &W, int64_t grid,
+                                  hipStream_t st) {
+  if (W.count <= 0) return hipSuccess;
+  if (grid > W.count) grid = W.count;
+  if (grid <= 0 || grid > 0x7FFFFFFFll || W.count > 0xFFFFFFFFll) return hipErrorInvalidValue;
+  const dim3 gr((unsigned)grid);
+  if (nw == 8 && !int8)
+    hipLaunchKernelGGL((k_residue_persistent<8, false>), gr, dim3(64 * 8), 0, st, W);
+  else if (nw == 4 && !int8)
+    hipLaunchKernelGGL((k_residue_persistent<4, false>), gr, dim3(64 * 4), 0, st, W);
+  else if (nw == 8)
+    hipLaunchKernelGGL((k_residue_persistent<8, true>), gr, dim3(64 * 8), 0, st, W);
+  else if (nw == 4)
+    hipLaunchKernelGGL((k_residue_persistent<4, true>), gr, dim3(64 * 4), 0, st, W);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_family(int fam, const Problem *P, const Group *G, int chunk,
                               hipStream_t st) {
+  // grouped launches: the bound product only (a batch's residue products run
+  // as one persistent launch)
   const bool grouped = G != nullptr;
+  if (grouped && fam != kFamBgemm) return hipErrorInvalidValue;
   Problem p1;
   Group g1;
   memset(&p1, 0, sizeof(p1));
@@ -722,10 +893,8 @@ hipError_t launch_gemm_family(int fam, const Problem *P, const Group *G, int chu
     g1 = *G;
   else
     p1 = *P;
-  const int64_t tiles = grouped ? G->total : family_blocks(fam, *P, chunk);
-  if (tiles <= 0) return hipSuccess;
-  int64_t blocks = tiles;
-  if (grouped && grid > 0 && grid < tiles) blocks = grid;
+  const int64_t blocks = grouped ? G->total : family_blocks(fam, *P, chunk);
+  if (blocks <= 0) return hipSuccess;
   if (blocks > 0x7FFFFFFFll) return hipErrorInvalidValue;
   const dim3 gr((unsigned)blocks),
       blk(fam == kFamBgemm ? 64 * NW_BOUND : 64 * NW_RES);
@@ -737,22 +906,13 @@ hipError_t launch_gemm_family(int fam, const Problem *P, const Group *G, int chu
         hipLaunchKernelGGL((k_bound_gemm<false>), gr, blk, 0, st, p1, g1);
       break;
     case kFamGemmSq:
-      if (grouped)
-        hipLaunchKernelGGL((k_residue_gemm<0, true>), gr, blk, 0, st, p1, g1, chunk);
-      else
-        hipLaunchKernelGGL((k_residue_gemm<0, false>), gr, blk, 0, st, p1, g1, chunk);
+      hipLaunchKernelGGL((k_residue_gemm<0>), gr, blk, 0, st, p1, chunk);
       break;
     case kFamGemmKa:
-      if (grouped)
-        hipLaunchKernelGGL((k_residue_gemm<1, true>), gr, blk, 0, st, p1, g1, chunk);
-      else
-        hipLaunchKernelGGL((k_residue_gemm<1, false>), gr, blk, 0, st, p1, g1, chunk);
+      hipLaunchKernelGGL((k_residue_gemm<1>), gr, blk, 0, st, p1, chunk);
       break;
     case kFamGemmI8:
-      if (grouped)
-        hipLaunchKernelGGL((k_residue_gemm<2, true>), gr, blk, 0, st, p1, g1, chunk);
-      else
-        hipLaunchKernelGGL((k_residue_gemm<2, false>), gr, blk, 0, st, p1, g1, chunk);
+      hipLaunchKernelGGL((k_residue_gemm<2>), gr, blk, 0, st, p1, chunk);
       break;
     default:
       return hipErrorInvalidValue;

@@ -105,6 +105,30 @@ struct Problem {
   int64_t ldc;
   int32_t limbs;       // 32-bit limbs of P (host tables), selects the CRT kernel
   int32_t mode;        // OZ2_MODE_ACCURATE or OZ2_MODE_FAST (selects the launch sequence)
+  int32_t parts;       // k parts of the residue products (split-K): the CRT sums this
+                       // many copies of the residue planes, each N mp np entries apart
+  int32_t reserved;
+};
+
+// One work item of the persistent residue-product launch: tile (tx, ty) of
+// modulus l of problem `prob`, over k in [k0, k1) (multiples of 256, walked in
+// chunks of at most kChunkK), written to copy `part` of the problem's residue
+// planes.
+struct ProductItem {
+  int32_t prob;
+  int16_t l, part;
+  int32_t tx, ty;
+  int32_t k0, k1;
+};
+
+// Work list of a persistent residue-product launch.  counters[0] hands out
+// items, counters[1] counts finished workgroups; both are zero between
+// launches (the last workgroup to finish clears them).
+struct WorkList {
+  const Problem *probs;
+  const ProductItem *items;
+  int64_t count;
+  uint32_t *counters;
 };
 
 // Layout of the FP8 bound operands and of every digit slice ("k-blocked"):
@@ -284,12 +308,18 @@ __device__ __forceinline__ Dims decode_block(const Dims &d, int64_t local) {
 // ---- launchers (all asynchronous on `st`) ----
 // Exactly one of P (a single problem, passed to the kernel by value) and G
 // (a grouped launch over device-resident problems) is non-null.  `chunk` is
-// the k chunk of the residue products; `grid` caps the number of workgroups
-// of a grouped product launch (0: one per tile), which then loop over tiles.
+// the k chunk of the residue products, which launch_gemm_family runs for a
+// single problem only (a batch's run as launch_gemm_persistent).
 hipError_t launch_quant_family(int fam, const Problem *P, const Group *G, hipStream_t st);
 hipError_t launch_scale_family(int fam, const Problem *P, const Group *G, hipStream_t st);
-hipError_t launch_gemm_family(int fam, const Problem *P, const Group *G, int chunk, int64_t grid,
+hipError_t launch_gemm_family(int fam, const Problem *P, const Group *G, int chunk,
                               hipStream_t st);
+// The persistent residue-product launch: `grid` workgroups of nw (8 or 4)
+// waves take items of W in order until none is left; int8 selects the INT8
+// arm's products (every item's modulus is then an INT8 one), else every
+// item's modulus is a square or Karatsuba FP8 modulus.
+hipError_t launch_gemm_persistent(int nw, bool int8, const WorkList &W, int64_t grid,
+                                  hipStream_t st);
 hipError_t launch_crt_family(const Problem *P, const Group *G, int limbs, int N, hipStream_t st);
 hipError_t launch_scal(int64_t m, int64_t n, double beta, double *C, int64_t ldc,
                        hipStream_t st);

@@ -2,6 +2,12 @@
 
   python -m paper_2603_10634_amd.profile_summary trace  DIR PREFIX OUT.md  [CMD]
       kernel-trace statistics (PREFIX_kernel_stats.csv) as a markdown table.
+  python -m paper_2603_10634_amd.profile_summary counters CSV OUT.md [CMD]
+      hardware counters of one rocprofv3 --pmc run (PREFIX_counter_collection.csv),
+      mean per dispatch of each kernel, with the derived figures: kernel time
+      (from the dispatch timestamps), the clock GRBM_GUI_ACTIVE counted per
+      XCD over that time, and MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES over the
+      SIMD cycles of the same span (MI355X: 8 XCDs, 256 CUs x 4 SIMDs).
   python -m paper_2603_10634_amd.profile_summary traffic DIR FETCH WRITE OUT.md OUT.json [CMD...]
       HBM bytes per dispatch from a FETCH_SIZE and a WRITE_SIZE counter run
       (FETCH_counter_collection.csv, WRITE_counter_collection.csv), each
@@ -59,6 +65,41 @@ def _per_kernel(path: str, counter: str):
     return {k: sum(v) / len(v) for k, v in vals.items()}
 
 
+XCDS = 8
+SIMDS = 256 * 4
+
+
+def counters(csv_path: str, out: str, cmd: str = "") -> None:
+    vals = defaultdict(lambda: defaultdict(list))
+    dur = defaultdict(dict)
+    for r in csv.DictReader(open(csv_path)):
+        name = short(r["Kernel_Name"])
+        vals[name][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        dur[name][r["Dispatch_Id"]] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+    names = sorted(vals, key=lambda n: -sum(dur[n].values()))
+    ctrs = sorted({c for n in vals for c in vals[n]})
+    with open(out, "w") as f:
+        f.write(f"# Hardware counters per dispatch: {os.path.basename(out)}\n\n")
+        if cmd:
+            f.write(f"Command:\n\n    {cmd}\n\n")
+        f.write("Means over the dispatches of each kernel.  clock = GRBM_GUI_ACTIVE / "
+                f"{XCDS} XCDs / kernel time; MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / "
+                f"(GRBM_GUI_ACTIVE / {XCDS} x {SIMDS} SIMDs).\n\n")
+        f.write("| kernel | dispatches | ms | clock GHz | MFMA busy | "
+                + " | ".join(ctrs) + " |\n")
+        f.write("|---|---|---|---|---|" + "---|" * len(ctrs) + "\n")
+        for n in names:
+            d = vals[n]
+            t = sum(dur[n].values()) / len(dur[n])
+            mean = {c: sum(v) / len(v) for c, v in d.items()}
+            grbm = mean.get("GRBM_GUI_ACTIVE")
+            clock = f"{grbm / XCDS / t / 1e9:.2f}" if grbm and t > 0 else ""
+            mfma = mean.get("SQ_VALU_MFMA_BUSY_CYCLES")
+            busy = f"{100 * mfma / (grbm / XCDS * SIMDS):.1f} %" if grbm and mfma else ""
+            f.write(f"| `{n}` | {len(dur[n])} | {t * 1e3:.3f} | {clock} | {busy} | "
+                    + " | ".join(f"{mean[c]:.4g}" if c in mean else "" for c in ctrs) + " |\n")
+
+
 def traffic(d: str, fetch: str, write: str, out_md: str, out_json: str, cmd: str = "") -> None:
     fk = _per_kernel(os.path.join(d, f"{fetch}_counter_collection.csv"), "FETCH_SIZE")
     wk = _per_kernel(os.path.join(d, f"{write}_counter_collection.csv"), "WRITE_SIZE")
@@ -99,6 +140,8 @@ if __name__ == "__main__":
     a = sys.argv[1:]
     if a and a[0] == "trace":
         trace(a[1], a[2], a[3], " ".join(a[4:]))
+    elif a and a[0] == "counters":
+        counters(a[1], a[2], " ".join(a[3:]))
     elif a and a[0] == "traffic":
         traffic(a[1], a[2], a[3], a[4], a[5], " ".join(a[6:]))
     else:

@@ -9,6 +9,7 @@ import torch
 import paper_2603_10634_amd as oz
 from oracle import ozaki2_ref as ref
 from workloads import to_colmajor, from_colmajor
+from workloads.reference import dd_dot_rows, normalised_error
 
 
 def device():
@@ -164,3 +165,44 @@ def check_stages(r: Run, opA, opB, N, st=None, mode="accurate", moduli="hybrid")
     P = r.planes(N)
     for l, plane in enumerate(st["planes"]):
         assert np.array_equal(P[l, :n, :m].T.astype(np.int64), plane), f"plane {l}"
+
+
+def same_bits(a, b):
+    """Bitwise equality, NaN matching NaN."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    both_nan = np.isnan(a) & np.isnan(b)
+    return bool(np.all(both_nan | (a.view(np.int64) == b.view(np.int64))))
+
+
+def sample_lines(n, count, seed, extra=()):
+    """The edge lines 0, 1, n/2, n-2, n-1, `count` seeded others and `extra`."""
+    rng = np.random.default_rng(seed)
+    fixed = [0, 1, n // 2, n - 2, n - 1]
+    return np.unique(np.concatenate([fixed, rng.integers(0, n, count), list(extra)]).astype(np.int64))
+
+
+def check_sampled(A, B, N, rows, cols, transA="N", transB="N", mode="accurate",
+                  moduli="hybrid", bounds=None, err_max=1e-15, label=""):
+    """One library call on op(A) x op(B) stored as transA / transB; shifts of
+    the sampled lines, sampled outputs bit for bit, normalised error."""
+    print(f"{label}: GPU N={N} {moduli} {mode} {transA}{transB}", flush=True)
+    r = run(A, B, N, transA, transB, keep_ws="lines", mode=mode, moduli=moduli)
+    assert r.status == 0
+    if bounds is None:
+        print(f"{label}: oracle bounds", flush=True)
+        bounds = ref.line_bounds(A, B, rows, cols, mode)
+    sc = ref.scaling_from_bounds(bounds, N, moduli)
+    sA, sB = r.lines(0)
+    assert np.array_equal(sA[rows], sc["sA"]), "shifts of the sampled rows"
+    assert np.array_equal(sB[cols], sc["sB"]), "shifts of the sampled columns"
+    print(f"{label}: oracle products", flush=True)
+    want, _ = ref.products(sc, slice(None), slice(None))
+    got = r.C[np.ix_(rows, cols)]
+    assert same_bits(got, want), f"{int(np.sum(got.view(np.int64) != want.view(np.int64)))} outputs differ"
+    hi, lo = dd_dot_rows(A[rows], B[:, cols])
+    err = normalised_error(got, hi, lo, np.abs(A[rows]), np.abs(B[:, cols]))
+    print(f"{label}: N={N} normalised error {err:.3e}, exact fix-ups {r.fixups()}",
+          flush=True)
+    assert err <= err_max, err
+    return bounds

@@ -22,15 +22,27 @@ CSRC = os.path.join(ROOT, "paper_2603_10634_amd", "csrc")
 LISTS = {"hybrid": 0, "karatsuba": 1, "int8": 2}
 
 
-@pytest.fixture(scope="module")
-def checker(tmp_path_factory):
-    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
-    if not os.path.exists(hipcc):
-        pytest.skip("hipcc not available")
-    out = str(tmp_path_factory.mktemp("crt") / "crt_host_check")
-    cmd = [hipcc, "-O2", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
-           "-I" + CSRC, "-x", "c++", os.path.join(ROOT, "tests", "crt_host_check.cpp"),
-           os.path.join(CSRC, "oz2_tables.cpp"), "-o", out]
+# Host builds of the checker: hipcc (the compiler of the library), and g++
+# with AddressSanitizer and UndefinedBehaviorSanitizer (any finding aborts).
+SANITIZE = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+            "-fno-omit-frame-pointer"]
+
+
+@pytest.fixture(scope="module", params=["hipcc", "sanitized"])
+def checker(request, tmp_path_factory):
+    out = str(tmp_path_factory.mktemp("crt") / f"crt_host_check_{request.param}")
+    srcs = [os.path.join(ROOT, "tests", "crt_host_check.cpp"), os.path.join(CSRC, "oz2_tables.cpp")]
+    flags = ["-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I" + CSRC]
+    if request.param == "hipcc":
+        hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+        if not os.path.exists(hipcc):
+            pytest.skip("hipcc not available")
+        cmd = [hipcc, "-O2", *flags, "-x", "c++", *srcs, "-o", out]
+    else:
+        gxx = shutil.which("g++")
+        if not gxx:
+            pytest.skip("g++ not available")
+        cmd = [gxx, "-O1", "-g", *SANITIZE, *flags, *srcs, "-o", out]
     subprocess.run(cmd, check=True, capture_output=True)
     return out
 

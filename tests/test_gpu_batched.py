@@ -1,9 +1,12 @@
-"""Batched calls (grouped launches over uneven problems), graph capture and
-the autotuner, through the C ABI.
+"""Batched calls (grouped launches over uneven problems, the residue products
+of the whole batch in one persistent launch), graph capture, the residue
+product configurations (tile program, split-K) and the autotuner, through the
+C ABI.
 
 A batched call must give, for every problem, exactly the C that a separate
 ozaki2_dgemm call gives (which the parity tests pin to the oracle), and the
-small problems are also compared with the oracle directly."""
+problems are also compared with the oracle directly (small ones in full,
+large ones on sampled outputs)."""
 import numpy as np
 import pytest
 import torch
@@ -86,11 +89,24 @@ class Batch:
         return [c.cpu().numpy() for c in Cs]
 
 
+def _pad(x):
+    return (x + 255) // 256 * 256
+
+
+def _split_copies(m, n, k, N):
+    """Bytes of the three extra residue-plane copies a batched problem holds
+    when split-K may apply to it (at most 4 tiles, padded k >= 512)."""
+    if _pad(m) * _pad(n) <= 4 * 256 * 256 and _pad(k) >= 512:
+        return 3 * 2 * N * _pad(m) * _pad(n)
+    return 0
+
+
 def _setup():
     oz.ozaki2_set_stream(torch.cuda.current_stream(dev()))
     oz.ozaki2_set_workspace(None, 0)
     oz.ozaki2_set_graph(False)
     oz.ozaki2_set_autotune(False)
+    oz.ozaki2_set_schedule(-1)
 
 
 def _uneven(count, lo, hi, seed):
@@ -140,7 +156,8 @@ def test_batched_sub_batches_with_small_workspace():
     shapes, trans, alpha, beta = _uneven(9, 20, 700, config_seed(4, 3))
     b = Batch(shapes, config_seed(4, 4), trans, alpha, beta)
     N = 12
-    need = [oz.ozaki2_workspace_bytes(m, n, k, N) for m, n, k in shapes]
+    need = [oz.ozaki2_workspace_bytes(m, n, k, N) + _split_copies(m, n, k, N)
+            for m, n, k in shapes]
     total = oz.ozaki2_workspace_bytes_batched([s[0] for s in shapes], [s[1] for s in shapes],
                                               [s[2] for s in shapes], N)
     assert total == sum(need)
@@ -247,17 +264,104 @@ def test_autotuner_picks_a_schedule_and_keeps_results():
         assert oz.ozaki2_get_schedule() == s1
     finally:
         oz.ozaki2_set_autotune(False)
-    print(f"autotuned schedule {s1}", flush=True)
-    assert 0 <= s1 < 4
+    print(f"autotuned configuration {s1}", flush=True)
+    assert 0 <= s1 < 6
     h0, h1, h2 = b.host(C0), b.host(C1), b.host(C2)
     for q in range(len(shapes)):
         assert _same(h0[q], h1[q]) and _same(h0[q], h2[q]), q
 
 
+@pytest.mark.parametrize("N,moduli", [(12, "hybrid"), (14, "int8")])
+def test_every_configuration_same_bits(N, moduli):
+    """Both tile programs and every split-K limit give the C of per-problem
+    calls, on problems that split (few tiles, long k, one of them beyond a k
+    chunk of 2^15) and problems that do not; forced configurations replay
+    from graphs too."""
+    _setup()
+    shapes = [(64, 64, 4096), (300, 200, 2000), (256, 512, 1024), (1000, 900, 800),
+              (70, 90, 40000), (33, 17, 300), (512, 512, 256)]
+    trans = [("N", "N"), ("T", "N"), ("N", "T"), ("T", "T"), ("N", "N"), ("T", "T"), ("N", "N")]
+    b = Batch(shapes, config_seed(4, 9), trans, beta=[0.0, 1.0, -0.5, 0.0, 2.0, 0.0, 0.25])
+    assert oz.ozaki2_set_moduli_list(moduli) == 0
+    try:
+        Cs = b.fresh_C()
+        b.singles(N, Cs)
+        hs = b.host(Cs)
+        for c in range(6):
+            print(f"configuration {c} ({moduli})", flush=True)
+            assert oz.ozaki2_set_schedule(c) == 0
+            for graph in (False, True):
+                oz.ozaki2_set_graph(graph)
+                Cb = b.fresh_C()
+                assert b.batched(N, Cb) == 0
+                assert oz.ozaki2_get_schedule() == c
+                hb = b.host(Cb)
+                for q in range(len(shapes)):
+                    assert _same(hb[q], hs[q]), (c, graph, q, shapes[q])
+            oz.ozaki2_set_graph(False)
+        # the smallest members against the oracle directly
+        for q in (5, 0):
+            m, n, k = shapes[q]
+            Chat = ref.emulate(b.opA[q], b.opB[q], N, moduli_set=moduli)
+            want = ref.combine_alpha_beta(Chat, 1.0, b.beta[q], b.Cin[q])
+            assert _same(from_colmajor(hs[q], m, n, b.ldc[q]), want), q
+    finally:
+        oz.ozaki2_set_schedule(-1)
+        oz.ozaki2_set_graph(False)
+        oz.ozaki2_set_moduli_list("hybrid")
+
+
+def test_autotune_cache_file(tmp_path):
+    """The autotuner's choice is written to the file named by
+    OZ2_AUTOTUNE_CACHE in the documented form (read back here as JSON); a
+    later process with tuning off takes that choice for the same shape
+    bucket, and one whose file is corrupt falls back to the default."""
+    import json
+    import os
+    import subprocess
+    import sys
+    path = tmp_path / "tune.json"
+    code = (
+        "import sys, torch, paper_2603_10634_amd as oz\n"
+        "sys.path.insert(0, 'tests')\n"
+        "from test_gpu_batched import Batch, _uneven\n"
+        "from workloads import config_seed\n"
+        "oz.ozaki2_set_stream(torch.cuda.current_stream())\n"
+        "shapes, trans, alpha, beta = _uneven(6, 64, 900, config_seed(4, 11))\n"
+        "b = Batch(shapes, config_seed(4, 12), trans, alpha, beta)\n"
+        "oz.ozaki2_set_autotune(sys.argv[1] == 'tune')\n"
+        "assert b.batched(12, b.fresh_C()) == 0\n"
+        "torch.cuda.synchronize()\n"
+        "print('CONFIG', oz.ozaki2_get_schedule())\n")
+    env = dict(os.environ, OZ2_AUTOTUNE_CACHE=str(path))
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+    def child(arg):
+        print(f"cache file: child process ({arg})", flush=True)
+        r = subprocess.run([sys.executable, "-c", code, arg], cwd=root, env=env,
+                           capture_output=True, text=True, timeout=300)
+        assert r.returncode == 0, r.stderr[-2000:]
+        return int(r.stdout.split("CONFIG")[1].split()[0])
+
+    chosen = child("tune")
+    doc = json.loads(path.read_text())
+    assert doc["oz2_autotune"] == 1 and len(doc["entries"]) == 1
+    entry = doc["entries"][0]
+    assert entry["config"] == chosen and entry["key"].startswith("n12m0l0:")
+    # another configuration recorded for the bucket: a fresh process uses it
+    other = (chosen + 1) % 6
+    path.write_text(path.read_text().replace(f'"config": {chosen}', f'"config": {other}'))
+    assert child("run") == other
+    # a malformed file is ignored: the default configuration
+    path.write_text('{"oz2_autotune": 1, "entries": [\n{"key": "x", "config": 99}\n]}\n')
+    assert child("run") == 0
+
+
 def test_batched_many_uneven_problems_sampled():
     """512 problems with m, n, k log-uniform in [64, 4096] (inputs drawn on the
-    GPU from a seeded generator): the batched call equals per-problem calls on
-    a sample of 48 problems, every schedule gives the same bits."""
+    GPU from a seeded generator): on a sample of 48 problems the batched call
+    equals per-problem calls and the oracle on sampled outputs; the autotuned
+    configuration gives the same bits for every problem."""
     _setup()
     shapes = batch_shapes(512, 64, 4096, config_seed(4, 0))
     g = torch.Generator(device=dev())
@@ -288,6 +392,16 @@ def test_batched_many_uneven_problems_sampled():
                                c, m[q], 12) == 0
         torch.cuda.synchronize()
         assert torch.equal(c.view(torch.int64), tC[q].view(torch.int64)), q
+        # the oracle directly, on sampled outputs (their lines' exponents
+        # from the whole problem's bound product)
+        opA = tA[q].cpu().numpy().T           # m x k
+        opB = tB[q].cpu().numpy().T           # k x n
+        rows = np.unique(np.concatenate([[0, m[q] - 1], rng.integers(0, m[q], 4)]))
+        cols = np.unique(np.concatenate([[0, n[q] - 1], rng.integers(0, n[q], 4)]))
+        sc = ref.scaling_lines(opA, opB, 12, rows, cols)
+        want, _ = ref.products(sc, slice(None), slice(None))
+        got = tC[q].cpu().numpy().T[np.ix_(rows, cols)]
+        assert _same(got, want), (q, shapes[q])
     oz.ozaki2_set_autotune(True)
     try:
         tC2 = [torch.empty_like(c) for c in tC]

@@ -12,7 +12,7 @@ from oracle import ozaki2_ref as ref
 from workloads import phi_matrix, normal_matrix, config_seed, batch_shapes, to_colmajor
 from workloads.reference import dd_dot_rows, normalised_error
 
-from gpu_util import run, check_stages
+from gpu_util import run, check_stages, check_sampled, sample_lines
 
 pytestmark = pytest.mark.gpu
 
@@ -189,27 +189,13 @@ def test_fast_graph_replays():
 
 
 def test_fast_full_size_sampled():
-    # m = n = k = 8192, phi = 0.5, N = 13 in fast mode: C on sampled rows (all
-    # columns) and sampled columns (all rows), which involves every line's shift
+    # m = n = k = 8192, phi = 0.5, 13 moduli (fast): shifts of sampled lines,
+    # sampled outputs bit for bit, normalised error against double-double
     n = 8192
     s = config_seed(2, 0)
     print("fast full size: generating", flush=True)
     A = phi_matrix(n, n, 0.5, s)
     B = phi_matrix(n, n, 0.5, s + 1)
-    print("fast full size: GPU", flush=True)
-    r = run(A, B, 13, keep_ws=False, mode="fast")
-    assert r.status == 0
-    rows = np.array([0, 3, 4095, 8191])
-    print("fast full size: oracle scaling", flush=True)
-    sc = ref.scaling(A, B, 13, mode="fast")
-    print("fast full size: oracle rows", flush=True)
-    Cs, _ = ref.products(sc, rows, np.arange(n))
-    assert _same(r.C[rows], Cs)
-    cols = np.array([2, 6000])
-    print("fast full size: oracle columns", flush=True)
-    Cs2, _ = ref.products(sc, np.arange(n), cols)
-    assert _same(r.C[:, cols], Cs2)
-    hi, lo = dd_dot_rows(A[rows[:2]], B[:, :1024])
-    err = normalised_error(r.C[rows[:2], :1024], hi, lo, np.abs(A[rows[:2]]), np.abs(B[:, :1024]))
-    print(f"fast full size: normalised error {err:.3e}", flush=True)
-    assert err <= 1e-15
+    rows = sample_lines(n, 20, 11)
+    cols = sample_lines(n, 20, 12)
+    check_sampled(A, B, 13, rows, cols, mode="fast", label="fast full size")

@@ -334,20 +334,24 @@ def test_workspace_too_small():
 
 def test_full_size_sampled():
     # the benchmark workload: m = n = k = 8192, phi = 0.5, N = 12, in the
-    # benchmark's launch configuration; every line's shift is compared and C on
-    # sampled rows (all columns) and sampled columns (all rows)
+    # benchmark's launch configuration: every line's shift (the full oracle
+    # scaling, from the whole bound product) and C on sampled rows (all
+    # columns) and sampled columns (all rows)
     n = 8192
     s = config_seed(2, 0)
     print("full size: generating", flush=True)
     A = phi_matrix(n, n, 0.5, s)
     B = phi_matrix(n, n, 0.5, s + 1)
     print("full size: GPU", flush=True)
-    r = run(A, B, 12, keep_ws=False)
+    r = run(A, B, 12, keep_ws="lines")
     assert r.status == 0
     rows = np.array([0, 1, 777, 4095, 8191])
     cols = np.arange(n)
     print("full size: oracle scaling", flush=True)
     sc = ref.scaling(A, B, 12)
+    sA, sB = r.lines(0)
+    assert np.array_equal(sA, sc["sA"]) and np.array_equal(sB, sc["sB"]), "shifts"
+    print(f"full size: every shift equal; exact fix-ups {r.fixups()}", flush=True)
     print("full size: oracle rows", flush=True)
     Cs, _ = ref.products(sc, rows, cols)
     assert _same(r.C[rows], Cs)
@@ -360,3 +364,30 @@ def test_full_size_sampled():
     err = normalised_error(r.C[rows[:2], :1024], hi, lo, np.abs(A[rows[:2]]), np.abs(B[:, :1024]))
     print(f"full size: normalised error {err:.3e}", flush=True)
     assert err <= 1e-15
+
+
+def test_allocation_failure_is_reported():
+    # OZ2_FAULT=alloc (read by the library once per process, so a child
+    # process): every allocation the library would make fails; the calls
+    # return OZ2_ERR_ALLOC and leave C untouched
+    import os
+    import subprocess
+    import sys
+    code = (
+        "import torch, paper_2603_10634_amd as oz\n"
+        "oz.ozaki2_set_stream(torch.cuda.current_stream())\n"
+        "A = torch.ones((64, 64), dtype=torch.float64, device='cuda')\n"
+        "C = torch.full((64, 64), 7.0, dtype=torch.float64, device='cuda')\n"
+        "s1 = oz.ozaki2_dgemm('N', 'N', 64, 64, 64, 1.0, A, 64, A, 64, 0.0, C, 64, 12)\n"
+        "s2 = oz.ozaki2_dgemm_batched(['N'], ['N'], [64], [64], [64], [1.0], [A], [64], [A],\n"
+        "                             [64], [0.0], [C], [64], 12)\n"
+        "torch.cuda.synchronize()\n"
+        "print('STATUS', s1, s2, bool((C == 7.0).all()))\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, OZ2_FAULT="alloc")
+    print("allocation failure: child process", flush=True)
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.split("STATUS")[1].split() == ["2", "2", "True"]
+    assert "allocat" in oz.ozaki2_status_string(2)

@@ -135,10 +135,17 @@ def test_batched_argument_errors_and_workspace():
                                   None, None, None, None, 12) == -2
     # empty outputs only: nothing to do, success without a device
     assert call(**one(m=[0], lda=[1], ldc=[1])) == 0
-    # workspace of a batch = sum over problems with a nonempty product
-    ms, ns, ks = [300, 0, 64, 1000], [200, 5, 64, 17], [700, 9, 0, 4096]
-    want = sum(oz.ozaki2_workspace_bytes(a, b, c, 12) for a, b, c in zip(ms, ns, ks)
-               if a and b and c)
+    # workspace of a batch = sum over problems with a nonempty product; a
+    # problem of at most 4 output tiles of 256 x 256 and at least 512 padded k
+    # holds 3 more copies of its residue planes (split-K parts)
+    ms, ns, ks = [300, 0, 64, 1000, 2000], [200, 5, 64, 17, 1500], [700, 9, 0, 4096, 300]
+    pad = lambda x: (x + 255) // 256 * 256
+    want = 0
+    for a, b, c in zip(ms, ns, ks):
+        if a and b and c:
+            want += oz.ozaki2_workspace_bytes(a, b, c, 12)
+            if pad(a) * pad(b) <= 4 * 256 * 256 and pad(c) >= 512:
+                want += 3 * 2 * 12 * pad(a) * pad(b)
     assert oz.ozaki2_workspace_bytes_batched(ms, ns, ks, 12) == want
     assert oz.ozaki2_workspace_bytes_batched([1], [-1], [1], 12) == 0
 
@@ -152,6 +159,10 @@ def test_batched_no_device_on_cpu():
     assert oz.ozaki2_set_graph(True) == 0 and oz.ozaki2_set_graph(False) == 0
     assert oz.ozaki2_set_autotune(True) == 0 and oz.ozaki2_set_autotune(False) == 0
     assert oz.ozaki2_get_schedule() == -1
+    for c in (-1, 0, 5):
+        assert oz.ozaki2_set_schedule(c) == 0
+    assert oz.ozaki2_set_schedule(6) == -1 and oz.ozaki2_set_schedule(-2) == -1
+    assert oz.ozaki2_set_schedule(-1) == 0
 
 
 def test_mode_setting_host_only():

@@ -28,15 +28,28 @@ KS = [64, 256, 1024, 4096, 16384, 65536, 1 << 18]
 E4M3 = ref.E4M3_NONNEG[1:]          # positive finite E4M3 values
 
 
-@pytest.fixture(scope="module")
-def window():
-    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
-    if not os.path.exists(hipcc):
-        pytest.skip("hipcc not available")
-    out = str(os.path.join(os.environ.get("TMPDIR", "/tmp"), f"oz2_window_check_{os.getpid()}"))
-    cmd = [hipcc, "-O2", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
-           "-I" + CSRC, "-x", "c++", os.path.join(ROOT, "tests", "window_host_check.cpp"),
-           os.path.join(CSRC, "oz2_tables.cpp"), "-o", out]
+# Host builds of the window: hipcc (the compiler of the library), and g++ with
+# AddressSanitizer and UndefinedBehaviorSanitizer (any finding aborts).
+SANITIZE = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+            "-fno-omit-frame-pointer"]
+
+
+@pytest.fixture(scope="module", params=["hipcc", "sanitized"])
+def window(request, tmp_path_factory):
+    out = str(tmp_path_factory.mktemp("window") / f"window_host_check_{request.param}")
+    srcs = [os.path.join(ROOT, "tests", "window_host_check.cpp"),
+            os.path.join(CSRC, "oz2_tables.cpp")]
+    flags = ["-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I" + CSRC]
+    if request.param == "hipcc":
+        hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+        if not os.path.exists(hipcc):
+            pytest.skip("hipcc not available")
+        cmd = [hipcc, "-O2", *flags, "-x", "c++", *srcs, "-o", out]
+    else:
+        gxx = shutil.which("g++")
+        if not gxx:
+            pytest.skip("g++ not available")
+        cmd = [gxx, "-O1", "-g", *SANITIZE, *flags, *srcs, "-o", out]
     subprocess.run(cmd, check=True, capture_output=True)
 
     def call(N, pairs):
@@ -46,8 +59,7 @@ def window():
         rows = [ln.split() for ln in r.stdout.splitlines()]
         return [(float.fromhex(a), float.fromhex(b), int(c), int(d)) for a, b, c, d in rows]
 
-    yield call
-    os.remove(out)
+    return call
 
 
 def _round_f32(v, direction):

@@ -51,6 +51,8 @@ extern "C" {
 #define OZ2_ERR_WORKSPACE    3  /* the caller's workspace is smaller than required */
 #define OZ2_ERR_UNSUPPORTED  4  /* valid arguments outside what is built (see below) */
 #define OZ2_ERR_NO_DEVICE    5  /* no gfx950 device is current */
+#define OZ2_ERR_SCRATCH      6  /* the problem exceeds the scratch buffer of
+                                   ozaki2_dgemm_noalloc */
 
 /* Largest number of moduli (the hybrid list keeps its six squares first for
  * N < 34, Section IV-B) and largest k handled in one call. */
@@ -367,6 +369,31 @@ int ozaki2_set_blocking(int64_t m_blk, int64_t n_blk);
 /* ozaki2_get_blocking - the calling thread's blocking (either pointer may be
  * NULL). */
 int ozaki2_get_blocking(int64_t *m_blk, int64_t *n_blk);
+
+/*
+ * ozaki2_dgemm_noalloc - ozaki2_dgemm for callers that cannot allocate device
+ * memory (code that must not call hipMalloc: tight serving loops, harnesses
+ * that forbid allocation).  Same arguments, results (bit-identical C),
+ * argument errors and quick returns as ozaki2_dgemm, in the calling thread's
+ * mode, modulus list, m/n blocking and stream; it ignores the thread's
+ * workspace, graph and timing settings.
+ *
+ * Its workspace is a fixed device buffer of OZ2_NOALLOC_SCRATCH_BYTES per
+ * GPU, held by the library until the process ends.  A problem whose
+ * workspace (ozaki2_workspace_bytes with the same blocking) exceeds it
+ * returns OZ2_ERR_SCRATCH and launches nothing; m/n blocking
+ * (ozaki2_set_blocking) lowers the need.  No call allocates: the first call
+ * on a device only looks up the buffer's device address and copies the
+ * moduli tables into a second fixed buffer (synchronously, so that first call
+ * must not be made during stream capture).  Every call on a GPU uses the same
+ * buffer, so calls that overlap on one GPU (other streams, other host
+ * threads) race and must be ordered by the caller.
+ */
+#define OZ2_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int ozaki2_dgemm_noalloc(char transA, char transB, int64_t m, int64_t n, int64_t k,
+                         double alpha, const double *A, int64_t lda,
+                         const double *B, int64_t ldb, double beta,
+                         double *C, int64_t ldc, int num_moduli);
 
 /* ozaki2_release - free the calling thread's library-owned workspace, timing
  * events, cached batch plans and graphs. */

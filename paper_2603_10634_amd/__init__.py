@@ -21,7 +21,8 @@ __all__ = [
     "ozaki2_get_mode", "MODE_ACCURATE", "MODE_FAST", "ozaki2_set_moduli_list",
     "ozaki2_get_moduli_list", "MODULI_HYBRID", "MODULI_KARATSUBA", "MODULI_INT8",
     "ozaki2_set_blocking", "ozaki2_get_blocking", "dgemm", "dgemm_batched",
-    "LIB_PATH", "HEADER_PATH", "header_functions",
+    "LIB_PATH", "HEADER_PATH", "header_functions", "ozaki2_dgemm_noalloc",
+    "NOALLOC_SCRATCH_BYTES",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -93,6 +94,9 @@ def lib() -> ctypes.CDLL:
         "ozaki2_set_blocking": (ctypes.c_int, [_i64, _i64]),
         "ozaki2_get_blocking": (ctypes.c_int, [_p64, _p64]),
         "ozaki2_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "ozaki2_dgemm_noalloc": (ctypes.c_int, [ctypes.c_char, ctypes.c_char, _i64, _i64, _i64,
+                                                ctypes.c_double, _vp, _i64, _vp, _i64,
+                                                ctypes.c_double, _vp, _i64, ctypes.c_int]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -132,6 +136,18 @@ def ozaki2_dgemm(transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
     A, B, C are device pointers (int) or tensors; returns the status code."""
     return lib().ozaki2_dgemm(_ch(transA), _ch(transB), m, n, k, float(alpha), _ptr(A), lda,
                               _ptr(B), ldb, float(beta), _ptr(C), ldc, int(num_moduli))
+
+
+def ozaki2_dgemm_noalloc(transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                         num_moduli) -> int:
+    """ozaki2_dgemm on the library's fixed scratch buffer, for callers that
+    cannot allocate (see include/ozaki2.h); returns the status code."""
+    return lib().ozaki2_dgemm_noalloc(_ch(transA), _ch(transB), m, n, k, float(alpha), _ptr(A),
+                                      lda, _ptr(B), ldb, float(beta), _ptr(C), ldc,
+                                      int(num_moduli))
+
+
+NOALLOC_SCRATCH_BYTES = 256 << 20   # OZ2_NOALLOC_SCRATCH_BYTES
 
 
 def ozaki2_workspace_bytes(m, n, k, num_moduli) -> int:

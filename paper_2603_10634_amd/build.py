@@ -26,7 +26,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 
-SOURCES = ["oz2_tables.cpp", "oz2_api.cpp", "oz2_quant.hip",
+SOURCES = ["oz2_tables.cpp", "oz2_api.cpp", "oz2_noalloc.cpp", "oz2_quant.hip",
            "oz2_scale.hip", "oz2_gemm.hip", "oz2_crt.hip"]
 
 

@@ -797,6 +797,47 @@ int check_args(char transA, char transB, int64_t m, int64_t n, int64_t k, int64_
 
 }  // namespace
 
+namespace oz2 {
+
+int dgemm_fixed(char transA, char transB, int64_t m, int64_t n, int64_t k, double alpha,
+                const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
+                double *C, int64_t ldc, int num_moduli, FixedResources (*resources)(int dev)) {
+  const int bad = check_args(transA, transB, m, n, k, lda, ldb, ldc, num_moduli);
+  if (bad) return bad;
+  ThreadState &ts = g_ts;
+  hipStream_t st = ts.stream;
+  ts.have_times = false;
+  if (m == 0 || n == 0) return OZ2_SUCCESS;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return OZ2_ERR_NO_DEVICE;
+  if (!device_ok(dev)) return OZ2_ERR_NO_DEVICE;
+  if (k == 0 || alpha == 0.0)
+    return launch_scal(m, n, beta, C, ldc, st) == hipSuccess ? OZ2_SUCCESS : OZ2_ERR_HIP;
+  if (k > OZ2_MAX_K) return OZ2_ERR_UNSUPPORTED;
+  Layout L;
+  if (!make_layout(m, n, k, num_moduli, &L, ts.blk_m, ts.blk_n)) return OZ2_ERR_UNSUPPORTED;
+  const Tables *ht = host_tables(num_moduli, ts.list);
+  if (!ht) return OZ2_ERR_UNSUPPORTED;
+  const FixedResources res = resources(dev);
+  if (!res.ws || !res.tables) return OZ2_ERR_HIP;
+  if (L.total > res.ws_bytes) return OZ2_ERR_SCRATCH;
+  const Tables *dt = res.tables + (size_t)ts.list * kMaxN + (num_moduli - 1);
+  const Problem P = make_problem(transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                                 num_moduli, res.ws, L, dt, ht);
+  if (L.mbp < L.mp || L.nbp < L.np) return enqueue_blocked(P, L.mbp, L.nbp, st);
+  Marks none{&ts, st, false};
+  return enqueue_single(P, st, none);
+}
+
+bool host_tables_for(int N, int list, Tables *out) {
+  const Tables *t = host_tables(N, list);
+  if (!t) return false;
+  *out = *t;
+  return true;
+}
+
+}  // namespace oz2
+
 extern "C" {
 
 const char *ozaki2_status_string(int status) {
@@ -807,6 +848,7 @@ const char *ozaki2_status_string(int status) {
     case OZ2_ERR_WORKSPACE: return "caller workspace too small";
     case OZ2_ERR_UNSUPPORTED: return "unsupported size or state";
     case OZ2_ERR_NO_DEVICE: return "no gfx950 device is current";
+    case OZ2_ERR_SCRATCH: return "problem needs more than the no-allocation scratch buffer";
     default: return status < 0 ? "invalid argument" : "unknown status";
   }
 }

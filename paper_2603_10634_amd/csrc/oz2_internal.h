@@ -321,6 +321,26 @@ hipError_t launch_gemm_family(int fam, const Problem *P, const Group *G, int chu
 hipError_t launch_gemm_persistent(int nw, bool int8, const WorkList &W, int64_t grid,
                                   hipStream_t st);
 hipError_t launch_crt_family(const Problem *P, const Group *G, int limbs, int N, hipStream_t st);
+// Device memory of the entry point that allocates nothing: a workspace and
+// the device tables of every (modulus list, N), laid out [list][N - 1].
+struct FixedResources {
+  uint8_t *ws;
+  size_t ws_bytes;
+  const Tables *tables;
+};
+
+// ozaki2_dgemm's argument checks, quick returns and launch sequence (with the
+// calling thread's stream, mode, modulus list and m/n blocking) on the
+// workspace and tables that resources(dev) returns for the current device;
+// never allocates, captures a graph or records timing events.  A problem
+// whose workspace exceeds resources' returns OZ2_ERR_SCRATCH.
+int dgemm_fixed(char transA, char transB, int64_t m, int64_t n, int64_t k, double alpha,
+                const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
+                double *C, int64_t ldc, int num_moduli, FixedResources (*resources)(int dev));
+
+// Host copy of the tables of N moduli of list `list` (false: unsupported).
+bool host_tables_for(int N, int list, Tables *out);
+
 hipError_t launch_scal(int64_t m, int64_t n, double beta, double *C, int64_t ldc,
                        hipStream_t st);
 

@@ -61,9 +61,10 @@ def test_workspace_layout(shape, N):
     assert max(e for _, e in spans) <= total
 
 
-def test_argument_errors(L):
+@pytest.mark.parametrize("entry", ["ozaki2_dgemm", "ozaki2_dgemm_noalloc"])
+def test_argument_errors(L, entry):
     d = 0  # no pointer is dereferenced on these paths
-    call = oz.ozaki2_dgemm
+    call = getattr(oz, entry)
     assert call("X", "N", 4, 4, 4, 1.0, d, 4, d, 4, 0.0, d, 4, 12) == -1
     assert call("N", "Q", 4, 4, 4, 1.0, d, 4, d, 4, 0.0, d, 4, 12) == -2
     assert call("N", "N", -1, 4, 4, 1.0, d, 4, d, 4, 0.0, d, 4, 12) == -3
@@ -86,6 +87,8 @@ def test_no_device_reported_on_cpu(L):
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     assert oz.ozaki2_dgemm("N", "N", 4, 4, 4, 1.0, 0, 4, 0, 4, 0.0, 0, 4, 12) == 5
+    assert oz.ozaki2_dgemm_noalloc("N", "N", 4, 4, 4, 1.0, 0, 4, 0, 4, 0.0, 0, 4, 12) == 5
+    assert "scratch" in oz.ozaki2_status_string(6)
     assert "gfx950" in oz.ozaki2_status_string(5)
 
 

@@ -443,7 +443,8 @@ def scaling(opA: np.ndarray, opB: np.ndarray, num_moduli: int, mode: str = "accu
                 sA=7 - EA + e, sB=7 - EB + f)
 
 
-def line_bounds(opA: np.ndarray, opB: np.ndarray, rows, cols, mode: str = "accurate") -> dict:
+def line_bounds(opA: np.ndarray, opB: np.ndarray, rows, cols, mode: str = "accurate",
+                log=None) -> dict:
     """Workflow steps 1-2 of Section IV-B for the rows `rows` of op(A) and the
     columns `cols` of op(B) only: mu', nu' of those lines and the bound that
     decides their scale exponents (accurate mode: the maximum of the bound
@@ -454,7 +455,9 @@ def line_bounds(opA: np.ndarray, opB: np.ndarray, rows, cols, mode: str = "accur
     maxima r_i, Abar Bbar[:, cols] the column maxima c_j.  The bound operands
     of both sides are built in full, because every partner line enters a
     maximum.  The result does not depend on the number of moduli, so one call
-    serves every N (scaling_from_bounds)."""
+    serves every N (scaling_from_bounds).  `log`, if given, is called with a
+    short message after each step (for progress reports on large inputs)."""
+    say = log or (lambda msg: None)
     if mode not in ("accurate", "fast"):
         raise ValueError("mode must be 'accurate' or 'fast'")
     opA = np.asarray(opA, dtype=np.float64)
@@ -472,12 +475,15 @@ def line_bounds(opA: np.ndarray, opB: np.ndarray, rows, cols, mode: str = "accur
     EA = ufp_exponents(A, axis=1)
     EB = ufp_exponents(B, axis=0)
     Abar, Bbar = bound_operands(A, B, EA, EB)
+    say("bound operands")
     if mode == "fast":
         r18, c18 = cauchy_schwarz_norms(Abar[rows], Bbar[:, cols])
     else:
         n, m = B.shape[1], A.shape[0]
         r18 = exact_bound_product(Abar[rows], Bbar).max(axis=1) if n else np.zeros(len(rows))
+        say("row maxima")
         c18 = exact_bound_product(Abar, Bbar[:, cols]).max(axis=0) if m else np.zeros(len(cols))
+        say("column maxima")
     return dict(A=A[rows], B=B[:, cols], badA=badA, badB=badB, EA=EA[rows], EB=EB[cols],
                 r18=r18, c18=c18, mode=mode)
 

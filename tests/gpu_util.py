@@ -182,27 +182,57 @@ def sample_lines(n, count, seed, extra=()):
     return np.unique(np.concatenate([fixed, rng.integers(0, n, count), list(extra)]).astype(np.int64))
 
 
+def sweep_sample(m, n, cancel=False):
+    """The rows and columns the accuracy sweep (accuracy_sweep) measures its
+    error on: first, middle, last and five seeded rows (all when m <= 128;
+    the cancellation block's rows 1, 100, 255 with it) and the first 1024
+    columns."""
+    if m <= 128:
+        rows = np.arange(m)
+    else:
+        rng = np.random.default_rng(m)
+        rows = np.unique(np.concatenate([[0, m // 2, m - 1], rng.integers(0, m, 5)]))
+        if cancel:
+            rows = np.unique(np.concatenate([rows, [1, 100, 255]]))
+    return rows.astype(np.int64), np.arange(min(n, 1024), dtype=np.int64)
+
+
 def check_sampled(A, B, N, rows, cols, transA="N", transB="N", mode="accurate",
-                  moduli="hybrid", bounds=None, err_max=1e-15, label=""):
-    """One library call on op(A) x op(B) stored as transA / transB; shifts of
-    the sampled lines, sampled outputs bit for bit, normalised error."""
+                  moduli="hybrid", cache=None, err_rows=None, err_cols=None, err_max=1e-15,
+                  label=""):
+    """One library call on op(A) x op(B) stored as transA / transB; the shifts
+    of the sampled lines and the outputs rows x cols bit for bit against the
+    oracle (line-restricted scaling), and the normalised error on
+    err_rows x err_cols (a subset of the sample; default: all of it).
+    `cache` (a dict, returned) keeps the oracle's bounds, results and
+    double-double reference for further calls on the same logical inputs."""
     print(f"{label}: GPU N={N} {moduli} {mode} {transA}{transB}", flush=True)
     r = run(A, B, N, transA, transB, keep_ws="lines", mode=mode, moduli=moduli)
     assert r.status == 0
-    if bounds is None:
+    cache = {} if cache is None else cache
+    if ("bounds", mode) not in cache:
         print(f"{label}: oracle bounds", flush=True)
-        bounds = ref.line_bounds(A, B, rows, cols, mode)
-    sc = ref.scaling_from_bounds(bounds, N, moduli)
+        cache[("bounds", mode)] = ref.line_bounds(
+            A, B, rows, cols, mode, log=lambda msg: print(f"{label}: oracle {msg}", flush=True))
+    key = (N, moduli, mode)
+    if key not in cache:
+        sc = ref.scaling_from_bounds(cache[("bounds", mode)], N, moduli)
+        print(f"{label}: oracle products", flush=True)
+        cache[key] = (sc, ref.products(sc, slice(None), slice(None))[0])
+    sc, want = cache[key]
     sA, sB = r.lines(0)
     assert np.array_equal(sA[rows], sc["sA"]), "shifts of the sampled rows"
     assert np.array_equal(sB[cols], sc["sB"]), "shifts of the sampled columns"
-    print(f"{label}: oracle products", flush=True)
-    want, _ = ref.products(sc, slice(None), slice(None))
     got = r.C[np.ix_(rows, cols)]
     assert same_bits(got, want), f"{int(np.sum(got.view(np.int64) != want.view(np.int64)))} outputs differ"
-    hi, lo = dd_dot_rows(A[rows], B[:, cols])
-    err = normalised_error(got, hi, lo, np.abs(A[rows]), np.abs(B[:, cols]))
+    er = rows if err_rows is None else np.asarray(err_rows)
+    ec = cols if err_cols is None else np.asarray(err_cols)
+    if "dd" not in cache:
+        cache["dd"] = dd_dot_rows(A[er], B[:, ec])
+    hi, lo = cache["dd"]
+    sub = got[np.ix_(np.searchsorted(rows, er), np.searchsorted(cols, ec))]
+    err = normalised_error(sub, hi, lo, np.abs(A[er]), np.abs(B[:, ec]))
     print(f"{label}: N={N} normalised error {err:.3e}, exact fix-ups {r.fixups()}",
           flush=True)
     assert err <= err_max, err
-    return bounds
+    return cache

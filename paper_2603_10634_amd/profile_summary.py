@@ -41,7 +41,8 @@ def gemm_source_sha() -> str:
 
 def short(name: str) -> str:
     name = name.replace("oz2::(anonymous namespace)::", "").replace("void ", "")
-    return name.split("(")[0]
+    name = name.split("(")[0]
+    return name if len(name) <= 64 else name[:60] + " ..."
 
 
 def trace(d: str, prefix: str, out: str, cmd: str = "") -> None:

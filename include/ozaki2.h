@@ -101,9 +101,10 @@ int ozaki2_dgemm(char transA, char transB, int64_t m, int64_t n, int64_t k,
  * ozaki2_workspace_bytes - device workspace one ozaki2_dgemm call of this
  * shape needs (every dimension padded to a multiple of 256, as in the paper's
  * Section IV-C): the FP8 bound operands, the FP8 digit slices of both
- * operands, one int16 residue plane per modulus and per-line vectors, for
- * the calling thread's modulus list (ozaki2_set_moduli_list) and m/n
- * blocking (ozaki2_set_blocking: slices and planes then cover one block).
+ * operands, one int16 residue plane per modulus and k part of the residue
+ * products (see ozaki2_set_split) and per-line vectors, for the calling
+ * thread's modulus list (ozaki2_set_moduli_list), m/n blocking
+ * (ozaki2_set_blocking: slices and planes then cover one block) and split.
  * Returns 0 for invalid sizes, for m, n or k above 2^40 and when the size
  * does not fit in size_t.
  */
@@ -177,7 +178,9 @@ int ozaki2_moduli(int num_moduli, int32_t *p, int32_t *kinds);
  *   off[5] uint8  [M x m_pad x k_pad]  digit slices of A' (slice order below), each
  *          k-blocked like Abar (INT8 residues as two's-complement bytes)
  *   off[6] uint8  [M x n_pad x k_pad]  digit slices of B'
- *   off[7] int16  [N x n_pad x m_pad]  C'_l, entry (i, j) at l*n_pad*m_pad + j*m_pad + i
+ *   off[7] int16  [N x n_pad x m_pad]  C'_l, entry (i, j) at l*n_pad*m_pad + j*m_pad + i;
+ *          with k parts (ozaki2_set_split) one such copy per part, q*N*n_pad*m_pad
+ *          apart, whose sum modulo p_l is C'_l (the last region of the layout)
  *   off[8] uint32 [m_pad + n_pad]  FP32 bits of the bound product's line maxima
  *          (accurate mode)
  *   off[9] uint32 [m_pad + n_pad]  line flags: 1 non-finite, 2 all zero, 4 exponent
@@ -196,6 +199,18 @@ int ozaki2_moduli(int num_moduli, int32_t *p, int32_t *kinds);
  */
 int ozaki2_workspace_layout(int64_t m, int64_t n, int64_t k, int num_moduli,
                             int64_t *off, int64_t *pads);
+
+/*
+ * ozaki2_workspace_parts - how an ozaki2_dgemm call of this shape splits k
+ * under the calling thread's settings (ozaki2_set_split, ozaki2_set_blocking):
+ * *parts = the k parts of the residue products, i.e. the copies of the
+ * residue planes at off[7]; *bound_parts = the k parts of the bound product
+ * (1: one pass; more: their FP32 part sums use the planes region first).
+ * Either pointer may be NULL.  Returns 0, or -1 for invalid sizes (nothing
+ * written).
+ */
+int ozaki2_workspace_parts(int64_t m, int64_t n, int64_t k, int num_moduli, int *parts,
+                           int *bound_parts);
 
 /*
  * ozaki2_dgemm_batched - `count` independent emulated DGEMMs
@@ -223,11 +238,11 @@ int ozaki2_workspace_layout(int64_t m, int64_t n, int64_t k, int num_moduli,
  * distinct argument list (the last 8 are cached per thread, with their
  * captured graphs, see ozaki2_set_graph).
  *
- * Workspace: problem q of a sub-batch uses the layout of
- * ozaki2_workspace_layout, with 4 copies of the residue planes for a problem
- * that split-K may apply to, at the sum of the earlier problems' sizes (each
- * its ozaki2_workspace_bytes plus those extra copies, 2 N mp np bytes
- * each).  A caller workspace (ozaki2_set_workspace)
+ * Workspace: problem q of a sub-batch uses the offsets of
+ * ozaki2_workspace_layout, with one copy of the residue planes (2 N mp np
+ * bytes, the last region), or 4 for a problem that split-K may apply to, at
+ * the sum of the earlier problems' sizes (each its planes offset plus its
+ * copies, rounded up to 256 bytes).  A caller workspace (ozaki2_set_workspace)
  * must hold the largest problem; the library-owned one grows to the whole
  * batch (ozaki2_workspace_bytes_batched), capped at 16 GiB.
  *
@@ -246,10 +261,9 @@ int ozaki2_dgemm_batched(int count, const char *transA, const char *transB,
                          double *const *C, const int64_t *ldc, int num_moduli);
 
 /* ozaki2_workspace_bytes_batched - workspace for running the whole batch as
- * one sub-batch (the sum over problems with m, n, k > 0 of
- * ozaki2_workspace_bytes plus, for problems split-K may apply to, three more
- * copies of the residue planes); 0 for invalid sizes and when a problem's
- * size or the sum does not fit in size_t. */
+ * one sub-batch (the sum over problems with m, n, k > 0 of their sizes as
+ * laid out for ozaki2_dgemm_batched); 0 for invalid sizes and when a
+ * problem's size or the sum does not fit in size_t. */
 size_t ozaki2_workspace_bytes_batched(int count, const int64_t *m, const int64_t *n,
                                       const int64_t *k, int num_moduli);
 
@@ -295,6 +309,23 @@ int ozaki2_get_schedule(void);
  * -1 for a value outside -1..5 (the setting is then unchanged).
  */
 int ozaki2_set_schedule(int config);
+
+/*
+ * ozaki2_set_split - number of k parts of the residue products of the
+ * calling thread's subsequent ozaki2_dgemm (and ozaki2_dgemm_noalloc) calls.
+ * Each modulus kind's products are one launch of (256 x 256 output tiles) x
+ * (moduli of the kind) x (k parts) workgroups, one per CU at a time; part q
+ * covers the q-th of `parts` near-equal ranges of 256-blocks of k and writes
+ * its own copy of the residue planes, which the CRT sums modulo p.  More
+ * parts keep the CUs busy when the output has few tiles.  0 (default): the
+ * library's rule, which minimises the launches' waves of workgroups per unit
+ * of k over 1..8 parts of at least 2048 k each (1 part for large outputs).
+ * 1..8: that many parts (at most one per 256-block of k).  Every setting
+ * gives bit-identical results; the workspace grows by 2 N mp np bytes per
+ * part beyond the first.  Returns 0, or -1 for a value outside 0..8 (the
+ * setting is then unchanged).
+ */
+int ozaki2_set_split(int parts);
 
 /*
  * ozaki2_set_mode - scaling mode of the calling thread's subsequent

@@ -15,10 +15,10 @@ import re
 __all__ = [
     "Ozaki2Error", "lib", "ozaki2_dgemm", "ozaki2_workspace_bytes", "ozaki2_set_stream",
     "ozaki2_set_workspace", "ozaki2_set_timing", "ozaki2_get_stage_times",
-    "ozaki2_get_kernel_times", "ozaki2_moduli", "ozaki2_workspace_layout", "ozaki2_release",
-    "ozaki2_status_string", "ozaki2_dgemm_batched", "ozaki2_workspace_bytes_batched",
-    "ozaki2_set_graph", "ozaki2_set_autotune", "ozaki2_get_schedule", "ozaki2_set_schedule", "ozaki2_set_mode",
-    "ozaki2_get_mode", "MODE_ACCURATE", "MODE_FAST", "ozaki2_set_moduli_list",
+    "ozaki2_get_kernel_times", "ozaki2_moduli", "ozaki2_workspace_layout",
+    "ozaki2_workspace_parts", "ozaki2_release", "ozaki2_status_string", "ozaki2_dgemm_batched", "ozaki2_workspace_bytes_batched",
+    "ozaki2_set_graph", "ozaki2_set_autotune", "ozaki2_get_schedule", "ozaki2_set_schedule",
+    "ozaki2_set_split", "ozaki2_set_mode", "ozaki2_get_mode", "MODE_ACCURATE", "MODE_FAST", "ozaki2_set_moduli_list",
     "ozaki2_get_moduli_list", "MODULI_HYBRID", "MODULI_KARATSUBA", "MODULI_INT8",
     "ozaki2_set_blocking", "ozaki2_get_blocking", "dgemm", "dgemm_batched",
     "LIB_PATH", "HEADER_PATH", "header_functions", "ozaki2_dgemm_noalloc",
@@ -77,6 +77,9 @@ def lib() -> ctypes.CDLL:
                                          ctypes.POINTER(ctypes.c_int32)]),
         "ozaki2_workspace_layout": (ctypes.c_int, [_i64, _i64, _i64, ctypes.c_int,
                                                    ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+        "ozaki2_workspace_parts": (ctypes.c_int, [_i64, _i64, _i64, ctypes.c_int,
+                                                  ctypes.POINTER(ctypes.c_int),
+                                                  ctypes.POINTER(ctypes.c_int)]),
         "ozaki2_release": (ctypes.c_int, []),
         "ozaki2_dgemm_batched": (ctypes.c_int, [ctypes.c_int, ctypes.c_char_p, ctypes.c_char_p,
                                                 _p64, _p64, _p64, _pd, _pvp, _p64, _pvp, _p64,
@@ -87,6 +90,7 @@ def lib() -> ctypes.CDLL:
         "ozaki2_set_autotune": (ctypes.c_int, [ctypes.c_int]),
         "ozaki2_get_schedule": (ctypes.c_int, []),
         "ozaki2_set_schedule": (ctypes.c_int, [ctypes.c_int]),
+        "ozaki2_set_split": (ctypes.c_int, [ctypes.c_int]),
         "ozaki2_set_mode": (ctypes.c_int, [ctypes.c_int]),
         "ozaki2_get_mode": (ctypes.c_int, []),
         "ozaki2_set_moduli_list": (ctypes.c_int, [ctypes.c_int]),
@@ -203,6 +207,17 @@ def ozaki2_workspace_layout(m, n, k, num_moduli) -> tuple[list[int], dict]:
     return list(off)[:r], dict(mp=pads[0], np=pads[1], kp=pads[2], M=pads[3])
 
 
+def ozaki2_workspace_parts(m, n, k, num_moduli) -> tuple[int, int]:
+    """(k parts of the residue products = plane copies, k parts of the bound
+    product) of an ozaki2_dgemm call of this shape under the thread's
+    settings."""
+    parts, bparts = ctypes.c_int(0), ctypes.c_int(0)
+    if lib().ozaki2_workspace_parts(m, n, k, num_moduli, ctypes.byref(parts),
+                                    ctypes.byref(bparts)) < 0:
+        raise ValueError("invalid sizes")
+    return parts.value, bparts.value
+
+
 def ozaki2_release() -> int:
     return lib().ozaki2_release()
 
@@ -254,6 +269,12 @@ def ozaki2_set_schedule(config: int) -> int:
     """Force the batched residue-product configuration (0..5), or -1 for the
     default / autotuned one."""
     return lib().ozaki2_set_schedule(int(config))
+
+
+def ozaki2_set_split(parts: int) -> int:
+    """Force the number of k parts (1..8) of the calling thread's
+    ozaki2_dgemm residue products, or 0 for the library's rule."""
+    return lib().ozaki2_set_split(int(parts))
 
 
 def _mode_code(mode) -> int:

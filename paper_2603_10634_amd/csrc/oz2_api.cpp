@@ -46,6 +46,7 @@ struct ThreadState {
   int mode = OZ2_MODE_ACCURATE;            // scaling mode (Section III-E)
   int list = OZ2_MODULI_HYBRID;            // modulus list (Sections III-B, III-D)
   int64_t blk_m = 0, blk_n = 0;            // m/n blocking of ozaki2_dgemm (0: none)
+  int split = 0;                           // k parts of ozaki2_dgemm's products (0: the rule)
   hipStream_t cap_stream = nullptr;        // private stream used only for capture
   int cap_dev = -1;
   std::list<std::unique_ptr<Plan>> plans;  // cached plans, most recent first
@@ -88,10 +89,72 @@ int parts_alloc(int64_t m, int64_t n, int64_t k) {
   return tiles <= kSplitTiles && round_up(k, kPad) >= 2 * kPad ? kMaxParts : 1;
 }
 
+// Split-K in single calls: each modulus kind's residue products are one
+// launch of T tiles x n moduli workgroups (T tiles of 256 x 256 outputs in a
+// block), one per CU at a time.  When T n is small against the CU count the
+// launch leaves CUs idle for its whole k loop, so k is split into parts that
+// run as workgroups of their own, each into its own copy of the planes (the
+// CRT sums the copies).  Every part is at most kChunkK long (one exact FP32
+// accumulation), so there are at least ceil(kp / kChunkK) parts; above that
+// the number minimises the launches' waves of workgroups per unit of k,
+// sum over kinds of ceil(T n_kind parts / kCUs) / parts (ties to fewer
+// parts), with at least kMinPartK of k in every added part and at most
+// kMaxSplit parts (kMaxSplit kChunkK = OZ2_MAX_K).  A fixed CU count keeps
+// the workspace size a function of the shape alone.
+constexpr int kMaxSplit = 8;
+constexpr int64_t kMinPartK = 2048;
+constexpr int64_t kCUs = 256;
+static_assert((int64_t)kMaxSplit * kChunkK >= OZ2_MAX_K, "parts cannot cover k");
+
+// (k above OZ2_MAX_K is refused before any launch; its workspace size is
+// given for kMaxSplit parts)
+int min_parts(int64_t kp) {
+  return (int)std::min<int64_t>(kMaxSplit, (kp + kChunkK - 1) / kChunkK);
+}
+
+int single_parts(int64_t mbp, int64_t nbp, int64_t kp, const Tables &t) {
+  const int64_t tiles = (mbp / kGemmTIW) * (nbp / kGemmTJ);
+  const int64_t kinds[3] = {t.nsq, t.nka, t.N - t.nsq - t.nka};
+  const int lo = min_parts(kp);
+  int best = lo;
+  double best_cost = 0.0;
+  for (int parts = lo; parts <= kMaxSplit && (parts == lo || kp / parts >= kMinPartK); ++parts) {
+    double cost = 0.0;
+    for (int64_t n : kinds)
+      if (n > 0) cost += (double)((tiles * n * parts + kCUs - 1) / kCUs) / parts;
+    if (parts == lo || cost < best_cost) {
+      best = parts;
+      best_cost = cost;
+    }
+  }
+  return best;
+}
+
+// Split-K of a single call's bound product (accurate mode): its launch has
+// one workgroup per 256 x 256 tile, so an output of few tiles leaves most CUs
+// idle through the whole k loop.  With fewer than kCUs / 2 tiles and at
+// least 2 kBoundPartK of k, k is cut into up to kMaxBoundSplit parts of at
+// least kBoundPartK, enough to give about one workgroup per CU; each part's
+// FP32 sums go to a buffer, and one more launch adds them in part order and
+// takes the line maxima.  The decision window counts the parts - 1 extra
+// additions.  The buffer (4 mp np bytes per part) lies over the residue
+// planes, which are written only later in the call.
+constexpr int kMaxBoundSplit = 16;
+constexpr int64_t kBoundPartK = 4096;
+
+int bound_parts(int64_t mp, int64_t np, int64_t kp) {
+  const int64_t tiles = (mp / kGemmTIW) * (np / kGemmTJ);
+  if (tiles >= kCUs / 2 || kp < 2 * kBoundPartK) return 1;
+  const int64_t want = (kCUs + tiles - 1) / tiles;
+  return (int)std::min<int64_t>({want, kp / kBoundPartK, kMaxBoundSplit});
+}
+
 struct Layout {
   int64_t mp, np, kp;
   int64_t mbp, nbp;  // padded block extents (mp, np when the call is not blocked)
   int M;
+  int parts;         // copies of the residue planes (k parts of the products)
+  int bparts;        // k parts of the bound product
   size_t off[17];
   size_t total;
 };
@@ -111,9 +174,10 @@ const Tables *host_tables(int N, int list) {
 // extent).  The per-line vectors and the bound operands cover the whole
 // problem; digit slices and residue planes cover one block.  The
 // zero-initialised per-line vectors come first and contiguously so one fill
-// clears them.
+// clears them.  The planes region holds `parts` copies (a batched call's
+// split-K allocation; 0 takes the single-call rule, single_parts).
 bool make_layout(int64_t m, int64_t n, int64_t k, int N, Layout *L, int64_t mb = 0,
-                 int64_t nb = 0, int parts = 1) {
+                 int64_t nb = 0, int parts = 0) {
   const Tables *ht = host_tables(N, g_ts.list);
   if (!ht) return false;
   const Tables &t = *ht;
@@ -128,6 +192,14 @@ bool make_layout(int64_t m, int64_t n, int64_t k, int N, Layout *L, int64_t mb =
   L->mbp = mb > 0 && mb < L->mp ? mb : L->mp;
   L->nbp = nb > 0 && nb < L->np ? nb : L->np;
   L->M = t.M;
+  L->bparts = 1;
+  if (parts <= 0) {
+    parts = g_ts.split > 0
+                ? std::max(min_parts(L->kp), (int)std::min<int64_t>(g_ts.split, L->kp / kPad))
+                : single_parts(L->mbp, L->nbp, L->kp, t);
+    L->bparts = bound_parts(L->mp, L->np, L->kp);
+  }
+  L->parts = parts;
   const int64_t lines = L->mp + L->np;
   size_t o = 0;
   bool ok = true;
@@ -155,7 +227,9 @@ bool make_layout(int64_t m, int64_t n, int64_t k, int N, Layout *L, int64_t mb =
   take(4, size3(L->np, L->kp, 1));             // Bbar
   take(5, size3(t.M, L->mbp, L->kp));          // A slices (one block)
   take(6, size3(t.M, L->nbp, L->kp));          // B slices
-  take(7, size3(sizeof(int16_t) * N * parts, L->mbp, L->nbp));  // planes (per k part)
+  // planes (per k part), or the split bound product's part sums
+  take(7, std::max(size3(sizeof(int16_t) * N * L->parts, L->mbp, L->nbp),
+                   L->bparts > 1 ? size3(sizeof(float) * L->bparts, L->mp, L->np) : 0));
   L->off[8] = L->off[12];
   L->off[9] = L->off[11];
   L->off[16] = L->off[14];
@@ -251,6 +325,7 @@ Problem make_problem(char transA, char transB, int64_t m, int64_t n, int64_t k, 
   w.Asl = ws + L.off[5];
   w.Bsl = ws + L.off[6];
   w.planes = (int16_t *)(ws + L.off[7]);
+  w.bpart = (float *)(ws + L.off[7]);
   w.zero = (uint32_t *)(ws + L.off[10]);
   w.zero_words = (int64_t)((L.off[15] - L.off[10]) / 4);
   w.lineB = L.mp;
@@ -261,11 +336,10 @@ Problem make_problem(char transA, char transB, int64_t m, int64_t n, int64_t k, 
   P.ldc = ldc;
   P.limbs = ht->limbs;
   P.mode = g_ts.mode;
-  P.parts = 1;
+  P.parts = L.parts;
+  P.bparts = P.mode == OZ2_MODE_FAST ? 1 : L.bparts;
   return P;
 }
-
-int num_chunks(int64_t kp) { return (int)((kp + kChunkK - 1) / kChunkK); }
 
 // Timing marks: event q is recorded after kernel group q - 1.
 struct Marks {
@@ -298,7 +372,10 @@ int enqueue_scaling(const Problem &P, hipStream_t st, Marks &mark) {
     OZ2_TRY(launch_quant_family(f, &P, nullptr, st));
   mark();
   // step 2: the FP8 bound product (its line maxima only; none in fast mode)
-  if (!fast) OZ2_TRY(launch_gemm_family(kFamBgemm, &P, nullptr, 0, st));
+  if (!fast) {
+    OZ2_TRY(launch_gemm_family(kFamBgemm, &P, nullptr, st));
+    if (P.bparts > 1) OZ2_TRY(launch_gemm_family(kFamBreduce, &P, nullptr, st));
+  }
   mark();
   // step 3: scale exponents mu, nu
   if (!fast)
@@ -316,10 +393,10 @@ int enqueue_products(const Problem &P, hipStream_t st, Marks &mark, bool res_a =
   if (res_a) OZ2_TRY(launch_quant_family(kFamResA, &P, nullptr, st));
   if (res_b) OZ2_TRY(launch_quant_family(kFamResB, &P, nullptr, st));
   mark();
-  // steps 7-8: residue products and their reduction modulo p, per k chunk
-  for (int c = 0; c < num_chunks(P.g.kp); ++c)
-    for (int f : {kFamGemmSq, kFamGemmKa, kFamGemmI8})
-      OZ2_TRY(launch_gemm_family(f, &P, nullptr, c, st));
+  // steps 7-8: residue products and their reduction modulo p (every k part
+  // of a kind in one launch)
+  for (int f : {kFamGemmSq, kFamGemmKa, kFamGemmI8})
+    OZ2_TRY(launch_gemm_family(f, &P, nullptr, st));
   mark();
   // steps 9-10: CRT and inverse scaling
   OZ2_TRY(launch_crt_family(&P, nullptr, P.limbs, P.g.N, st));
@@ -388,6 +465,10 @@ constexpr int kNumConfigs = 6;
 int config_waves(int c) { return c / 3 == 0 ? 8 : 4; }
 int config_max_parts(int c) { return c % 3 == 0 ? 1 : (c % 3 == 1 ? 2 : 4); }
 
+// Grouped launches of at most this many blocks carry a block -> problem
+// table (4 bytes per block) in the plan.
+constexpr int64_t kMaxSegTable = (int64_t)1 << 24;
+
 // The persistent launch of the residue products (not a kernel family of the
 // single-problem path).
 constexpr int kFamPersist = kNumFamilies;
@@ -398,7 +479,7 @@ constexpr int kFamPersist = kNumFamilies;
 // exist once per configuration (they differ in the k parts).
 struct GLaunch {
   int fam, config;  // config: -1 for the launches every configuration shares
-  size_t off_probs, off_order, off_start;
+  size_t off_probs, off_order, off_start, off_seg;  // off_seg: 0 when there is no table
   size_t off_items, off_counters;
   int64_t items;
   bool int8;
@@ -661,7 +742,7 @@ void build_subbatch(const std::vector<Problem> &probs, ImageWriter &W, SubBatch 
   const size_t at_nat = W.put(nat.data(), sizeof(int32_t) * np);
   auto add = [&](int fam, size_t off_probs, int config) {
     std::vector<int64_t> start(np + 1, 0);
-    for (int q = 0; q < np; ++q) start[q + 1] = start[q] + family_blocks(fam, probs[q], 0);
+    for (int q = 0; q < np; ++q) start[q + 1] = start[q] + family_blocks(fam, probs[q]);
     if (start[np] == 0) return;
     GLaunch L;
     memset(&L, 0, sizeof(L));
@@ -670,6 +751,13 @@ void build_subbatch(const std::vector<Problem> &probs, ImageWriter &W, SubBatch 
     L.off_probs = off_probs;
     L.off_order = at_nat;
     L.off_start = W.put(start.data(), sizeof(int64_t) * (np + 1));
+    if (start[np] <= kMaxSegTable) {
+      // block -> problem, so that no block searches the prefix sums
+      std::vector<int32_t> seg((size_t)start[np]);
+      for (int q = 0; q < np; ++q)
+        std::fill(seg.begin() + start[q], seg.begin() + start[q + 1], q);
+      L.off_seg = W.put(seg.data(), sizeof(int32_t) * seg.size());
+    }
     L.G.nseg = np;
     L.G.total = start[np];
     sb->launches.push_back(L);
@@ -705,8 +793,10 @@ void build_subbatch(const std::vector<Problem> &probs, ImageWriter &W, SubBatch 
               it.part = (int16_t)part;
               it.tx = (int32_t)tx;
               it.ty = (int32_t)ty;
-              it.k0 = (int32_t)(part * nb / parts * kPad);
-              it.k1 = (int32_t)((part + 1) * nb / parts * kPad);
+              int64_t k0, k1;
+              part_range(g.kp, parts, part, &k0, &k1);
+              it.k0 = (int32_t)k0;
+              it.k1 = (int32_t)k1;
               items.push_back(it);
             }
     }
@@ -734,7 +824,7 @@ void build_subbatch(const std::vector<Problem> &probs, ImageWriter &W, SubBatch 
 // Kernel group of a family, as reported by ozaki2_get_kernel_times.
 int family_group(int fam) {
   switch (fam) {
-    case kFamBgemm: return 1;
+    case kFamBgemm: case kFamBreduce: return 1;
     case kFamDecide: case kFamFixup: case kFamFinal: return 2;
     case kFamResA: case kFamResB: return 3;
     case kFamGemmSq: case kFamGemmKa: case kFamGemmI8: case kFamPersist: return 4;
@@ -767,7 +857,7 @@ int enqueue_subbatch(const SubBatch &sb, int config, int cus, hipStream_t st, Ma
     if (L.fam == kFamPersist)
       OZ2_TRY(launch_gemm_persistent(config_waves(config), L.int8, L.W, cus, st));
     else if (L.fam == kFamBgemm)
-      OZ2_TRY(launch_gemm_family(L.fam, nullptr, &L.G, 0, st));
+      OZ2_TRY(launch_gemm_family(L.fam, nullptr, &L.G, st));
     else if (L.fam == kFamDecide || L.fam == kFamFixup || L.fam == kFamFinal)
       OZ2_TRY(launch_scale_family(L.fam, nullptr, &L.G, st));
     else if (L.fam == kFamCrt)
@@ -886,6 +976,16 @@ int ozaki2_workspace_layout(int64_t m, int64_t n, int64_t k, int num_moduli, int
     pads[3] = L.M;
   }
   return 11;
+}
+
+int ozaki2_workspace_parts(int64_t m, int64_t n, int64_t k, int num_moduli, int *parts,
+                           int *bound_parts) {
+  if (m < 0 || n < 0 || k < 0 || num_moduli < 1 || num_moduli > OZ2_MAX_MODULI) return -1;
+  Layout L;
+  if (!make_layout(m, n, k, num_moduli, &L, g_ts.blk_m, g_ts.blk_n)) return -1;
+  if (parts) *parts = L.parts;
+  if (bound_parts) *bound_parts = L.bparts;
+  return 0;
 }
 
 int ozaki2_set_stream(void *stream) {
@@ -1237,6 +1337,7 @@ int ozaki2_dgemm_batched(int count, const char *transA, const char *transB, cons
           L.G.probs = (const Problem *)(base + L.off_probs);
           L.G.order = (const int32_t *)(base + L.off_order);
           L.G.start = (const int64_t *)(base + L.off_start);
+          L.G.seg = L.off_seg ? (const int32_t *)(base + L.off_seg) : nullptr;
         }
     }
     p->bucket = bucket_key(p->shape_key);
@@ -1333,6 +1434,12 @@ int ozaki2_get_schedule(void) { return g_ts.last_schedule; }
 int ozaki2_set_schedule(int config) {
   if (config < -1 || config >= kNumConfigs) return -1;
   g_ts.forced = config;
+  return OZ2_SUCCESS;
+}
+
+int ozaki2_set_split(int parts) {
+  if (parts < 0 || parts > kMaxSplit) return -1;
+  g_ts.split = parts;
   return OZ2_SUCCESS;
 }
 

@@ -90,10 +90,14 @@ template <int L, int NF, bool GROUPED>
 __global__ __launch_bounds__(256) void k_crt(Problem P1, Group G) {
   int64_t local;
   const Problem &P = *locate<GROUPED>(P1, G, blockIdx.x, local);
-  const int64_t nbx = (P.g.m + 255) / 256;
-  const int64_t bx = local % nbx, j = local / nbx;
+  // block: 64 rows (one wave each) x 4 columns, so that outputs with few
+  // rows leave few threads idle
+  const int64_t nbx = (P.g.m + 63) / 64;
+  const int64_t i = (local % nbx) * 64 + (threadIdx.x & 63);
+  const int64_t j = (local / nbx) * 4 + (threadIdx.x >> 6);
+  if (j >= P.g.n) return;
   crt_entry<L, NF>(P.w.planes, P.w.shift, P.w.flags, P.tab, P.g.N, P.g.m, P.g.mp, P.g.np,
-                   P.w.lineB, P.alpha, P.beta, P.C, P.ldc, bx * 256 + threadIdx.x, j, P.parts);
+                   P.w.lineB, P.alpha, P.beta, P.C, P.ldc, i, j, P.parts);
 }
 
 __global__ void k_scal(int64_t m, double beta, double *__restrict__ C, int64_t ldc) {
@@ -118,7 +122,7 @@ hipError_t launch_crt_family(const Problem *P, const Group *G, int limbs, int N,
     g1 = *G;
   else
     p1 = *P;
-  const int64_t blocks = grouped ? G->total : family_blocks(kFamCrt, *P, 0);
+  const int64_t blocks = grouped ? G->total : family_blocks(kFamCrt, *P);
   if (blocks <= 0) return hipSuccess;
   if (blocks > 0x7FFFFFFFll) return hipErrorInvalidValue;
   const dim3 grid((unsigned)blocks), blk(256);

@@ -632,33 +632,37 @@ __device__ __forceinline__ void int8_tile_w(const uint8_t *Asl, const uint8_t *B
     }
 }
 
-// Residue products of k chunk `chunk` of one problem, 256 x 256 tiles: KIND 0
-// over the square moduli (tile index z = l), 1 over the Karatsuba moduli
-// (l = nsq + z), 2 over the INT8 moduli (l = nsq + nka + z).
+// Residue products of one problem, 256 x 256 tiles: KIND 0 over the square
+// moduli (l = z mod nsq), 1 over the Karatsuba moduli (l = nsq + z mod nka),
+// 2 over the INT8 moduli (l = nsq + nka + z mod n8).  The workgroup covers k
+// part z / (moduli of the kind) of P.parts and writes that part's copy of the
+// planes; the host makes every part at most kChunkK long.
 template <int KIND>
-__global__ __launch_bounds__(64 * NW_RES, 1) void k_residue_gemm(Problem P, int chunk) {
+__global__ __launch_bounds__(64 * NW_RES, 1) void k_residue_gemm(Problem P) {
   __shared__ __attribute__((aligned(1024))) uint8_t lds[LDS_RING];
   const Geometry &g = P.g;
-  const Dims d =
-      family_dims(KIND == 0 ? kFamGemmSq : (KIND == 1 ? kFamGemmKa : kFamGemmI8), P, chunk);
+  const Dims d = family_dims(KIND == 0 ? kFamGemmSq : (KIND == 1 ? kFamGemmKa : kFamGemmI8), P);
   const Dims c = decode_block(d, blockIdx.x);
   const int64_t mp = uni(g.mp), np = uni(g.np), kp = uni(g.kp);
-  const int64_t kbeg = (int64_t)chunk * kChunkK;
-  const int64_t len = kp - kbeg < kChunkK ? kp - kbeg : kChunkK;
-  const int l = (int)uni((KIND == 0 ? 0 : (KIND == 1 ? g.nsq : g.nsq + g.nka)) + c.z);
+  const int parts = (int)uni((int64_t)P.parts);
+  const int64_t nz = d.z / parts;
+  const int part = (int)uni(c.z / nz);
+  const int l = (int)uni((KIND == 0 ? 0 : (KIND == 1 ? g.nsq : g.nsq + g.nka)) + c.z % nz);
+  int64_t k0, k1;
+  part_range(kp, parts, part, &k0, &k1);
+  const int nk = (int)uni((k1 - k0) / BK);
+  k0 = uni(k0);
+  int16_t *planes = uni(P.w.planes) + uni((int64_t)part * g.N) * mp * np;
   const int tid = threadIdx.x;
   if (KIND == 0)
-    square_tile_w<NW_RES>(uni(P.w.Asl), uni(P.w.Bsl), uni(P.w.planes), uni(P.tab), mp, np, kp,
-                          kbeg, (int)(len / BK), chunk > 0 ? 1 : 0, l, uni(c.x * TIW),
-                          uni(c.y * TJ), lds, tid);
+    square_tile_w<NW_RES>(uni(P.w.Asl), uni(P.w.Bsl), planes, uni(P.tab), mp, np, kp, k0, nk, 0,
+                          l, uni(c.x * TIW), uni(c.y * TJ), lds, tid);
   else if (KIND == 1)
-    karatsuba_tile_w<NW_RES>(uni(P.w.Asl), uni(P.w.Bsl), uni(P.w.planes), uni(P.tab), mp, np,
-                             kp, kbeg, (int)(len / BK), chunk > 0 ? 1 : 0, l, uni(c.x * TIW),
-                             uni(c.y * TJ), lds, tid);
+    karatsuba_tile_w<NW_RES>(uni(P.w.Asl), uni(P.w.Bsl), planes, uni(P.tab), mp, np, kp, k0, nk,
+                             0, l, uni(c.x * TIW), uni(c.y * TJ), lds, tid);
   else
-    int8_tile_w<NW_RES>(uni(P.w.Asl), uni(P.w.Bsl), uni(P.w.planes), uni(P.tab), mp, np, kp,
-                        kbeg, (int)(len / BK), chunk > 0 ? 1 : 0, l, uni(c.x * TIW),
-                        uni(c.y * TJ), lds, tid);
+    int8_tile_w<NW_RES>(uni(P.w.Asl), uni(P.w.Bsl), planes, uni(P.tab), mp, np, kp, k0, nk, 0, l,
+                        uni(c.x * TIW), uni(c.y * TJ), lds, tid);
 }
 
 // One 256 x 256 tile of any FP8 modulus (square or Karatsuba) as three
@@ -790,26 +794,14 @@ __global__ __launch_bounds__(64 * NW, 1) void k_residue_persistent(WorkList W) {
   }
 }
 
-// Line maxima of one 256 x 256 tile of the bound product Abar Bbar (wide
-// single-product loop; FP32 accumulation in one fixed k order, so the result
-// does not depend on the tiling).
-__device__ __forceinline__ void bound_tile(const uint8_t *Abar, const uint8_t *Bbar, int64_t mp,
-                                           int64_t np, int nk, uint32_t *__restrict__ rmaxA,
-                                           uint32_t *__restrict__ rmaxB, int64_t i0, int64_t j0,
-                                           uint8_t *lds, int tid) {
+// Line maxima of one 256 x 256 tile (j0.., i0..) of the bound product held in
+// acc (the layout of the wide tile loop): row maxima into rmaxA, column maxima
+// into rmaxB, by atomic maxima over the tiles.
+__device__ __forceinline__ void bound_maxima(const v16f (&acc)[4][TB<NW_BOUND>()],
+                                             uint32_t *__restrict__ rmaxA,
+                                             uint32_t *__restrict__ rmaxB, int64_t i0,
+                                             int64_t j0, int tid) {
   constexpr int NWW = NW_BOUND, TBW = TB<NW_BOUND>();
-  v16f acc[4][TBW];
-#pragma unroll
-  for (int tj = 0; tj < 4; ++tj)
-#pragma unroll
-    for (int ti = 0; ti < TBW; ++ti)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) acc[tj][ti][v] = 0.0f;
-  resident_ptr(rmaxA, rmaxB);
-  pin_agpr(acc);
-  kloop_w<NWW>(Bbar + j0 * 64, Abar + i0 * 64, np, mp, 0, nk, lds, acc, tid);
-  pin_agpr(acc);
-
   const int lane = tid & 63, wave = tid >> 6;
   const int wj = wave / (NWW / 2), wi = wave % (NWW / 2);
   // maxima over j of each column i (row maxima of Abar Bbar, for mu)
@@ -841,6 +833,52 @@ __device__ __forceinline__ void bound_tile(const uint8_t *Abar, const uint8_t *B
     }
 }
 
+// Part sums of the split bound product: value q of thread t of tile `tile`
+// of part `part` at ((part * tiles + tile) * kBoundVals + q) * threads + t,
+// so that each access of a wave covers 256 consecutive bytes.
+constexpr int kBoundThreads = 64 * NW_BOUND;
+constexpr int kBoundVals = 4 * TB<NW_BOUND>() * 16;
+
+__device__ __forceinline__ int64_t bound_part_at(int64_t part, int64_t tiles, int64_t tile,
+                                                 int q, int tid) {
+  return ((part * tiles + tile) * kBoundVals + q) * kBoundThreads + tid;
+}
+
+// One 256 x 256 tile of the bound product Abar Bbar over k in [kbeg, kbeg +
+// 64 nk) (wide single-product loop; FP32 accumulation in one fixed k order,
+// so the result does not depend on the tiling): its line maxima, or with
+// part_out its FP32 sums stored for k_bound_reduce.
+__device__ __forceinline__ void bound_tile(const uint8_t *Abar, const uint8_t *Bbar, int64_t mp,
+                                           int64_t np, int64_t kbeg, int nk,
+                                           uint32_t *__restrict__ rmaxA,
+                                           uint32_t *__restrict__ rmaxB,
+                                           float *__restrict__ part_out, int64_t i0, int64_t j0,
+                                           uint8_t *lds, int tid) {
+  constexpr int NWW = NW_BOUND, TBW = TB<NW_BOUND>();
+  v16f acc[4][TBW];
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+    for (int ti = 0; ti < TBW; ++ti)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[tj][ti][v] = 0.0f;
+  resident_ptr(rmaxA, rmaxB);
+  pin_agpr(acc);
+  kloop_w<NWW>(Bbar + j0 * 64, Abar + i0 * 64, np, mp, kbeg, nk, lds, acc, tid);
+  pin_agpr(acc);
+  if (part_out) {
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+      for (int ti = 0; ti < TBW; ++ti)
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+          part_out[(int64_t)((tj * TBW + ti) * 16 + v) * kBoundThreads + tid] = acc[tj][ti][v];
+    return;
+  }
+  bound_maxima(acc, rmaxA, rmaxB, i0, j0, tid);
+}
+
 template <bool GROUPED>
 __global__ __launch_bounds__(64 * NW_BOUND, 1) void k_bound_gemm(Problem P1, Group G) {
   __shared__ __attribute__((aligned(1024))) uint8_t lds[LDS_RING];
@@ -849,13 +887,54 @@ __global__ __launch_bounds__(64 * NW_BOUND, 1) void k_bound_gemm(Problem P1, Gro
     int64_t local;
     const Problem &P = *locate<GROUPED>(P1, G, b, local);
     const Geometry &g = P.g;
-    const Dims d = family_dims(kFamBgemm, P, 0);
+    const Dims d = family_dims(kFamBgemm, P);
     const Dims c = decode_block(d, local);
     const int64_t mp = uni(g.mp), np = uni(g.np), kp = uni(g.kp);
     uint32_t *rmax = uni(P.w.rmax);
-    bound_tile(uni(P.w.Abar), uni(P.w.Bbar), mp, np, (int)(kp / BK), rmax, rmax + mp,
-               uni(c.x * TIW), uni(c.y * TJ), lds, threadIdx.x);
+    // a split product (single problems only): part c.z of P.bparts
+    const int parts = GROUPED ? 1 : (int)uni((int64_t)P.bparts);
+    int64_t k0 = 0, k1 = kp;
+    float *part_out = nullptr;
+    if (!GROUPED && parts > 1) {
+      part_range(kp, parts, (int)c.z, &k0, &k1);
+      const int64_t tiles = d.x * d.y;
+      part_out = uni(P.w.bpart) + bound_part_at(c.z, tiles, c.y * d.x + c.x, 0, 0);
+    }
+    bound_tile(uni(P.w.Abar), uni(P.w.Bbar), mp, np, uni(k0), (int)uni((k1 - k0) / BK), rmax,
+               rmax + mp, part_out, uni(c.x * TIW), uni(c.y * TJ), lds, threadIdx.x);
   }
+}
+
+// Split bound product: per tile, the FP32 sum of its parts in part order,
+// then the line maxima.
+__global__ __launch_bounds__(64 * NW_BOUND, 1) void k_bound_reduce(Problem P) {
+  constexpr int TBW = TB<NW_BOUND>();
+  const Dims d = family_dims(kFamBgemm, P);
+  const int64_t tiles = d.x * d.y;
+  const int64_t tile = blockIdx.x, parts = P.bparts;
+  const int tid = threadIdx.x;
+  const float *src = P.w.bpart + bound_part_at(0, tiles, tile, 0, tid);
+  const int64_t part_stride = tiles * kBoundVals * kBoundThreads;
+  v16f acc[4][TBW];
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+    for (int ti = 0; ti < TBW; ++ti)
+#pragma unroll
+      for (int v = 0; v < 16; ++v)
+        acc[tj][ti][v] = src[(int64_t)((tj * TBW + ti) * 16 + v) * kBoundThreads];
+  for (int64_t q = 1; q < parts; ++q) {
+    const float *s = src + q * part_stride;
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+      for (int ti = 0; ti < TBW; ++ti)
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+          acc[tj][ti][v] += s[(int64_t)((tj * TBW + ti) * 16 + v) * kBoundThreads];
+  }
+  uint32_t *rmax = P.w.rmax;
+  bound_maxima(acc, rmax, rmax + P.g.mp, (tile % d.x) * TIW, (tile / d.x) * TJ, tid);
 }
 
 }  // namespace
@@ -879,10 +958,9 @@ hipError_t launch_gemm_persistent(int nw, bool int8, const WorkList &W, int64_t 
   return hipGetLastError();
 }
 
-hipError_t launch_gemm_family(int fam, const Problem *P, const Group *G, int chunk,
-                              hipStream_t st) {
-  // grouped launches: the bound product only (a batch's residue products run
-  // as one persistent launch)
+hipError_t launch_gemm_family(int fam, const Problem *P, const Group *G, hipStream_t st) {
+  // grouped launches: the (unsplit) bound product only (a batch's residue
+  // products run as one persistent launch)
   const bool grouped = G != nullptr;
   if (grouped && fam != kFamBgemm) return hipErrorInvalidValue;
   Problem p1;
@@ -893,11 +971,11 @@ hipError_t launch_gemm_family(int fam, const Problem *P, const Group *G, int chu
     g1 = *G;
   else
     p1 = *P;
-  const int64_t blocks = grouped ? G->total : family_blocks(fam, *P, chunk);
+  const int64_t blocks = grouped ? G->total : family_blocks(fam, *P);
   if (blocks <= 0) return hipSuccess;
   if (blocks > 0x7FFFFFFFll) return hipErrorInvalidValue;
   const dim3 gr((unsigned)blocks),
-      blk(fam == kFamBgemm ? 64 * NW_BOUND : 64 * NW_RES);
+      blk(fam == kFamBgemm || fam == kFamBreduce ? 64 * NW_BOUND : 64 * NW_RES);
   switch (fam) {
     case kFamBgemm:
       if (grouped)
@@ -905,14 +983,17 @@ hipError_t launch_gemm_family(int fam, const Problem *P, const Group *G, int chu
       else
         hipLaunchKernelGGL((k_bound_gemm<false>), gr, blk, 0, st, p1, g1);
       break;
+    case kFamBreduce:
+      hipLaunchKernelGGL(k_bound_reduce, gr, blk, 0, st, p1);
+      break;
     case kFamGemmSq:
-      hipLaunchKernelGGL((k_residue_gemm<0>), gr, blk, 0, st, p1, chunk);
+      hipLaunchKernelGGL((k_residue_gemm<0>), gr, blk, 0, st, p1);
       break;
     case kFamGemmKa:
-      hipLaunchKernelGGL((k_residue_gemm<1>), gr, blk, 0, st, p1, chunk);
+      hipLaunchKernelGGL((k_residue_gemm<1>), gr, blk, 0, st, p1);
       break;
     case kFamGemmI8:
-      hipLaunchKernelGGL((k_residue_gemm<2>), gr, blk, 0, st, p1, chunk);
+      hipLaunchKernelGGL((k_residue_gemm<2>), gr, blk, 0, st, p1);
       break;
     default:
       return hipErrorInvalidValue;

@@ -11,7 +11,7 @@ namespace oz2 {
 constexpr int kMaxN = OZ2_MAX_MODULI;
 constexpr int kLimbs = 11;       // 32-bit limbs for S = sum_l w_l u_l (P < 2^296 for N = 33)
 constexpr int kPad = 256;        // every dimension is padded to this multiple
-constexpr int kChunkK = 1 << 15; // k handled by one residue-product launch
+constexpr int kChunkK = 1 << 15; // longest k one residue-product accumulation covers
 constexpr int kPowT = 192;       // 2^t mod p is tabulated for t < kPowT; the integer
                                  // a' = mant 2^t of an input never has t >= e + 8, and the
                                  // scale exponent e stays below 160 for N <= 33
@@ -78,6 +78,8 @@ struct Work {
   uint8_t *Abar, *Bbar;
   uint8_t *Asl, *Bsl;
   int16_t *planes;
+  float *bpart;       // FP32 sums of the bound product's k parts (when split), laid
+                      // over the planes, which are written only later
   uint32_t *zero;     // the buffers that start at zero (amax .. amb), contiguous
   int64_t zero_words;
   int64_t lineB;      // index of op(B)'s first line in the per-line vectors, counted
@@ -107,7 +109,7 @@ struct Problem {
   int32_t mode;        // OZ2_MODE_ACCURATE or OZ2_MODE_FAST (selects the launch sequence)
   int32_t parts;       // k parts of the residue products (split-K): the CRT sums this
                        // many copies of the residue planes, each N mp np entries apart
-  int32_t reserved;
+  int32_t bparts;      // k parts of the bound product (1: one pass with line maxima)
 };
 
 // One work item of the persistent residue-product launch: tile (tx, ty) of
@@ -158,13 +160,14 @@ enum Family : int {
   kFamBarB,
   kFamNormA,      // fast mode: squared norms of the bound operands' lines
   kFamNormB,
-  kFamBgemm,      // FP8 bound product (line maxima)
+  kFamBgemm,      // FP8 bound product (line maxima, or per-part sums when split)
+  kFamBreduce,    // split bound product: sum of the parts, line maxima
   kFamDecide,     // scale exponents from the FP8 bound
   kFamFixup,      // exact bound product for undecided lines
   kFamFinal,      // shifts
   kFamResA,       // residues and FP8 digits
   kFamResB,
-  kFamGemmSq,     // residue products, square moduli (one launch per k chunk)
+  kFamGemmSq,     // residue products, square moduli (every k part in one launch)
   kFamGemmKa,     // residue products, Karatsuba moduli
   kFamGemmI8,     // residue products, INT8 moduli
   kFamCrt,        // CRT, inverse scaling, alpha / beta
@@ -199,9 +202,9 @@ struct Dims {
   int64_t x, y, z;
 };
 
-// Block grid of family `fam` for one problem (k chunk `chunk` for the residue
-// products).  Blocks are numbered x fastest, then y, then z.
-__host__ __device__ inline Dims family_dims(int fam, const Problem &P, int chunk) {
+// Block grid of family `fam` for one problem.  Blocks are numbered x fastest,
+// then y, then z.
+__host__ __device__ inline Dims family_dims(int fam, const Problem &P) {
   const Geometry &g = P.g;
   switch (fam) {
     case kFamFill: {
@@ -225,7 +228,9 @@ __host__ __device__ inline Dims family_dims(int fam, const Problem &P, int chunk
     case kFamResB:
       return {g.np / kQL, g.kp / kQK, 1};
     case kFamBgemm:
-      return {g.mp / kGemmTIW, g.np / kGemmTJ, 1};
+      return {g.mp / kGemmTIW, g.np / kGemmTJ, P.bparts};
+    case kFamBreduce:
+      return {g.mp / kGemmTIW, g.np / kGemmTJ, P.bparts > 1 ? 1 : 0};
     case kFamDecide:
     case kFamFinal:
       return {(g.mp + g.np + 255) / 256, 1, 1};
@@ -236,20 +241,29 @@ __host__ __device__ inline Dims family_dims(int fam, const Problem &P, int chunk
     case kFamGemmSq:
     case kFamGemmKa:
     case kFamGemmI8: {
-      if ((int64_t)chunk * kChunkK >= g.kp) return {0, 1, 1};
-      if (fam == kFamGemmSq) return {g.mp / kGemmTIW, g.np / kGemmTJ, g.nsq};
-      if (fam == kFamGemmKa) return {g.mp / kGemmTIW, g.np / kGemmTJ, g.nka};
-      return {g.mp / kGemmTIW, g.np / kGemmTJ, g.N - g.nsq - g.nka};
+      // z = part * (moduli of the kind) + modulus
+      const int64_t nz = fam == kFamGemmSq ? g.nsq : (fam == kFamGemmKa ? g.nka : g.N - g.nsq - g.nka);
+      return {g.mp / kGemmTIW, g.np / kGemmTJ, nz * P.parts};
     }
     case kFamCrt:
-      return {(g.m + 255) / 256, g.n, 1};
+      return {(g.m + 63) / 64, (g.n + 3) / 4, 1};
     default:
       return {0, 1, 1};
   }
 }
 
-__host__ __device__ inline int64_t family_blocks(int fam, const Problem &P, int chunk) {
-  const Dims d = family_dims(fam, P, chunk);
+// k range [*k0, *k1) of part `part` of `parts` of the residue products: the
+// kp / kPad blocks of 256 k dealt out as evenly as possible (no part is empty
+// when parts <= kp / kPad).
+__host__ __device__ inline void part_range(int64_t kp, int parts, int part, int64_t *k0,
+                                           int64_t *k1) {
+  const int64_t nb = kp / kPad;
+  *k0 = (int64_t)part * nb / parts * kPad;
+  *k1 = ((int64_t)part + 1) * nb / parts * kPad;
+}
+
+__host__ __device__ inline int64_t family_blocks(int fam, const Problem &P) {
+  const Dims d = family_dims(fam, P);
   return d.x * d.y * d.z;
 }
 
@@ -260,6 +274,7 @@ struct Group {
   const Problem *probs;
   const int32_t *order;
   const int64_t *start;
+  const int32_t *seg;   // segment of every block (null: found by binary search in start)
   int nseg;
   int64_t total;
 };
@@ -285,7 +300,9 @@ template <bool GROUPED>
 __device__ __forceinline__ const Problem *locate(const Problem &P1, const Group &G, int64_t b,
                                                  int64_t &local) {
   if constexpr (GROUPED) {
-    const int q = find_segment(G, b);
+    // one load from the per-block table where the plan has one (a binary
+    // search costs a chain of dependent loads in every block)
+    const int q = G.seg ? G.seg[b] : find_segment(G, b);
     local = b - G.start[q];
     return &G.probs[G.order[q]];
   } else {
@@ -307,13 +324,12 @@ __device__ __forceinline__ Dims decode_block(const Dims &d, int64_t local) {
 
 // ---- launchers (all asynchronous on `st`) ----
 // Exactly one of P (a single problem, passed to the kernel by value) and G
-// (a grouped launch over device-resident problems) is non-null.  `chunk` is
-// the k chunk of the residue products, which launch_gemm_family runs for a
-// single problem only (a batch's run as launch_gemm_persistent).
+// (a grouped launch over device-resident problems) is non-null.
+// launch_gemm_family runs the residue products for a single problem only (a
+// batch's run as launch_gemm_persistent).
 hipError_t launch_quant_family(int fam, const Problem *P, const Group *G, hipStream_t st);
 hipError_t launch_scale_family(int fam, const Problem *P, const Group *G, hipStream_t st);
-hipError_t launch_gemm_family(int fam, const Problem *P, const Group *G, int chunk,
-                              hipStream_t st);
+hipError_t launch_gemm_family(int fam, const Problem *P, const Group *G, hipStream_t st);
 // The persistent residue-product launch: `grid` workgroups of nw (8 or 4)
 // waves take items of W in order until none is left; int8 selects the INT8
 // arm's products (every item's modulus is then an INT8 one), else every

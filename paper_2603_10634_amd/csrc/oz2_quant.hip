@@ -78,7 +78,7 @@ template <bool GROUPED>
 __global__ __launch_bounds__(256) void k_fill(Problem P1, Group G) {
   int64_t local;
   const Problem &P = *locate<GROUPED>(P1, G, blockIdx.x, local);
-  const Dims d = family_dims(kFamFill, P, 0);
+  const Dims d = family_dims(kFamFill, P);
   fill_zero(P.w.zero, P.w.zero_words, local, d.x);
 }
 
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(256) void k_bound_operand(Problem P1, Group G) {
   const Problem &P = *locate<GROUPED>(P1, G, blockIdx.x, local);
   const Operand &op = SIDE == 0 ? P.A : P.B;
   const int64_t base = SIDE == 0 ? 0 : P.g.mp;
-  const Dims d = family_dims(SIDE == 0 ? kFamBarA : kFamBarB, P, 0);
+  const Dims d = family_dims(SIDE == 0 ? kFamBarA : kFamBarB, P);
   const int64_t bx = local % d.x, by = local / d.x;
   bound_operand_tile(op, SIDE == 0 ? P.g.mp : P.g.np, bx * kQL, by * kQK, P.w.amax + base,
                      P.w.E + base, P.w.flags + base, SIDE == 0 ? P.w.Abar : P.w.Bbar, tile);
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(256) void k_bound_norm(Problem P1, Group G) {
   const Problem &P = *locate<GROUPED>(P1, G, blockIdx.x, local);
   const Operand &op = SIDE == 0 ? P.A : P.B;
   const int64_t base = SIDE == 0 ? 0 : P.g.mp;
-  const Dims d = family_dims(SIDE == 0 ? kFamNormA : kFamNormB, P, 0);
+  const Dims d = family_dims(SIDE == 0 ? kFamNormA : kFamNormB, P);
   const int64_t bx = local % d.x, by = local / d.x;
   bound_norm_tile(op, bx * kQL, by * kQK, P.w.amax + base, P.w.E + base, P.w.flags + base,
                   P.w.rfix + base, tile);
@@ -239,12 +239,17 @@ __global__ __launch_bounds__(256) void k_bound_norm(Problem P1, Group G) {
 // signed integer x = sign mant 2^min(t, 10) (t > 0) or a' (t <= 0) is held
 // exactly in a double (|x| < 2^63).  Per modulus, x mod p is taken in FP64:
 // q = rint(x p^-1) is within 21 of the rounded quotient (within one when
-// |x| < 2^53), x - q p is exact in one fused multiply-add (|x - q p| < 2^15),
-// and when some input of the wave has t > 0 one FP32 step reduces it to
-// within one of [lo, hi] = [-floor(p/2), ceil(p/2) - 1]; one correction in
-// each direction finishes.  Inputs with t > 10 (only for large N: t <= e - 45
-// for the scale exponent e) are then multiplied by 2^(t - 10) mod p (tables)
-// and reduced again in FP32 (products below 2^20, exact).  Digits (Sections
+// |x| < 2^53), and f = x - q p is exact in one fused multiply-add
+// (|f| < 2^15).  One FP32 step f - p rint(f p^-1) then removes the nearest
+// multiple of p: the computed quotient is within |f / p| 2^-23 < 2^-8 / p of
+// f / p, while for odd p an integer f / p is at least 1 / (2p) from a tie,
+// so the result is exactly in [-(p - 1)/2, (p - 1)/2]; for even p it is
+// in [-p/2, p/2] and a tie's +p/2 is moved to -p/2, giving the symmetric
+// range [-floor(p/2), ceil(p/2) - 1] in both cases.  Inputs with t > 10 (only
+// for large N: t <= e - 45 for the scale exponent e) are multiplied by
+// 2^(t - 10) mod p (tables) and reduced by the same FP32 step (products below
+// p^2 / 2 < 2^20, exact; quotient error below p 2^-24 < 1 / (2p) for
+// p < 2896).  Digits (Sections
 // III-B, III-C) are formed in FP32, exact for these small integers, and
 // packed to E4M3 two at a time by the hardware conversion (exact: every digit
 // has |d| <= 16).  An INT8 modulus (Section II) stores the residue itself,
@@ -257,40 +262,37 @@ constexpr int kRE = kQK * kQL / 256;  // inputs per thread of a quantization til
 struct ResidueIn {
   double x[kRE];  // sign mant 2^min(t, 10) (t > 0) or signed a' (t <= 0), exact
   int t[kRE];     // t > 10: the power of two t - 10 still to apply, else 0
-  bool big;      // some lane of the wave has t > 0
-  bool huge;     // some lane of the wave has t > 10
+  bool huge;      // some lane of the wave has t > 10
 };
 
-template <int KIND>
+template <int KIND, bool EVEN>
 __device__ __forceinline__ void modulus_pass(const ResidueIn &in, const Tables *__restrict__ tab,
                                              int l, uint8_t *dst, int64_t slice_stride) {
   const int p = tab->p[l];
   const float pf = (float)p;
-  const float lof = (float)(-(p >> 1)), hif = (float)(p - 1 - (p >> 1));
+  const float hif = (float)(p - 1 - (p >> 1));
   const double pd = (double)p, invpd = tab->inv_pd[l];
   const float invpf = tab->inv_p[l];
   float fu[kRE];
 #pragma unroll
   for (int q = 0; q < kRE; ++q) {
     const double x = in.x[q];
-    float f = (float)fma(-rint(x * invpd), pd, x);
-    if (in.big) f = fmaf(-rintf(f * invpf), pf, f);
-    f = f > hif ? f - pf : f;
-    f = f < lof ? f + pf : f;
-    fu[q] = f;
+    const float f = (float)fma(-rint(x * invpd), pd, x);
+    fu[q] = fmaf(-rintf(f * invpf), pf, f);
   }
   if (in.huge) {
 #pragma unroll
     for (int q = 0; q < kRE; ++q) {
       if (in.t[q] > 0) {
         const float prod = fu[q] * (float)tab->pw[l][in.t[q]];
-        const float qq = rintf(prod * invpf);
-        float f = fmaf(-qq, pf, prod);
-        f = f > hif ? f - pf : f;
-        f = f < lof ? f + pf : f;
-        fu[q] = f;
+        fu[q] = fmaf(-rintf(prod * invpf), pf, prod);
       }
     }
+  }
+  if (EVEN) {
+    // a tie leaves +p/2, which belongs to -p/2
+#pragma unroll
+    for (int q = 0; q < kRE; ++q) fu[q] = fu[q] > hif ? fu[q] - pf : fu[q];
   }
   constexpr int G = kRE / 4;
   int w1[G], w2[G], w3[G];
@@ -313,9 +315,13 @@ __device__ __forceinline__ void modulus_pass(const ResidueIn &in, const Tables *
     for (int z = 0; z < 4; ++z) {
       const float f = fu[4 * g + z];
       if (KIND == 0) {
-        // p = s^2: x1 = round(u / s) (ties away from zero), x2 = u - s x1
+        // p = s^2: x1 = round(u / s) (ties away from zero), x2 = u - s x1;
+        // for odd s, u / s is never a tie and rint rounds to the nearest
         const float tq = f * invs;
-        x1[z] = truncf(tq + copysignf(0.5f, tq)) + 0.0f;  // + 0 turns -0 into +0
+        if (EVEN)
+          x1[z] = truncf(tq + copysignf(0.5f, tq)) + 0.0f;  // + 0 turns -0 into +0
+        else
+          x1[z] = rintf(tq) + 0.0f;
         x2[z] = fmaf(-sf, x1[z], f);
       } else {
         // s = 16: x1 = sign(u) ceil(|u| / 16), x2 = u - 16 x1, x3 = x1 + x2
@@ -352,7 +358,7 @@ __device__ __forceinline__ void residues_tile(const Operand &op, int64_t kp, int
   const int s = shift[r];  // log2(mu_r)
 
   ResidueIn in;
-  bool big = false, huge = false;
+  bool huge = false;
 #pragma unroll
   for (int q = 0; q < kRE; ++q) {
     const uint64_t bits = (uint64_t)__double_as_longlong(tile[tile_at(rl, b * kRE + q)]);
@@ -374,21 +380,35 @@ __device__ __forceinline__ void residues_tile(const Operand &op, int64_t kp, int
     const double md = ldexp((double)m, t < kDirectT ? t : kDirectT);
     in.x[q] = ((bits >> 63) && m) ? -md : md;
     in.t[q] = t > kDirectT ? t - kDirectT : 0;
-    big |= t > 0;
     huge |= t > kDirectT;
   }
-  in.big = __any(big);
   in.huge = __any(huge);
 
   const int64_t slice_stride = lines_pad * kp;
   uint8_t *base = slices + kblocked(r, h0 + b * kRE, lines_pad);
+  // p is uniform: the parity test is a branch, not a select
   int l = 0;
-  for (; l < nsq; ++l)
-    modulus_pass<0>(in, tab, l, base + (int64_t)tab->slice0[l] * slice_stride, slice_stride);
-  for (; l < nsq + nka; ++l)
-    modulus_pass<1>(in, tab, l, base + (int64_t)tab->slice0[l] * slice_stride, slice_stride);
-  for (; l < N; ++l)
-    modulus_pass<2>(in, tab, l, base + (int64_t)tab->slice0[l] * slice_stride, slice_stride);
+  for (; l < nsq; ++l) {
+    uint8_t *dst = base + (int64_t)tab->slice0[l] * slice_stride;
+    if (tab->p[l] & 1)
+      modulus_pass<0, false>(in, tab, l, dst, slice_stride);
+    else
+      modulus_pass<0, true>(in, tab, l, dst, slice_stride);
+  }
+  for (; l < nsq + nka; ++l) {
+    uint8_t *dst = base + (int64_t)tab->slice0[l] * slice_stride;
+    if (tab->p[l] & 1)
+      modulus_pass<1, false>(in, tab, l, dst, slice_stride);
+    else
+      modulus_pass<1, true>(in, tab, l, dst, slice_stride);
+  }
+  for (; l < N; ++l) {
+    uint8_t *dst = base + (int64_t)tab->slice0[l] * slice_stride;
+    if (tab->p[l] & 1)
+      modulus_pass<2, false>(in, tab, l, dst, slice_stride);
+    else
+      modulus_pass<2, true>(in, tab, l, dst, slice_stride);
+  }
 }
 
 template <bool GROUPED, int SIDE>
@@ -398,7 +418,7 @@ __global__ __launch_bounds__(256) void k_residues(Problem P1, Group G) {
   const Problem &P = *locate<GROUPED>(P1, G, blockIdx.x, local);
   const Operand &op = SIDE == 0 ? P.A : P.B;
   const int64_t base = SIDE == 0 ? 0 : P.w.lineB;
-  const Dims d = family_dims(SIDE == 0 ? kFamResA : kFamResB, P, 0);
+  const Dims d = family_dims(SIDE == 0 ? kFamResA : kFamResB, P);
   const int64_t bx = local % d.x, by = local / d.x;
   residues_tile(op, P.g.kp, SIDE == 0 ? P.g.mp : P.g.np, bx * kQL, by * kQK, P.w.shift + base,
                 P.tab, P.g.N, P.g.nsq, P.g.nka, SIDE == 0 ? P.w.Asl : P.w.Bsl, tile);
@@ -416,7 +436,7 @@ hipError_t launch_quant_family(int fam, const Problem *P, const Group *G, hipStr
     g1 = *G;
   else
     p1 = *P;
-  const int64_t blocks = grouped ? G->total : family_blocks(fam, *P, 0);
+  const int64_t blocks = grouped ? G->total : family_blocks(fam, *P);
   if (blocks <= 0) return hipSuccess;
   if (blocks > 0x7FFFFFFFll) return hipErrorInvalidValue;
   const dim3 grid((unsigned)blocks), blk(256);

@@ -45,7 +45,7 @@ __global__ __launch_bounds__(256) void k_scale_decide(Problem P1, Group G) {
   int ev = 0;
   if (r > 0.0f && !(w.flags[L] & kZeroLine)) {
     int e_small, e_large;
-    window_exponents((double)r, P.g.kp, P.tab->D, &e_small, &e_large);
+    window_exponents((double)r, P.g.kp, P.bparts, P.tab->D, &e_small, &e_large);
     ev = e_small;
     if (e_small != e_large) {
       const uint32_t slot = atomicAdd(&w.amb[0], 1u);
@@ -56,46 +56,93 @@ __global__ __launch_bounds__(256) void k_scale_decide(Problem P1, Group G) {
   w.e[L] = ev;
 }
 
-// Exact maxima of the bound product over the flagged lines.  Each of the
-// problem's nblk workgroups walks (line, block of 32 partner lines) items.
+// Exact maxima of the bound product over the flagged lines.  With both
+// factors multiples of 2^-9 up to 256, q9 = 2^9 x (an entry of Abar or Bbar)
+// is an integer below 2^18 and every partial sum of q9 products is an integer
+// below 2^52 (k <= 2^18), so FP64 fused multiply-adds sum them exactly, in any
+// order.  The flagged lines are taken in groups of kFixG consecutive list
+// entries; an item is (side, group, chunk of kFixJ partner lines): the group's
+// lines of that side (rows of op(A), or columns of op(B)), decoded into LDS
+// kFixKC k at a time, against one partner line per thread; the block's
+// maximum per line goes to rfix (2^18 x the exact maximum) by an atomic
+// maximum.  Each of the problem's nblk workgroups walks items blk, blk + nblk..
+constexpr int kFixG = 8;
+constexpr int kFixKC = 512;
+constexpr int kFixJ = 256;
+
 __device__ __forceinline__ void scale_fixup(const uint8_t *__restrict__ Abar,
                                             const uint8_t *__restrict__ Bbar, int64_t mp,
                                             int64_t np, int64_t kp,
                                             const uint32_t *__restrict__ amb,
                                             uint64_t *__restrict__ rfix, int64_t blk,
                                             int64_t nblk) {
-  const uint32_t count = amb[0];
-  const int64_t npb = ((mp > np ? mp : np) + 31) / 32;
-  const int64_t items = (int64_t)count * npb;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ double own[kFixG][kFixKC];
+  __shared__ double q9tab[128];
+  const int t = threadIdx.x;
+  if (t < 128) q9tab[t] = (double)e4m3_q9((uint32_t)t);
+  const int64_t count = amb[0];
+  const int64_t groups = (count + kFixG - 1) / kFixG;
+  const int64_t chunks = ((mp > np ? mp : np) + kFixJ - 1) / kFixJ;
+  const int64_t items = 2 * groups * chunks;
   for (int64_t it = blk; it < items; it += nblk) {
-    const int64_t L = amb[1 + it / npb];
-    const int64_t pb = it % npb;
-    const bool rowA = L < mp;
-    const uint8_t *own = rowA ? Abar : Bbar;
-    const int64_t rown = rowA ? L : L - mp, nown = rowA ? mp : np;
-    const uint8_t *part = rowA ? Bbar : Abar;
-    const int64_t npart = rowA ? np : mp;
-    uint64_t best = 0;
-    for (int z = 0; z < 8; ++z) {
-      const int64_t j = pb * 32 + wave * 8 + z;
-      if (j >= npart) break;
-      uint64_t sum = 0;
-      for (int64_t h = (int64_t)lane * 8; h < kp; h += 512) {
-        // 8 bytes at h (h % 8 == 0) sit in one 64-byte piece of the line
-        const uint64_t a8 = *(const uint64_t *)(own + kblocked(rown, h, nown));
-        const uint64_t b8 = *(const uint64_t *)(part + kblocked(j, h, npart));
+    const int side = (int)(it & 1);  // 0: rows of op(A) against the columns of op(B)
+    const int64_t g = (it >> 1) % groups, c = (it >> 1) / groups;
+    const uint8_t *own_op = side == 0 ? Abar : Bbar;
+    const uint8_t *part = side == 0 ? Bbar : Abar;
+    const int64_t nown = side == 0 ? mp : np, npart = side == 0 ? np : mp;
+    const int64_t base = side == 0 ? 0 : mp;  // line index of the side's first line
+    // the group's lines of this side (-1: none), the same in every thread
+    int64_t L[kFixG];
+    bool any = false;
 #pragma unroll
-        for (int z8 = 0; z8 < 8; ++z8) {
-          const uint32_t qa = e4m3_q9((uint32_t)(a8 >> (8 * z8)) & 0x7Fu);
-          const uint32_t qb = e4m3_q9((uint32_t)(b8 >> (8 * z8)) & 0x7Fu);
-          sum += (uint64_t)qa * qb;
+    for (int q = 0; q < kFixG; ++q) {
+      const int64_t e = g * kFixG + q;
+      const int64_t l = e < count ? (int64_t)amb[1 + e] : -1;
+      L[q] = l >= 0 && (l < mp) == (side == 0) ? l : -1;
+      any |= L[q] >= 0;
+    }
+    if (!any || c * kFixJ >= npart) continue;
+    const int64_t j = c * kFixJ + t;
+    double acc[kFixG];
+#pragma unroll
+    for (int q = 0; q < kFixG; ++q) acc[q] = 0.0;
+    for (int64_t k0 = 0; k0 < kp; k0 += kFixKC) {
+      const int kc = kp - k0 < kFixKC ? (int)(kp - k0) : kFixKC;  // 256 or 512
+      __syncthreads();  // the previous chunk's (or item's) readers are done
+#pragma unroll
+      for (int v = 0; v < kFixG * kFixKC / kFixJ; ++v) {
+        const int q = v / (kFixKC / kFixJ);
+        const int h = (v % (kFixKC / kFixJ)) * kFixJ + t;
+        double x = 0.0;
+        if (L[q] >= 0 && h < kc)
+          x = q9tab[own_op[kblocked(L[q] - base, k0 + h, nown)] & 0x7Fu];
+        own[q][h] = x;
+      }
+      __syncthreads();
+      if (j < npart) {
+        for (int h = 0; h < kc; h += 8) {
+          // 8 bytes at h (h % 8 == 0) sit in one 64-byte piece of the line
+          const uint64_t b8 = *(const uint64_t *)(part + kblocked(j, k0 + h, npart));
+#pragma unroll
+          for (int z = 0; z < 8; ++z) {
+            const double b = q9tab[(uint32_t)(b8 >> (8 * z)) & 0x7Fu];
+#pragma unroll
+            for (int q = 0; q < kFixG; ++q) acc[q] = fma(own[q][h + z], b, acc[q]);
+          }
         }
       }
-      for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
-      best = sum > best ? sum : best;
     }
-    if (lane == 0 && best) atomicMax((unsigned long long *)&rfix[L], (unsigned long long)best);
+    // block maxima per line: exact integers below 2^52
+#pragma unroll
+    for (int q = 0; q < kFixG; ++q) {
+      if (L[q] < 0) continue;
+      uint64_t m = (uint64_t)acc[q];
+      for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t o = __shfl_xor(m, off, 64);
+        m = o > m ? o : m;
+      }
+      if ((t & 63) == 0 && m) atomicMax((unsigned long long *)&rfix[L[q]], (unsigned long long)m);
+    }
   }
 }
 
@@ -103,7 +150,7 @@ template <bool GROUPED>
 __global__ __launch_bounds__(256) void k_scale_fixup(Problem P1, Group G) {
   int64_t local;
   const Problem &P = *locate<GROUPED>(P1, G, blockIdx.x, local);
-  const Dims d = family_dims(kFamFixup, P, 0);
+  const Dims d = family_dims(kFamFixup, P);
   scale_fixup(P.w.Abar, P.w.Bbar, P.g.mp, P.g.np, P.g.kp, P.w.amb, P.w.rfix, local, d.x);
 }
 
@@ -135,7 +182,7 @@ hipError_t launch_scale_family(int fam, const Problem *P, const Group *G, hipStr
     g1 = *G;
   else
     p1 = *P;
-  const int64_t blocks = grouped ? G->total : family_blocks(fam, *P, 0);
+  const int64_t blocks = grouped ? G->total : family_blocks(fam, *P);
   if (blocks <= 0) return hipSuccess;
   if (blocks > 0x7FFFFFFFll) return hipErrorInvalidValue;
   const dim3 grid((unsigned)blocks), blk(256);

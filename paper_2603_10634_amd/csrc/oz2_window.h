@@ -16,13 +16,17 @@
 //
 // (The measured behaviour of v_mfma_f32_32x32x64_f8f6f4 is narrower: the
 // products are truncated toward zero inside a group and the accumulator
-// rounds up at most once per instruction.)  For one output c = sum_h x_h with
-// x_h >= 0 and Q = ceil(k/8) groups, a group sum s changes by less than
-// 7 2^-13 g <= 7 2^-13 s by (W1), and Q faithful additions multiply the
-// result by at most (1 +- 2^-23)^Q, so with e1 = 7 2^-13, u = 2^-23:
+// rounds up at most once per instruction.)  When the k range is split into
+// `parts` ranges whose FP32 sums are added afterwards (each addition rounded
+// to nearest, within (W2)), every group sum passes through at most
+// ceil(k/8) + parts - 1 additions.  For one output c = sum_h x_h with x_h >= 0
+// and Q = ceil(k/8) + parts - 1, a group sum s changes by less than
+// 7 2^-13 g <= 7 2^-13 s by (W1), and at most Q faithful additions multiply
+// it by at most (1 +- 2^-23)^Q, so with e1 = 7 2^-13, u = 2^-23:
 //     c (1 - gu) <= c' <= c (1 + go),
-//     gu = e1 + Q u,   go = e1 + 1.02 Q u   (for Q u <= 2^-8, i.e. k <= 2^18;
-//     (1 + e1)(1 + u)^Q <= (1 + e1)(1 + 1.004 Q u) <= 1 + e1 + 1.02 Q u).
+//     gu = e1 + Q u,   go = e1 + 1.02 Q u   (for Q u <= 2^-7, i.e. k <= 2^18
+//     with up to 2^14 parts; (1 + e1)(1 + u)^Q <= (1 + e1)(1 + 1.004 Q u)
+//     <= 1 + e1 + 1.02 Q u).
 // The maximum over a line inherits both bounds (r' >= c'_max >= r (1 - gu),
 // r' <= max_j c_j (1 + go) = r (1 + go)), so
 //     r'/(1 + go) <= r <= r'/(1 - gu).
@@ -47,9 +51,10 @@
 
 namespace oz2 {
 
-// Relative deviations of (W) for a k extent of kp: c (1 - gu) <= c' <= c (1 + go).
-OZ2_HD inline void bound_deviation(int64_t kp, double *gu, double *go) {
-  const double Q = (double)((kp + 7) / 8);
+// Relative deviations of (W) for a k extent of kp summed in `parts` ranges:
+// c (1 - gu) <= c' <= c (1 + go).
+OZ2_HD inline void bound_deviation(int64_t kp, int parts, double *gu, double *go) {
+  const double Q = (double)((kp + 7) / 8 + parts - 1);
   const double e1 = 7.0 * 0x1p-13;
   *gu = e1 + Q * 0x1p-23;
   *go = e1 + 1.02 * Q * 0x1p-23;
@@ -57,9 +62,9 @@ OZ2_HD inline void bound_deviation(int64_t kp, double *gu, double *go) {
 
 // The library's window [lo, hi] for the exact line maximum, given the
 // computed one r' (twice the deviations of (W)).
-OZ2_HD inline void bound_window(double rp, int64_t kp, double *lo, double *hi) {
+OZ2_HD inline void bound_window(double rp, int64_t kp, int parts, double *lo, double *hi) {
   double gu, go;
-  bound_deviation(kp, &gu, &go);
+  bound_deviation(kp, parts, &gu, &go);
   *lo = rp / (1.0 + 2.0 * go) * (1.0 - 0x1p-50);
   *hi = rp / (1.0 - 2.0 * gu) * (1.0 + 0x1p-50);
 }
@@ -76,10 +81,10 @@ OZ2_HD inline int exponent_rule(double x, double D) {
 
 // Scale exponents of the two ends of the window of a computed maximum rp > 0:
 // equal values settle the line, different ones send it to the exact fix-up.
-OZ2_HD inline void window_exponents(double rp, int64_t kp, double D, int *e_small,
-                                    int *e_large) {
+OZ2_HD inline void window_exponents(double rp, int64_t kp, int parts, double D,
+                                    int *e_small, int *e_large) {
   double lo, hi;
-  bound_window(rp, kp, &lo, &hi);
+  bound_window(rp, kp, parts, &lo, &hi);
   *e_small = exponent_rule(hi, D);
   *e_large = exponent_rule(lo, D);
 }

@@ -7,8 +7,10 @@
 //   B m_blk n_blk               ozaki2_set_blocking
 //   M mode                      ozaki2_set_mode
 //   S config                    ozaki2_set_schedule
+//   K parts                     ozaki2_set_split
 //   W m n k N                   ozaki2_workspace_bytes
 //   Y m n k N                   ozaki2_workspace_layout (status, 11 offsets, 4 pads)
+//   R m n k N                   ozaki2_workspace_parts (status, parts, bound parts)
 //   Q N count m n k ...         ozaki2_workspace_bytes_batched
 //   D ta tb m n k lda ldb ldc N ozaki2_dgemm on null pointers (argument checks;
 //                               valid arguments end at the device check)
@@ -28,7 +30,7 @@ hipError_t launch_quant_family(int, const Problem *, const Group *, hipStream_t)
 hipError_t launch_scale_family(int, const Problem *, const Group *, hipStream_t) {
   return hipSuccess;
 }
-hipError_t launch_gemm_family(int, const Problem *, const Group *, int, hipStream_t) {
+hipError_t launch_gemm_family(int, const Problem *, const Group *, hipStream_t) {
   return hipSuccess;
 }
 hipError_t launch_gemm_persistent(int, bool, const WorkList &, int64_t, hipStream_t) {
@@ -58,6 +60,9 @@ int main() {
     } else if (!strcmp(cmd, "S")) {
       if (scanf("%lld", &a[0]) != 1) return 2;
       printf("%d\n", ozaki2_set_schedule((int)a[0]));
+    } else if (!strcmp(cmd, "K")) {
+      if (scanf("%lld", &a[0]) != 1) return 2;
+      printf("%d\n", ozaki2_set_split((int)a[0]));
     } else if (!strcmp(cmd, "W")) {
       if (scanf("%lld %lld %lld %lld", &a[0], &a[1], &a[2], &a[3]) != 4) return 2;
       printf("%zu\n", ozaki2_workspace_bytes(a[0], a[1], a[2], (int)a[3]));
@@ -69,6 +74,11 @@ int main() {
       for (int q = 0; q < 11; ++q) printf(" %lld", r > 0 ? (long long)off[q] : 0ll);
       for (int q = 0; q < 4; ++q) printf(" %lld", r > 0 ? (long long)pads[q] : 0ll);
       printf("\n");
+    } else if (!strcmp(cmd, "R")) {
+      if (scanf("%lld %lld %lld %lld", &a[0], &a[1], &a[2], &a[3]) != 4) return 2;
+      int parts = 0, bparts = 0;
+      const int r = ozaki2_workspace_parts(a[0], a[1], a[2], (int)a[3], &parts, &bparts);
+      printf("%d %d %d\n", r, r == 0 ? parts : 0, r == 0 ? bparts : 0);
     } else if (!strcmp(cmd, "Q")) {
       long long N, cnt;
       if (scanf("%lld %lld", &N, &cnt) != 2 || cnt < 0 || cnt > 4096) return 2;

@@ -19,7 +19,7 @@ def device():
 class Run:
     """Output of one ozaki2_dgemm call."""
 
-    def __init__(self, status, C, ldc, m, n, ws=None, off=None, pads=None):
+    def __init__(self, status, C, ldc, m, n, ws=None, off=None, pads=None, parts=1):
         self.status = status
         self.Cbuf = C
         self.ldc = ldc
@@ -27,6 +27,7 @@ class Run:
         self.ws = ws
         self.off = off
         self.pads = pads
+        self.parts = parts  # k parts of the residue products: plane copies
         self.m, self.n = m, n
 
     # ---- workspace views (see ozaki2_workspace_layout) ----
@@ -62,11 +63,21 @@ class Run:
         return np.stack([self._unblock(self.ws[o + q * rows * kp:o + (q + 1) * rows * kp], rows, kp)
                          for q in range(M)])
 
-    def planes(self, N):
+    def planes(self, N, ps):
+        """C'_l for the moduli ps: the sum of the plane copies of the k parts
+        reduced to smod(., p_l)."""
         mp, np_ = self.pads["mp"], self.pads["np"]
         o = self.off[7]
-        return np.frombuffer(self.ws[o:o + 2 * N * mp * np_].tobytes(),
-                             dtype=np.int16).reshape(N, np_, mp)
+        size = 2 * N * mp * np_
+        copies = self.parts
+        assert copies >= 1 and o + copies * size <= len(self.ws)
+        parts = np.frombuffer(self.ws[o:o + copies * size].tobytes(),
+                              dtype=np.int16).reshape(copies, N, np_, mp).astype(np.int64)
+        total = parts.sum(axis=0)
+        if copies == 1:
+            return total
+        h = np.array([p // 2 for p in ps], dtype=np.int64)[:, None, None]
+        return (total + h) % np.array(ps, dtype=np.int64)[:, None, None] - h
 
 
 def run(opA, opB, N, transA="N", transB="N", alpha=1.0, beta=0.0, Cin=None,
@@ -114,13 +125,15 @@ def _run_list(tA, tB, tC, transA, transB, m, n, k, alpha, lda, ldb, beta, ldc, N
         oz.ozaki2_set_mode("accurate")
     off = pads = None
     wsh = None
+    parts = 1
     if keep_ws:
         # keep_ws == "lines": only the per-line vectors, which precede Abar
         off, pads = oz.ozaki2_workspace_layout(m, n, k, N)
+        parts = oz.ozaki2_workspace_parts(m, n, k, N)[0]
         shift = base - ws.data_ptr()
         upto = off[3] if keep_ws == "lines" else wbytes
         wsh = ws[shift:shift + upto].cpu().numpy()
-    return Run(st, tC.cpu().numpy(), ldc, m, n, wsh, off, pads)
+    return Run(st, tC.cpu().numpy(), ldc, m, n, wsh, off, pads, parts)
 
 
 def check_stages(r: Run, opA, opB, N, st=None, mode="accurate", moduli="hybrid"):
@@ -162,9 +175,23 @@ def check_stages(r: Run, opA, opB, N, st=None, mode="accurate", moduli="hybrid")
             assert not SB[sl, n:].any() and not SB[sl, :, k:].any(), f"B slice {sl} padding"
             sl += 1
     assert sl == r.pads["M"]
-    P = r.planes(N)
+    P = r.planes(N, [pm["p"] for pm in st["per_modulus"]])
     for l, plane in enumerate(st["planes"]):
         assert np.array_equal(P[l, :n, :m].T.astype(np.int64), plane), f"plane {l}"
+
+
+class split:
+    """Context: the calling thread's ozaki2_dgemm calls use `parts` k parts
+    for their residue products (0: the library's rule)."""
+
+    def __init__(self, parts):
+        self.parts = parts
+
+    def __enter__(self):
+        assert oz.ozaki2_set_split(self.parts) == 0
+
+    def __exit__(self, *exc):
+        oz.ozaki2_set_split(0)
 
 
 def same_bits(a, b):

@@ -46,6 +46,7 @@ def _commands(rng):
                 m, n, k = (rng.choice(sizes) for _ in range(3))
                 N = rng.choice([0, 1, 6, 7, 12, 13, 16, 33, 34])
                 cmds.append(("W", m, n, k, N))
+                cmds.append(("R", m, n, k, N))
             cmds.append(("B", 0, 0))
         for _ in range(25):
             m, n, k = (rng.choice(sizes) for _ in range(3))
@@ -65,6 +66,12 @@ def _commands(rng):
         cmds.append(("M", mode))
     for c in (-2, -1, 0, 5, 6, -1):
         cmds.append(("S", c))
+    for parts in (-1, 9, 3, 0):
+        cmds.append(("K", parts))
+        for _ in range(10):
+            m, n, k = (rng.choice(sizes) for _ in range(3))
+            cmds.append(("W", m, n, k, 12))
+            cmds.append(("R", m, n, k, 12))
     for _ in range(200):
         ta, tb = rng.choice("NnTtCcX"), rng.choice("NnTtCcQ")
         m, n, k = (rng.choice([-1, 0, 1, 4, 5, 300]) for _ in range(3))
@@ -85,6 +92,8 @@ def _library(cmd):
         return str(L.ozaki2_set_mode(args[0]))
     if op == "S":
         return str(L.ozaki2_set_schedule(args[0]))
+    if op == "K":
+        return str(L.ozaki2_set_split(args[0]))
     if op == "W":
         return str(L.ozaki2_workspace_bytes(*args))
     if op == "Y":
@@ -95,6 +104,11 @@ def _library(cmd):
         vals = [r] + [off[q] if r > 0 else 0 for q in range(11)] + \
             [pads[q] if r > 0 else 0 for q in range(4)]
         return " ".join(str(v) for v in vals)
+    if op == "R":
+        import ctypes
+        parts, bparts = ctypes.c_int(0), ctypes.c_int(0)
+        r = L.ozaki2_workspace_parts(*args, ctypes.byref(parts), ctypes.byref(bparts))
+        return f"{r} {parts.value if r == 0 else 0} {bparts.value if r == 0 else 0}"
     if op == "Q":
         N, cnt = args[0], args[1]
         v = args[2:]
@@ -133,5 +147,6 @@ def test_host_logic_sanitized_matches_library(host_api):
         oz.ozaki2_set_blocking(0, 0)
         oz.ozaki2_set_mode("accurate")
         oz.ozaki2_set_schedule(-1)
+        oz.ozaki2_set_split(0)
     bad = [(c, g, w) for c, g, w in zip(cmds, got, want) if g != w]
     assert not bad, bad[:5]

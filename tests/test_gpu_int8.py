@@ -10,7 +10,7 @@ from oracle import ozaki2_ref as ref
 from workloads import phi_matrix, normal_matrix, config_seed, batch_shapes, to_colmajor
 from workloads.reference import dd_dot_rows, normalised_error
 
-from gpu_util import run, check_stages, check_sampled, sample_lines
+from gpu_util import run, check_stages, check_sampled, sample_lines, split
 
 pytestmark = pytest.mark.gpu
 
@@ -87,7 +87,8 @@ def test_int8_extreme_sums_exact(k):
     A = np.full((64, k), a)
     B = np.full((k, 96), a)
     A[1::2] *= -1.0
-    r = run(A, B, 14, keep_ws=True, moduli=I8)
+    with split(1):   # the fewest k parts: accumulations of up to 2^15
+        r = run(A, B, 14, keep_ws=True, moduli=I8)
     assert r.status == 0
     Chat, st = ref.emulate(A, B, 14, keep_stages=True, moduli_set=I8)
     assert int(st["per_modulus"][0]["uA"][0, 0]) == -128
@@ -102,7 +103,7 @@ def test_int8_long_k():
     r = run(A, B, 15, keep_ws=True, moduli=I8)
     assert r.status == 0
     Chat, st = ref.emulate(A, B, 15, keep_stages=True, moduli_set=I8)
-    P = r.planes(15)
+    P = r.planes(15, [pm["p"] for pm in st["per_modulus"]])
     for l, plane in enumerate(st["planes"]):
         assert np.array_equal(P[l, :72, :40].T.astype(np.int64), plane), f"plane {l}"
     assert _same(r.C, Chat)

@@ -12,7 +12,7 @@ from oracle import ozaki2_ref as ref
 from workloads import phi_matrix, normal_matrix, config_seed, batch_shapes, to_colmajor
 from workloads.reference import dd_dot_rows, normalised_error
 
-from gpu_util import run, check_stages, check_sampled, sample_lines
+from gpu_util import run, check_stages, check_sampled, sample_lines, split
 
 pytestmark = pytest.mark.gpu
 
@@ -93,7 +93,8 @@ def test_karatsuba_extreme_digit_sums_exact():
     A = np.full((64, k), a)
     B = np.full((k, 96), b)
     A[1::2] *= -1.0
-    r = run(A, B, 5, keep_ws=True, moduli=KA)
+    with split(1):   # one k part: a single accumulation over all 2^15
+        r = run(A, B, 5, keep_ws=True, moduli=KA)
     assert r.status == 0
     Chat, st = ref.emulate(A, B, 5, keep_stages=True, moduli_set=KA)
     check_stages(r, A, B, 5, st, moduli=KA)
@@ -106,7 +107,7 @@ def test_karatsuba_long_k():
     r = run(A, B, 13, keep_ws=True, moduli=KA)
     assert r.status == 0
     Chat, st = ref.emulate(A, B, 13, keep_stages=True, moduli_set=KA)
-    P = r.planes(13)
+    P = r.planes(13, [pm["p"] for pm in st["per_modulus"]])
     for l, plane in enumerate(st["planes"]):
         assert np.array_equal(P[l, :72, :40].T.astype(np.int64), plane), f"plane {l}"
     assert _same(r.C, Chat)

@@ -13,7 +13,7 @@ from oracle import ozaki2_ref as ref
 from workloads import phi_matrix, integer_matrix, normal_matrix, config_seed
 from workloads.reference import dd_dot_rows, normalised_error
 
-from gpu_util import run, check_stages
+from gpu_util import run, check_stages, split
 
 pytestmark = pytest.mark.gpu
 
@@ -158,18 +158,52 @@ def test_integer_inputs_give_exact_product():
     assert np.array_equal(r.C, A @ B)      # |sums| < 2^53: the float64 matmul is exact
 
 
-@pytest.mark.parametrize("k", [32768, 40000, 65536, 65536 + 300])
-def test_long_k_chunks(k):
-    # beyond 2^15 the residue products are summed over several launches
-    print(f"long k={k}", flush=True)
+@pytest.mark.parametrize("k,parts", [(32768, 0), (40000, 0), (65536, 0), (65536 + 300, 0),
+                                     (65536 + 300, 4), (1 << 18, 0)])
+def test_long_k_chunks(k, parts):
+    # every k part of the residue products is at most 2^15 long (so at least
+    # ceil(k / 2^15) parts), each in its own copy of the planes that the CRT
+    # sums: the rule's 8 parts for this small output, a forced 4, and 8
+    # parts of exactly 2^15 at the largest supported k
+    print(f"long k={k} parts={parts}", flush=True)
     A, B = _inputs(40, 72, k, 1.0, 6000 + k)
-    r = run(A, B, 12, keep_ws=True)
+    with split(parts):
+        r = run(A, B, 12, keep_ws=True)
     assert r.status == 0
     Chat, st = ref.emulate(A, B, 12, keep_stages=True)
-    P = r.planes(12)
+    P = r.planes(12, [pm["p"] for pm in st["per_modulus"]])
     for l, plane in enumerate(st["planes"]):
         assert np.array_equal(P[l, :72, :40].T.astype(np.int64), plane), f"plane {l}"
     assert _same(r.C, Chat)
+
+
+def test_exact_fixups_many_lines_both_sides():
+    # rows of op(A) with n_i leading ones and columns of op(B) with n'_j
+    # leading ones: (Abar Bbar)_ij = 2^14 min(n_i, n'_j), so r_i = 2^14 n_i
+    # and c_j = 2^14 n'_j, spread over 64 consecutive counts around a
+    # threshold of the exponent rule.  The FP32 maxima are exact, yet every
+    # line within the window's width of the threshold (several dozen, on both
+    # sides, in groups of mixed sides) goes to the exact fix-up; k = 8448
+    # also leaves a 256-k tail of the fix-up's 512-k chunks and splits the
+    # bound product in 2 parts.
+    k, N = 8448, 12
+    P = ref.crt_weights([p for p, _, _ in ref.moduli_table(N)])[0]
+    # threshold r = (P - 1) / 2^(2e+1) with r / 2^14 in [2^11, 2^13)
+    e = ((P - 1).bit_length() - 1 - 14 - 13) // 2
+    nstar = (P - 1) / 2.0 ** (2 * e + 1) / 2.0 ** 14
+    assert 2 ** 11 <= nstar < 2 ** 13 - 64
+    counts = int(nstar) - 32 + np.arange(64)
+    A = (np.arange(k)[None, :] < counts[:, None]).astype(np.float64)
+    B = A.T.copy()
+    Chat, st = ref.emulate(A, B, N, keep_stages=True)
+    assert len(set(st["e"].tolist())) == 2 and len(set(st["f"].tolist())) == 2
+    r = run(A, B, N, keep_ws=True)
+    assert r.status == 0
+    print(f"many fix-ups: {r.fixups()} lines", flush=True)
+    assert r.fixups() >= 20
+    check_stages(r, A, B, N, st)
+    assert _same(r.C, Chat)
+    assert np.array_equal(r.C, np.minimum(counts[:, None], counts[None, :]).astype(np.float64))
 
 
 def _constant_case(k):
@@ -192,12 +226,14 @@ def _constant_case(k):
 
 def test_extreme_digit_sums_exact():
     # product sums of 256 k = 2^23 per FP8 product at k = 2^15 must be exact
+    # (one k part: a single accumulation over all 2^15)
     k = 32768
     a, b = _constant_case(k)
     A = np.full((64, k), a)
     B = np.full((k, 96), b)
     A[1::2] *= -1.0
-    r = run(A, B, 12, keep_ws=True)
+    with split(1):
+        r = run(A, B, 12, keep_ws=True)
     assert r.status == 0
     Chat, st = ref.emulate(A, B, 12, keep_stages=True)
     check_stages(r, A, B, 12, st)
@@ -236,7 +272,8 @@ def test_square_cross_sums_reach_2_24():
     b1, b2 = int(pm["dB"][0][0, 0]), int(pm["dB"][1][0, 0])
     assert (a1, a2, b1, b2) == (16, 16, 16, 16)
     assert (int(pm["dA"][0][1, 0]), int(pm["dA"][1][1, 0])) == (-16, -16)
-    r = run(A, B, 12, keep_ws=True)
+    with split(1):   # one k part: a single accumulation over all 2^15
+        r = run(A, B, 12, keep_ws=True)
     assert r.status == 0
     check_stages(r, A, B, 12, st)
     assert _same(r.C, Chat)
@@ -245,6 +282,9 @@ def test_square_cross_sums_reach_2_24():
 def _bound_case(kind):
     if kind == "spread":
         return _inputs(300, 280, 1000, 2.0, 7000)
+    if kind == "split":
+        # one output tile, k = 20000: the bound product runs as 4 k parts
+        return _inputs(200, 190, 20000, 2.0, 7003)
     if kind == "wide":
         return _inputs(256, 256, 4096, 4.0, 7001)
     # one dominant entry per 64-block and many small ones with awkward
@@ -256,27 +296,41 @@ def _bound_case(kind):
     return A, B
 
 
-@pytest.mark.parametrize("kind", ["spread", "wide", "dominant"])
+def _bound_parts(m, n, kp):
+    """k parts of a single call's bound product (fewer than 128 output tiles
+    and k of at least 8192: up to 16 parts of at least 4096, about 256
+    workgroups)."""
+    tiles = -(-m // 256) * -(-n // 256)
+    if tiles >= 128 or kp < 8192:
+        return 1
+    return min(-(-256 // tiles), kp // 4096, 16)
+
+
+@pytest.mark.parametrize("kind", ["spread", "wide", "dominant", "split"])
 def test_bound_maxima_within_window(kind):
     # the GPU's FP32 line maxima of the bound product against the exact ones:
     # within the deviations of the stated worst case the library's decision
     # window is derived from (oz2_window.h; the window itself is twice as
-    # wide on each side), and the measured hardware's narrower behaviour
+    # wide on each side), and the measured hardware's narrower behaviour;
+    # a split product adds its parts' sums, parts - 1 more roundings
     A, B = _bound_case(kind)
     r = run(A, B, 12, keep_ws=True)
     assert r.status == 0
     Chat, st = ref.emulate(A, B, 12, keep_stages=True)
+    check_stages(r, A, B, 12, st)
     assert _same(r.C, Chat)
     rA, rB = r.lines(8, np.uint32)
     kp = r.pads["kp"]
-    Q = (kp + 7) // 8
+    parts = _bound_parts(A.shape[0], B.shape[1], kp)
+    assert (parts > 1) == (kind == "split")
+    Q = (kp + 7) // 8 + parts - 1
     # worst case (W): under by at most 7 2^-13 + Q 2^-23, over by at most
     # 7 2^-13 + 1.02 Q 2^-23
     down = 7 * 2.0 ** -13 + Q * 2.0 ** -23
     up = 7 * 2.0 ** -13 + 1.02 * Q * 2.0 ** -23
     # measured behaviour: truncation inside groups of 8, at most one upward
-    # FP32 rounding per instruction of 64 k
-    hw_up = (kp / 64 + 2) * 2.0 ** -23
+    # FP32 rounding per instruction of 64 k (and per addition of a part)
+    hw_up = (kp / 64 + 2 + parts) * 2.0 ** -23
     worst_down = worst_up = 0.0
     for g32, exact18 in ((rA, st["r18"]), (rB, st["c18"])):
         g = g32.view(np.float32).astype(np.float64)

@@ -17,7 +17,14 @@ the fused multiply-adds there are exact, so they are modelled in integers):
 
 The largest magnitudes are covered exhaustively near the top of each range
 (where the estimate errors are largest) and by random samples elsewhere, for
-every modulus of all three lists up to N = 33."""
+every modulus of all three lists up to N = 33.
+
+And the residue pass of the quantization kernel (x mod p for the scaled
+integers): the FP64 step x - rint(x fl(1/p)) p for integers |x| < 2^53 and
+|x| = mant 2^10 < 2^63 near ties, then one FP32 step with no further
+correction for odd p (one for even p) must give the symmetric residue;
+likewise for the later multiplication by 2^t mod p; and the square digit
+rint(u fl(1/s)) must equal round(u / s) with ties away from zero for odd s."""
 import numpy as np
 import pytest
 
@@ -111,3 +118,69 @@ def test_int8_epilogue_remainder(p):
     # a later k chunk adds the stored plane value (|r| <= p/2) to a new one
     w = np.arange(-p, p + 1, dtype=np.int64)
     assert np.array_equal(_smod_i32(w, p), _sym(w, p))
+
+
+def _all_moduli():
+    out = set()
+    for name in ("hybrid", "karatsuba", "int8"):
+        for p, _, _ in ref.moduli_table(33, name):
+            out.add(p)
+    return sorted(out)
+
+
+def _fp32_step(f, p):
+    """f - rint(f fl(1/p)) p, then for even p +p/2 moved to -p/2."""
+    r = f - _est(f, p) * p
+    if p % 2 == 0:
+        r = np.where(r > p - 1 - p // 2, r - p, r)
+    return r
+
+
+def _near_ties(p, top, count):
+    """Integers below `top` in magnitude whose residue sits at or next to
+    +-p/2, the wrap point, or 0."""
+    q = RNG.integers(0, top // p - 1, count, dtype=np.int64)
+    off = np.array([-(p // 2) - 1, -(p // 2), -(p // 2) + 1, -1, 0, 1, p // 2 - 1, p // 2,
+                    p // 2 + 1, (p + 1) // 2], dtype=np.int64)
+    x = (q[:, None] * p + off[None, :]).ravel()
+    x = x[np.abs(x) < top]
+    return np.concatenate([x, -x])
+
+
+@pytest.mark.parametrize("p", _all_moduli())
+def test_residue_pass_reduction(p):
+    inv = np.float64(1.0) / np.float64(p)
+    # |x| < 2^53: any integer
+    small = np.concatenate([_near_ties(p, 2 ** 53, 1 << 14),
+                            RNG.integers(-2 ** 53 + 1, 2 ** 53, 1 << 15, dtype=np.int64),
+                            np.arange(-4 * p, 4 * p + 1, dtype=np.int64)])
+    # mant 2^10 with mant < 2^53: chosen near ties through mant = x / 2^10
+    mant = _near_ties(p, 2 ** 53, 1 << 14) // p * p
+    big = np.concatenate([mant * 1024, (mant + RNG.integers(0, p, mant.size)) * 1024,
+                          np.array([(2 ** 53 - 1) * 1024, -(2 ** 53 - 1) * 1024])])
+    for x in (small, big):
+        xf = x.astype(np.float64)
+        assert np.all(xf.astype(np.int64) == x)            # exact doubles
+        q = np.rint(xf * inv).astype(np.int64)
+        f = x - q * p                                       # the exact fma
+        assert np.all(np.abs(f) < 2 ** 15)
+        assert np.array_equal(_fp32_step(f, p), _sym(x, p))
+
+
+@pytest.mark.parametrize("p", _all_moduli())
+def test_residue_pass_power_step(p):
+    # u in the symmetric range times every tabulated 2^t mod p
+    u = np.arange(-(p // 2), p - p // 2, dtype=np.int64)
+    pw = np.unique([pow(2, t, p) for t in range(1, 192)]).astype(np.int64)
+    prod = (u[:, None] * pw[None, :]).ravel()
+    assert np.all(np.abs(prod) < 2 ** 20)
+    assert np.array_equal(_fp32_step(prod, p), _sym(prod, p))
+
+
+@pytest.mark.parametrize("p,s", [(p, s) for p, s in _moduli("square") if s % 2 == 1])
+def test_square_digit_odd_radix(p, s):
+    u = np.arange(-(p // 2), p - p // 2, dtype=np.int64)
+    got = np.rint(u.astype(np.float32) * _inv(s)).astype(np.int64)
+    want = np.sign(u) * ((2 * np.abs(u) + s) // (2 * s))    # ties away from zero
+    assert np.array_equal(got, want)
+    assert np.all(np.abs(got) <= 16) and np.all(np.abs(u - s * got) <= 16)

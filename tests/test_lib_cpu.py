@@ -61,6 +61,72 @@ def test_workspace_layout(shape, N):
     assert max(e for _, e in spans) <= total
 
 
+def _min_parts(k):
+    """Every k part is at most 2^15 long (one exact FP32 accumulation)."""
+    return -(-((max(k, 1) + 255) // 256 * 256) // 2 ** 15)
+
+
+def _rule_parts(m, n, k, N):
+    """k parts of a single call's residue products: from the minimum up to 8
+    parts (at least 2048 k each beyond the minimum), the fewest that
+    minimise sum over modulus kinds of
+    ceil(tiles * moduli of the kind * parts / 256) / parts."""
+    pad = lambda x: (max(x, 1) + 255) // 256 * 256
+    tiles = pad(m) // 256 * (pad(n) // 256)
+    kinds = [sum(1 for _, kd, _ in ref.hybrid_moduli(N) if kd == want)
+             for want in ("square", "karatsuba")]
+    lo = _min_parts(k)
+    best, best_cost = lo, None
+    for parts in range(lo, 9):
+        if parts > lo and pad(k) // parts < 2048:
+            break
+        cost = sum(-(-tiles * c * parts // 256) / parts for c in kinds if c)
+        if best_cost is None or cost < best_cost:
+            best, best_cost = parts, cost
+    return best
+
+
+def _bound_parts(m, n, k):
+    """k parts of a single call's bound product: with fewer than 128 output
+    tiles and k of at least 8192, up to 16 parts of at least 4096 k, about
+    one workgroup per CU (256)."""
+    pad = lambda x: (max(x, 1) + 255) // 256 * 256
+    tiles = pad(m) // 256 * (pad(n) // 256)
+    if tiles >= 128 or pad(k) < 8192:
+        return 1
+    return min(-(-256 // tiles), pad(k) // 4096, 16)
+
+
+@pytest.mark.parametrize("shape,N,want", [
+    ((8192, 8192, 8192), 12, 1), ((16384, 16384, 1024), 12, 1), ((4096, 4096, 4096), 12, 1),
+    ((1024, 1024, 65536), 12, 8), ((40, 72, 65536), 12, 8), ((300, 200, 4096), 12, 2),
+    ((300, 200, 2048), 12, 1), ((2048, 2048, 16384), 12, 2), ((1024, 1024, 65536), 7, 8),
+    ((8192, 8192, 65536), 12, 2), ((4096, 4096, 2 ** 18), 12, 8), ((4096, 4096, 40000), 12, 2),
+    ((1024, 1024, 65536), 1, 8), ((256, 256, 2 ** 18), 1, 8)])
+def test_single_call_split(shape, N, want):
+    m, n, k = shape
+    pad = lambda x: (x + 255) // 256 * 256
+    assert _rule_parts(m, n, k, N) == want
+    off, pads = oz.ozaki2_workspace_layout(m, n, k, N)
+    plane = 2 * N * pads["mp"] * pads["np"]
+    # the last region holds the plane copies, or the split bound product's
+    # part sums when those are larger (they are done before the planes)
+    bound = 4 * pads["mp"] * pads["np"] * _bound_parts(m, n, k)
+    size = lambda parts: off[7] + pad(max(plane * parts, bound))
+    assert oz.ozaki2_workspace_bytes(m, n, k, N) == size(want)
+    try:
+        for forced in (1, 3, 8):
+            assert oz.ozaki2_set_split(forced) == 0
+            got = max(_min_parts(k), min(forced, pads["kp"] // 256))
+            assert oz.ozaki2_workspace_bytes(m, n, k, N) == size(got)
+        # refused values leave the setting (8) unchanged
+        assert oz.ozaki2_set_split(9) == -1 and oz.ozaki2_set_split(-1) == -1
+        assert oz.ozaki2_workspace_bytes(m, n, k, N) == size(min(8, pads["kp"] // 256))
+    finally:
+        oz.ozaki2_set_split(0)
+    assert oz.ozaki2_workspace_bytes(m, n, k, N) == size(want)
+
+
 @pytest.mark.parametrize("entry", ["ozaki2_dgemm", "ozaki2_dgemm_noalloc"])
 def test_argument_errors(L, entry):
     d = 0  # no pointer is dereferenced on these paths
@@ -138,17 +204,18 @@ def test_batched_argument_errors_and_workspace():
                                   None, None, None, None, 12) == -2
     # empty outputs only: nothing to do, success without a device
     assert call(**one(m=[0], lda=[1], ldc=[1])) == 0
-    # workspace of a batch = sum over problems with a nonempty product; a
-    # problem of at most 4 output tiles of 256 x 256 and at least 512 padded k
-    # holds 3 more copies of its residue planes (split-K parts)
+    # workspace of a batch = sum over problems with a nonempty product of the
+    # layout up to the planes plus its plane copies: 4 for a problem of at
+    # most 4 output tiles of 256 x 256 and at least 512 padded k (split-K
+    # parts), else 1
     ms, ns, ks = [300, 0, 64, 1000, 2000], [200, 5, 64, 17, 1500], [700, 9, 0, 4096, 300]
     pad = lambda x: (x + 255) // 256 * 256
     want = 0
     for a, b, c in zip(ms, ns, ks):
         if a and b and c:
-            want += oz.ozaki2_workspace_bytes(a, b, c, 12)
-            if pad(a) * pad(b) <= 4 * 256 * 256 and pad(c) >= 512:
-                want += 3 * 2 * 12 * pad(a) * pad(b)
+            off, _ = oz.ozaki2_workspace_layout(a, b, c, 12)
+            copies = 4 if pad(a) * pad(b) <= 4 * 256 * 256 and pad(c) >= 512 else 1
+            want += off[7] + pad(2 * 12 * pad(a) * pad(b) * copies)
     assert oz.ozaki2_workspace_bytes_batched(ms, ns, ks, 12) == want
     assert oz.ozaki2_workspace_bytes_batched([1], [-1], [1], 12) == 0
 
@@ -256,12 +323,14 @@ def test_workspace_sizes_that_do_not_fit_are_refused():
     assert ws(256, 256, 2 ** 40 + 1, 12) == 0
     assert ws(2 ** 40, 2 ** 40, 256, 12) == 0      # planes: 24 x 2^80 bytes
     assert ws(2 ** 33, 2 ** 33, 256, 12) == 0      # planes: 24 x 2^66 bytes
-    big = ws(2 ** 29, 2 ** 29, 2 ** 18, 12)        # about 2^62.6 bytes: fits
+    big = ws(2 ** 29, 2 ** 29, 2 ** 15, 12)        # about 2^62.6 bytes: fits
     assert big > 2 ** 62
+    # k = 2^18 needs 8 k parts of 2^15, each with its own planes: 2^65.6 bytes
+    assert ws(2 ** 29, 2 ** 29, 2 ** 18, 12) == 0
     # the sum over a batch must not wrap either
     wb = oz.ozaki2_workspace_bytes_batched
-    assert wb([2 ** 29] * 2, [2 ** 29] * 2, [2 ** 18] * 2, 12) == 2 * big
-    assert wb([2 ** 29] * 3, [2 ** 29] * 3, [2 ** 18] * 3, 12) == 0
+    assert wb([2 ** 29] * 2, [2 ** 29] * 2, [2 ** 15] * 2, 12) == 2 * big
+    assert wb([2 ** 29] * 3, [2 ** 29] * 3, [2 ** 15] * 3, 12) == 0
     # ordinary sizes are unchanged: the layout of 8192^3 at N = 12
     assert ws(8192, 8192, 8192, 12) == 5772017920
 

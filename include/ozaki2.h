@@ -185,9 +185,11 @@ int ozaki2_moduli(int num_moduli, int32_t *p, int32_t *kinds);
  *          (accurate mode)
  *   off[9] uint32 [m_pad + n_pad]  line flags: 1 non-finite, 2 all zero, 4 exponent
  *          from an exact bound (fixed-up lines; every line in fast mode)
- *   off[10] uint32 [1 + m_pad + n_pad]  number of lines whose scale exponent
- *          the FP8 bound could not settle (recomputed exactly), then their
- *          indices (accurate mode)
+ *   off[10] uint32 [2 + m_pad + n_pad]  the lines whose scale exponent the FP8
+ *          bound could not settle (recomputed exactly; accurate mode): their
+ *          numbers among the rows of op(A) and the columns of op(B), then the
+ *          rows' line indices from entry 2 up and the columns' from the last
+ *          entry down
  * The layout, and so the workspace size, is the same in both modes.
  * Lines 0..m_pad-1 are rows of op(A), m_pad..m_pad+n_pad-1 columns of op(B).
  * Slices: modulus l contributes 2 (square) or 3 (Karatsuba) consecutive

@@ -218,7 +218,7 @@ bool make_layout(int64_t m, int64_t n, int64_t k, int N, Layout *L, int64_t mb =
   take(11, sizeof(uint32_t) * lines);          // flags
   take(12, sizeof(uint32_t) * lines);          // rmax
   take(13, sizeof(uint64_t) * lines);          // rfix
-  take(14, sizeof(uint32_t) * (lines + 1));    // amb
+  take(14, sizeof(uint32_t) * (lines + 2));    // amb
   L->off[15] = o;                              // end of the zeroed group
   take(0, sizeof(int32_t) * lines);            // shift
   take(1, sizeof(int32_t) * lines);            // E
@@ -758,6 +758,7 @@ void build_subbatch(const std::vector<Problem> &probs, ImageWriter &W, SubBatch 
         std::fill(seg.begin() + start[q], seg.begin() + start[q + 1], q);
       L.off_seg = W.put(seg.data(), sizeof(int32_t) * seg.size());
     }
+    L.G.tab = probs[0].tab;
     L.G.nseg = np;
     L.G.total = start[np];
     sb->launches.push_back(L);

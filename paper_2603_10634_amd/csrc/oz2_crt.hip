@@ -96,8 +96,8 @@ __global__ __launch_bounds__(256) void k_crt(Problem P1, Group G) {
   const int64_t i = (local % nbx) * 64 + (threadIdx.x & 63);
   const int64_t j = (local / nbx) * 4 + (threadIdx.x >> 6);
   if (j >= P.g.n) return;
-  crt_entry<L, NF>(P.w.planes, P.w.shift, P.w.flags, P.tab, P.g.N, P.g.m, P.g.mp, P.g.np,
-                   P.w.lineB, P.alpha, P.beta, P.C, P.ldc, i, j, P.parts);
+  crt_entry<L, NF>(P.w.planes, P.w.shift, P.w.flags, tables_of<GROUPED>(P1, G), P.g.N, P.g.m,
+                   P.g.mp, P.g.np, P.w.lineB, P.alpha, P.beta, P.C, P.ldc, i, j, P.parts);
 }
 
 __global__ void k_scal(int64_t m, double beta, double *__restrict__ C, int64_t ldc) {

@@ -838,6 +838,7 @@ __device__ __forceinline__ void bound_maxima(const v16f (&acc)[4][TB<NW_BOUND>()
 // so that each access of a wave covers 256 consecutive bytes.
 constexpr int kBoundThreads = 64 * NW_BOUND;
 constexpr int kBoundVals = 4 * TB<NW_BOUND>() * 16;
+static_assert(4 * TB<NW_BOUND>() == 16, "k_bound_reduce's grid assumes 16 MFMA blocks per wave");
 
 __device__ __forceinline__ int64_t bound_part_at(int64_t part, int64_t tiles, int64_t tile,
                                                  int q, int tid) {
@@ -905,36 +906,54 @@ __global__ __launch_bounds__(64 * NW_BOUND, 1) void k_bound_gemm(Problem P1, Gro
   }
 }
 
-// Split bound product: per tile, the FP32 sum of its parts in part order,
-// then the line maxima.
-__global__ __launch_bounds__(64 * NW_BOUND, 1) void k_bound_reduce(Problem P) {
-  constexpr int TBW = TB<NW_BOUND>();
+// Split bound product: per tile and MFMA block (tj, ti) of every wave, the
+// FP32 sum of its parts in part order, then that block's line maxima.  Block
+// z of the launch takes tile z / (4 TBW) and (tj, ti) from z mod (4 TBW), so
+// that the launch has 4 TBW workgroups per tile.
+__global__ __launch_bounds__(64 * NW_BOUND) void k_bound_reduce(Problem P) {
+  constexpr int TBW = TB<NW_BOUND>(), NWW = NW_BOUND;
   const Dims d = family_dims(kFamBgemm, P);
   const int64_t tiles = d.x * d.y;
-  const int64_t tile = blockIdx.x, parts = P.bparts;
+  const int64_t tile = blockIdx.x / (4 * TBW);
+  const int sub = (int)(blockIdx.x % (4 * TBW));
+  const int tj = sub / TBW, ti = sub % TBW;
+  const int parts = P.bparts;
   const int tid = threadIdx.x;
-  const float *src = P.w.bpart + bound_part_at(0, tiles, tile, 0, tid);
+  const float *src = P.w.bpart + bound_part_at(0, tiles, tile, sub * 16, tid);
   const int64_t part_stride = tiles * kBoundVals * kBoundThreads;
-  v16f acc[4][TBW];
+  float acc[16];
 #pragma unroll
-  for (int tj = 0; tj < 4; ++tj)
-#pragma unroll
-    for (int ti = 0; ti < TBW; ++ti)
-#pragma unroll
-      for (int v = 0; v < 16; ++v)
-        acc[tj][ti][v] = src[(int64_t)((tj * TBW + ti) * 16 + v) * kBoundThreads];
-  for (int64_t q = 1; q < parts; ++q) {
+  for (int v = 0; v < 16; ++v) acc[v] = src[v * kBoundThreads];
+#pragma unroll 4
+  for (int q = 1; q < parts; ++q) {
     const float *s = src + q * part_stride;
+    float x[16];
 #pragma unroll
-    for (int tj = 0; tj < 4; ++tj)
+    for (int v = 0; v < 16; ++v) x[v] = s[v * kBoundThreads];
 #pragma unroll
-      for (int ti = 0; ti < TBW; ++ti)
-#pragma unroll
-        for (int v = 0; v < 16; ++v)
-          acc[tj][ti][v] += s[(int64_t)((tj * TBW + ti) * 16 + v) * kBoundThreads];
+    for (int v = 0; v < 16; ++v) acc[v] += x[v];
   }
-  uint32_t *rmax = P.w.rmax;
-  bound_maxima(acc, rmax, rmax + P.g.mp, (tile % d.x) * TIW, (tile / d.x) * TJ, tid);
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wj = wave / (NWW / 2), wi = wave % (NWW / 2);
+  const int64_t i0 = (tile % d.x) * TIW, j0 = (tile / d.x) * TJ;
+  uint32_t *rmaxA = P.w.rmax, *rmaxB = P.w.rmax + P.g.mp;
+  // row maxima (rows i of this block: one per lane % 32)
+  float m = 0.0f;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) m = fmaxf(m, acc[v]);
+  m = fmaxf(m, __shfl_xor(m, 32, 64));
+  if (lane < 32) atomicMax(&rmaxA[i0 + wi * 32 * TBW + ti * 32 + lane], __float_as_uint(m));
+  // column maxima (columns j: one per value v and lane / 32)
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    float c = acc[v];
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) c = fmaxf(c, __shfl_xor(c, off, 64));
+    if ((lane & 31) == 0) {
+      const int64_t j = j0 + wj * 128 + tj * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+      atomicMax(&rmaxB[j], __float_as_uint(c));
+    }
+  }
 }
 
 }  // namespace

@@ -74,7 +74,9 @@ struct Work {
   uint32_t *flags;    // [mp + np]
   uint64_t *rfix;     // [mp + np] 2^18 x the exact line bound: bound-product maxima of
                       // fixed-up lines (accurate mode), squared norms (fast mode)
-  uint32_t *amb;      // [1 + mp + np] count, then the lines needing a fix-up
+  uint32_t *amb;      // [2 + mp + np] the lines needing a fix-up: counts of rows of op(A)
+                      // and of columns of op(B), then the rows' line indices from
+                      // amb[2] up and the columns' from amb[1 + mp + np] down
   uint8_t *Abar, *Bbar;
   uint8_t *Asl, *Bsl;
   int16_t *planes;
@@ -229,14 +231,14 @@ __host__ __device__ inline Dims family_dims(int fam, const Problem &P) {
       return {g.np / kQL, g.kp / kQK, 1};
     case kFamBgemm:
       return {g.mp / kGemmTIW, g.np / kGemmTJ, P.bparts};
-    case kFamBreduce:
-      return {g.mp / kGemmTIW, g.np / kGemmTJ, P.bparts > 1 ? 1 : 0};
+    case kFamBreduce:  // (the wide tile's 16 MFMA blocks per wave) per tile
+      return {16 * (g.mp / kGemmTIW) * (g.np / kGemmTJ), 1, P.bparts > 1 ? 1 : 0};
     case kFamDecide:
     case kFamFinal:
       return {(g.mp + g.np + 255) / 256, 1, 1};
-    case kFamFixup: {
-      int64_t b = (g.mp + g.np) / 64;
-      return {b < 8 ? 8 : (b > 512 ? 512 : b), 1, 1};
+    case kFamFixup: {  // one-wave workgroups walking the flagged lines' items
+      int64_t b = (g.mp + g.np) / 8;
+      return {b < 8 ? 8 : (b > 4096 ? 4096 : b), 1, 1};
     }
     case kFamGemmSq:
     case kFamGemmKa:
@@ -275,9 +277,17 @@ struct Group {
   const int32_t *order;
   const int64_t *start;
   const int32_t *seg;   // segment of every block (null: found by binary search in start)
+  const Tables *tab;    // the device tables, the same for every problem of a batch: read
+                        // through this kernel argument, they load with scalar loads
   int nseg;
   int64_t total;
 };
+
+// The device tables of the problem a block works on (see Group::tab).
+template <bool GROUPED>
+__host__ __device__ inline const Tables *tables_of(const Problem &P1, const Group &G) {
+  return GROUPED ? G.tab : P1.tab;
+}
 
 #if defined(__HIPCC__)
 // Segment holding block b: the last q with start[q] <= b (start is sorted;

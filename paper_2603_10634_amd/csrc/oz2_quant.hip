@@ -421,7 +421,8 @@ __global__ __launch_bounds__(256) void k_residues(Problem P1, Group G) {
   const Dims d = family_dims(SIDE == 0 ? kFamResA : kFamResB, P);
   const int64_t bx = local % d.x, by = local / d.x;
   residues_tile(op, P.g.kp, SIDE == 0 ? P.g.mp : P.g.np, bx * kQL, by * kQK, P.w.shift + base,
-                P.tab, P.g.N, P.g.nsq, P.g.nka, SIDE == 0 ? P.w.Asl : P.w.Bsl, tile);
+                tables_of<GROUPED>(P1, G), P.g.N, P.g.nsq, P.g.nka,
+                SIDE == 0 ? P.w.Asl : P.w.Bsl, tile);
 }
 
 }  // namespace

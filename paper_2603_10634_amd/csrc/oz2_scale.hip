@@ -45,11 +45,15 @@ __global__ __launch_bounds__(256) void k_scale_decide(Problem P1, Group G) {
   int ev = 0;
   if (r > 0.0f && !(w.flags[L] & kZeroLine)) {
     int e_small, e_large;
-    window_exponents((double)r, P.g.kp, P.bparts, P.tab->D, &e_small, &e_large);
+    window_exponents((double)r, P.g.kp, P.bparts, tables_of<GROUPED>(P1, G)->D, &e_small,
+                     &e_large);
     ev = e_small;
     if (e_small != e_large) {
-      const uint32_t slot = atomicAdd(&w.amb[0], 1u);
-      w.amb[1 + slot] = (uint32_t)L;
+      // rows of op(A) from the front of the list, columns of op(B) from the back
+      if (L < P.g.mp)
+        w.amb[2 + atomicAdd(&w.amb[0], 1u)] = (uint32_t)L;
+      else
+        w.amb[1 + lines - atomicAdd(&w.amb[1], 1u)] = (uint32_t)L;
       w.flags[L] |= kFixup;
     }
   }
@@ -60,15 +64,87 @@ __global__ __launch_bounds__(256) void k_scale_decide(Problem P1, Group G) {
 // factors multiples of 2^-9 up to 256, q9 = 2^9 x (an entry of Abar or Bbar)
 // is an integer below 2^18 and every partial sum of q9 products is an integer
 // below 2^52 (k <= 2^18), so FP64 fused multiply-adds sum them exactly, in any
-// order.  The flagged lines are taken in groups of kFixG consecutive list
-// entries; an item is (side, group, chunk of kFixJ partner lines): the group's
-// lines of that side (rows of op(A), or columns of op(B)), decoded into LDS
-// kFixKC k at a time, against one partner line per thread; the block's
-// maximum per line goes to rfix (2^18 x the exact maximum) by an atomic
-// maximum.  Each of the problem's nblk workgroups walks items blk, blk + nblk..
-constexpr int kFixG = 8;
-constexpr int kFixKC = 512;
-constexpr int kFixJ = 256;
+// order.  The flagged lines of each side (rows of op(A), columns of op(B):
+// the two ends of the list) are taken in groups of kFixG; an item is (group,
+// chunk of kFixJ partner lines): the group's lines, decoded into LDS kFixKC k
+// at a time, against one partner line per thread; the block's maximum per
+// line goes to rfix (2^18 x the exact maximum) by an atomic maximum.  Each of
+// the problem's nblk workgroups walks items blk, blk + nblk, ...
+constexpr int kFixG = 2;   // few lines per item: many items, so many waves per SIMD
+constexpr int kFixJ = 64;  // one wave per workgroup: small LDS, many workgroups per CU
+constexpr int kFixKC = 256;
+
+// One item with the group's first G lines (L[q] < 0: none): acc[q] = the exact
+// bound product of line L[q] with partner line j (one per thread), k in
+// chunks of kFixKC decoded into LDS; the partner's bytes of the next 64 k are
+// loaded while the current 64 are summed.
+template <int G>
+__device__ __forceinline__ void fixup_item(const uint8_t *__restrict__ own_op, int64_t nown,
+                                           int64_t base, const uint8_t *__restrict__ part,
+                                           int64_t npart, int64_t kp, const int64_t (&L)[kFixG],
+                                           int64_t j, double (*own)[kFixKC],
+                                           const double *q9tab, uint64_t *__restrict__ rfix) {
+  const int t = threadIdx.x;
+  double acc[G];
+#pragma unroll
+  for (int q = 0; q < G; ++q) acc[q] = 0.0;
+  const bool jv = j < npart;
+  for (int64_t k0 = 0; k0 < kp; k0 += kFixKC) {  // kp is a multiple of kFixKC
+    __syncthreads();  // the previous chunk's (or item's) readers are done
+#pragma unroll
+    for (int v = 0; v < G * kFixKC / kFixJ; ++v) {
+      const int q = v / (kFixKC / kFixJ);
+      const int h = (v % (kFixKC / kFixJ)) * kFixJ + t;
+      double x = 0.0;
+      if (L[q] >= 0) x = q9tab[own_op[kblocked(L[q] - base, k0 + h, nown)] & 0x7Fu];
+      own[q][h] = x;
+    }
+    __syncthreads();
+    if (jv) {
+      // the partner's 64 bytes of each 64-k block are contiguous, blocks
+      // 64 npart bytes apart
+      const uint8_t *pj = part + kblocked(j, k0, npart);
+      const int64_t step = npart * 64;
+      constexpr int nb = kFixKC / 64;
+      uint32_t cur[16];
+#pragma unroll
+      for (int w = 0; w < 16; ++w) cur[w] = *(const uint32_t *)(pj + 4 * w);
+      for (int b = 0; b < nb; ++b) {
+        uint32_t nxt[16];
+        if (b + 1 < nb) {
+#pragma unroll
+          for (int w = 0; w < 16; ++w) nxt[w] = *(const uint32_t *)(pj + (b + 1) * step + 4 * w);
+        }
+#pragma unroll 2
+        for (int w = 0; w < 16; ++w) {
+          const uint32_t word = cur[w];
+#pragma unroll
+          for (int z = 0; z < 4; ++z) {
+            const double bv = q9tab[(word >> (8 * z)) & 0x7Fu];
+            const int h = b * 64 + w * 4 + z;
+#pragma unroll
+            for (int q = 0; q < G; ++q) acc[q] = fma(own[q][h], bv, acc[q]);
+          }
+        }
+        if (b + 1 < nb) {
+#pragma unroll
+          for (int w = 0; w < 16; ++w) cur[w] = nxt[w];
+        }
+      }
+    }
+  }
+  // maxima per line over the wave's partners: exact integers below 2^52
+#pragma unroll
+  for (int q = 0; q < G; ++q) {
+    if (L[q] < 0) continue;
+    uint64_t m = jv ? (uint64_t)acc[q] : 0ull;
+    for (int off = 32; off > 0; off >>= 1) {
+      const uint64_t o = __shfl_xor(m, off, 64);
+      m = o > m ? o : m;
+    }
+    if (t == 0 && m) atomicMax((unsigned long long *)&rfix[L[q]], (unsigned long long)m);
+  }
+}
 
 __device__ __forceinline__ void scale_fixup(const uint8_t *__restrict__ Abar,
                                             const uint8_t *__restrict__ Bbar, int64_t mp,
@@ -79,75 +155,42 @@ __device__ __forceinline__ void scale_fixup(const uint8_t *__restrict__ Abar,
   __shared__ double own[kFixG][kFixKC];
   __shared__ double q9tab[128];
   const int t = threadIdx.x;
-  if (t < 128) q9tab[t] = (double)e4m3_q9((uint32_t)t);
-  const int64_t count = amb[0];
-  const int64_t groups = (count + kFixG - 1) / kFixG;
-  const int64_t chunks = ((mp > np ? mp : np) + kFixJ - 1) / kFixJ;
-  const int64_t items = 2 * groups * chunks;
+  for (int c = t; c < 128; c += kFixJ) q9tab[c] = (double)e4m3_q9((uint32_t)c);
+  const int64_t lines = mp + np;
+  const int64_t countA = amb[0], countB = amb[1];
+  const int64_t groupsA = (countA + kFixG - 1) / kFixG, groupsB = (countB + kFixG - 1) / kFixG;
+  // partners: the columns of op(B) for rows of op(A), and the other way
+  const int64_t chunksA = (np + kFixJ - 1) / kFixJ, chunksB = (mp + kFixJ - 1) / kFixJ;
+  const int64_t itemsA = groupsA * chunksA, items = itemsA + groupsB * chunksB;
   for (int64_t it = blk; it < items; it += nblk) {
-    const int side = (int)(it & 1);  // 0: rows of op(A) against the columns of op(B)
-    const int64_t g = (it >> 1) % groups, c = (it >> 1) / groups;
+    const int side = it < itemsA ? 0 : 1;  // 0: rows of op(A) against the columns of op(B)
+    const int64_t r = side == 0 ? it : it - itemsA;
+    const int64_t groups = side == 0 ? groupsA : groupsB;
+    const int64_t g = r % groups, c = r / groups;
+    const int64_t count = side == 0 ? countA : countB;
     const uint8_t *own_op = side == 0 ? Abar : Bbar;
     const uint8_t *part = side == 0 ? Bbar : Abar;
     const int64_t nown = side == 0 ? mp : np, npart = side == 0 ? np : mp;
     const int64_t base = side == 0 ? 0 : mp;  // line index of the side's first line
-    // the group's lines of this side (-1: none), the same in every thread
+    // the group's lines (-1: none), the same in every thread; groups are
+    // filled from the front, so the first n are valid
     int64_t L[kFixG];
-    bool any = false;
 #pragma unroll
     for (int q = 0; q < kFixG; ++q) {
       const int64_t e = g * kFixG + q;
-      const int64_t l = e < count ? (int64_t)amb[1 + e] : -1;
-      L[q] = l >= 0 && (l < mp) == (side == 0) ? l : -1;
-      any |= L[q] >= 0;
+      L[q] = e < count ? (int64_t)amb[side == 0 ? 2 + e : 1 + lines - e] : -1;
     }
-    if (!any || c * kFixJ >= npart) continue;
+    const int64_t n = count - g * kFixG;
     const int64_t j = c * kFixJ + t;
-    double acc[kFixG];
-#pragma unroll
-    for (int q = 0; q < kFixG; ++q) acc[q] = 0.0;
-    for (int64_t k0 = 0; k0 < kp; k0 += kFixKC) {
-      const int kc = kp - k0 < kFixKC ? (int)(kp - k0) : kFixKC;  // 256 or 512
-      __syncthreads();  // the previous chunk's (or item's) readers are done
-#pragma unroll
-      for (int v = 0; v < kFixG * kFixKC / kFixJ; ++v) {
-        const int q = v / (kFixKC / kFixJ);
-        const int h = (v % (kFixKC / kFixJ)) * kFixJ + t;
-        double x = 0.0;
-        if (L[q] >= 0 && h < kc)
-          x = q9tab[own_op[kblocked(L[q] - base, k0 + h, nown)] & 0x7Fu];
-        own[q][h] = x;
-      }
-      __syncthreads();
-      if (j < npart) {
-        for (int h = 0; h < kc; h += 8) {
-          // 8 bytes at h (h % 8 == 0) sit in one 64-byte piece of the line
-          const uint64_t b8 = *(const uint64_t *)(part + kblocked(j, k0 + h, npart));
-#pragma unroll
-          for (int z = 0; z < 8; ++z) {
-            const double b = q9tab[(uint32_t)(b8 >> (8 * z)) & 0x7Fu];
-#pragma unroll
-            for (int q = 0; q < kFixG; ++q) acc[q] = fma(own[q][h + z], b, acc[q]);
-          }
-        }
-      }
-    }
-    // block maxima per line: exact integers below 2^52
-#pragma unroll
-    for (int q = 0; q < kFixG; ++q) {
-      if (L[q] < 0) continue;
-      uint64_t m = (uint64_t)acc[q];
-      for (int off = 32; off > 0; off >>= 1) {
-        const uint64_t o = __shfl_xor(m, off, 64);
-        m = o > m ? o : m;
-      }
-      if ((t & 63) == 0 && m) atomicMax((unsigned long long *)&rfix[L[q]], (unsigned long long)m);
-    }
+    if (n > 1)
+      fixup_item<kFixG>(own_op, nown, base, part, npart, kp, L, j, own, q9tab, rfix);
+    else
+      fixup_item<1>(own_op, nown, base, part, npart, kp, L, j, own, q9tab, rfix);
   }
 }
 
 template <bool GROUPED>
-__global__ __launch_bounds__(256) void k_scale_fixup(Problem P1, Group G) {
+__global__ __launch_bounds__(kFixJ) void k_scale_fixup(Problem P1, Group G) {
   int64_t local;
   const Problem &P = *locate<GROUPED>(P1, G, blockIdx.x, local);
   const Dims d = family_dims(kFamFixup, P);
@@ -164,7 +207,7 @@ __global__ __launch_bounds__(256) void k_scale_finalize(Problem P1, Group G) {
   int ev = w.e[L];
   if (w.flags[L] & kFixup) {
     const uint64_t r18 = w.rfix[L];  // 2^18 x the exact line maximum, < 2^53
-    ev = r18 ? exponent_rule(ldexp((double)r18, -18), P.tab->D) : 0;
+    ev = r18 ? exponent_rule(ldexp((double)r18, -18), tables_of<GROUPED>(P1, G)->D) : 0;
     w.e[L] = ev;
   }
   w.shift[L] = 7 - w.E[L] + ev;
@@ -185,7 +228,7 @@ hipError_t launch_scale_family(int fam, const Problem *P, const Group *G, hipStr
   const int64_t blocks = grouped ? G->total : family_blocks(fam, *P);
   if (blocks <= 0) return hipSuccess;
   if (blocks > 0x7FFFFFFFll) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)blocks), blk(256);
+  const dim3 grid((unsigned)blocks), blk(fam == kFamFixup ? kFixJ : 256);
 #define OZ2_S(KER)                                             \
   if (grouped)                                                 \
     hipLaunchKernelGGL((KER<true>), grid, blk, 0, st, p1, g1); \

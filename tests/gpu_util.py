@@ -42,7 +42,7 @@ class Run:
 
     def fixups(self):
         """Number of lines whose scale exponent was settled by the exact fix-up."""
-        return int(self._vec(10, np.uint32, 1)[0])
+        return int(self._vec(10, np.uint32, 2).sum())
 
     @staticmethod
     def _unblock(buf, rows, kp):

@@ -184,3 +184,4 @@ def test_square_digit_odd_radix(p, s):
     want = np.sign(u) * ((2 * np.abs(u) + s) // (2 * s))    # ties away from zero
     assert np.array_equal(got, want)
     assert np.all(np.abs(got) <= 16) and np.all(np.abs(u - s * got) <= 16)
+

@@ -262,7 +262,7 @@ __device__ __forceinline__ void dma_part_w(const uint8_t *gB, const uint8_t *gA,
 //     slot j % SW) and the reads of stage j + 1's A-side fragments and first
 //     B-side block row between them, so that LDS latency and the barrier hide
 //     behind MFMAs already in registers.
-template <int NW, class ACC>
+template <int NW, bool STEADY, class ACC>
 __device__ __forceinline__ void stage_iter_w(int j, int nk, const uint8_t *gB, const uint8_t *gA,
                                              const DmaOffsets &d, int64_t kbeg,
                                              const uint8_t *lds, uint32_t ring,
@@ -273,9 +273,10 @@ __device__ __forceinline__ void stage_iter_w(int j, int nk, const uint8_t *gB, c
   const int wave = tid >> 6;
   const int wj = wave / (NWW / 2), wi = wave % (NWW / 2);
   const uint8_t *cur = lds + (j % SW) * STAGEW;
-  const bool ld_prev = j + SW - 1 < nk;
-  const bool ld_next = j + SW < nk;
-  const bool rd_next = j + 1 < nk;
+  // STEADY: j + SW < nk, so every load and read below exists
+  const bool ld_prev = STEADY || j + SW - 1 < nk;
+  const bool ld_next = STEADY || j + SW < nk;
+  const bool rd_next = STEADY || j + 1 < nk;
   const int64_t kofs_prev = kbeg + (int64_t)(j + SW - 1) * BK;
   const uint32_t slot_prev = ring + ((j + SW - 1) % SW) * STAGEW;
 #pragma unroll
@@ -295,7 +296,10 @@ __device__ __forceinline__ void stage_iter_w(int j, int nk, const uint8_t *gB, c
     }
   }
   wait_lgkm0();
-  if (rd_next) wait_stages<L, SW - 2>(nk - 2 - j);
+  if (STEADY)
+    wait_vm<(SW - 2) * L>();
+  else if (rd_next)
+    wait_stages<L, SW - 2>(nk - 2 - j);
   __builtin_amdgcn_s_barrier();
   __builtin_amdgcn_sched_barrier(0);
   const uint8_t *nxt = lds + ((j + 1) % SW) * STAGEW;
@@ -347,10 +351,16 @@ __device__ __forceinline__ void kloop_w(const uint8_t *gB, const uint8_t *gA, in
 #pragma unroll
   for (int ti = 0; ti < TBW; ++ti) fa0[ti] = lds_frag(lds + BSZ, wi * 32 * TBW + ti * 32, tid);
   fb[0] = lds_frag(lds, wj * 128, tid);
-  // nk is a multiple of 4 (k is padded to 256): two stages per trip, no tail
-  for (int j = 0; j < nk; j += 2) {
-    stage_iter_w<NW>(j, nk, gB, gA, d, kbeg, lds, ring, fa0, fa1, fb, acc, tid);
-    stage_iter_w<NW>(j + 1, nk, gB, gA, d, kbeg, lds, ring, fa1, fa0, fb, acc, tid);
+  // nk is a multiple of 4 (k is padded to 256): two stages per trip, no tail;
+  // the trips whose stages all load a later stage run without the checks
+  int j = 0;
+  for (; j + 1 + SW < nk; j += 2) {
+    stage_iter_w<NW, true>(j, nk, gB, gA, d, kbeg, lds, ring, fa0, fa1, fb, acc, tid);
+    stage_iter_w<NW, true>(j + 1, nk, gB, gA, d, kbeg, lds, ring, fa1, fa0, fb, acc, tid);
+  }
+  for (; j < nk; j += 2) {
+    stage_iter_w<NW, false>(j, nk, gB, gA, d, kbeg, lds, ring, fa0, fa1, fb, acc, tid);
+    stage_iter_w<NW, false>(j + 1, nk, gB, gA, d, kbeg, lds, ring, fa1, fa0, fb, acc, tid);
   }
   __builtin_amdgcn_s_barrier();
 }

@@ -262,8 +262,9 @@ __device__ __forceinline__ void dma_part_w(const uint8_t *gB, const uint8_t *gA,
 //     slot j % SW) and the reads of stage j + 1's A-side fragments and first
 //     B-side block row between them, so that LDS latency and the barrier hide
 //     behind MFMAs already in registers.
-template <int NW, bool STEADY, class ACC>
+template <int NW, bool STEADY, bool CHAIN, class ACC>
 __device__ __forceinline__ void stage_iter_w(int j, int nk, const uint8_t *gB, const uint8_t *gA,
+                                             const uint8_t *gBn, const uint8_t *gAn,
                                              const DmaOffsets &d, int64_t kbeg,
                                              const uint8_t *lds, uint32_t ring,
                                              const v8i (&fa)[TB<NW>()], v8i (&fan)[TB<NW>()],
@@ -273,11 +274,19 @@ __device__ __forceinline__ void stage_iter_w(int j, int nk, const uint8_t *gB, c
   const int wave = tid >> 6;
   const int wj = wave / (NWW / 2), wi = wave % (NWW / 2);
   const uint8_t *cur = lds + (j % SW) * STAGEW;
-  // STEADY: j + SW < nk, so every load and read below exists
-  const bool ld_prev = STEADY || j + SW - 1 < nk;
-  const bool ld_next = STEADY || j + SW < nk;
+  // STEADY: j + SW < nk, so every load and read below exists.  CHAIN: the
+  // loads of stages past nk - 1 fetch the next pass's first stages (from gBn,
+  // gAn; nk is a multiple of SW, so into the slots its own prologue would
+  // use), exactly as a steady stage would, so the waits are the steady ones
+  const bool ld_prev = STEADY || CHAIN || j + SW - 1 < nk;
+  const bool ld_next = STEADY || CHAIN || j + SW < nk;
   const bool rd_next = STEADY || j + 1 < nk;
-  const int64_t kofs_prev = kbeg + (int64_t)(j + SW - 1) * BK;
+  const bool prev_here = STEADY || j + SW - 1 < nk;
+  const bool next_here = STEADY || j + SW < nk;
+  const uint8_t *gBp = prev_here ? gB : gBn, *gAp = prev_here ? gA : gAn;
+  const uint8_t *gBx = next_here ? gB : gBn, *gAx = next_here ? gA : gAn;
+  const int64_t kofs_prev = kbeg + (int64_t)(j + SW - 1 - (prev_here ? 0 : nk)) * BK;
+  const int64_t kofs_next = kbeg + (int64_t)(j + SW - (next_here ? 0 : nk)) * BK;
   const uint32_t slot_prev = ring + ((j + SW - 1) % SW) * STAGEW;
 #pragma unroll
   for (int tj = 0; tj < 3; ++tj) {
@@ -288,15 +297,15 @@ __device__ __forceinline__ void stage_iter_w(int j, int nk, const uint8_t *gB, c
       acc[tj][ti] = mma(fb[tj], fa[ti], acc[tj][ti]);
       __builtin_amdgcn_sched_barrier(0);
       if (ti == 0 && ld_prev) {
-        if (tj == 0) dma_part_w<NW, 1>(gB, gA, d, kofs_prev, slot_prev);
-        if (tj == 1) dma_part_w<NW, 2>(gB, gA, d, kofs_prev, slot_prev);
-        if (tj == 2) dma_part_w<NW, 3>(gB, gA, d, kofs_prev, slot_prev);
+        if (tj == 0) dma_part_w<NW, 1>(gBp, gAp, d, kofs_prev, slot_prev);
+        if (tj == 1) dma_part_w<NW, 2>(gBp, gAp, d, kofs_prev, slot_prev);
+        if (tj == 2) dma_part_w<NW, 3>(gBp, gAp, d, kofs_prev, slot_prev);
       }
       __builtin_amdgcn_sched_barrier(0);
     }
   }
   wait_lgkm0();
-  if (STEADY)
+  if (STEADY || (CHAIN && rd_next))
     wait_vm<(SW - 2) * L>();
   else if (rd_next)
     wait_stages<L, SW - 2>(nk - 2 - j);
@@ -308,7 +317,7 @@ __device__ __forceinline__ void stage_iter_w(int j, int nk, const uint8_t *gB, c
     acc[3][ti] = mma(fb[3], fa[ti], acc[3][ti]);
     __builtin_amdgcn_sched_barrier(0);
     if (ti == 0 && ld_next)
-      dma_part_w<NW, 0>(gB, gA, d, kbeg + (int64_t)(j + SW) * BK, ring + (j % SW) * STAGEW);
+      dma_part_w<NW, 0>(gBx, gAx, d, kofs_next, ring + (j % SW) * STAGEW);
     if (rd_next) {
       // the next stage's fragments: the A side after MFMA 0, then B block 0
       if (ti == 0) {
@@ -322,26 +331,34 @@ __device__ __forceinline__ void stage_iter_w(int j, int nk, const uint8_t *gB, c
 }
 
 // acc += A B over nk stages of 64 k for one wide tile; gB / gA point at row
-// j0 / i0 of one B-side / A-side slice.
-template <int NW, class ACC>
+// j0 / i0 of one B-side / A-side slice.  Passes of one tile over the same k
+// range can be chained: with CHAIN_OUT the last stages also load the first
+// stages of the next pass (gBn, gAn), which the next pass's loop, with
+// CHAIN_IN, then finds in flight instead of issuing them itself; the fold
+// between the passes runs while they land.
+template <int NW, bool CHAIN_IN = false, bool CHAIN_OUT = false, class ACC>
 __device__ __forceinline__ void kloop_w(const uint8_t *gB, const uint8_t *gA, int64_t rowsB,
                                         int64_t rowsA, int64_t kbeg, int nk, uint8_t *lds,
-                                        ACC (&acc)[4][TB<NW>()], int tid) {
+                                        ACC (&acc)[4][TB<NW>()], int tid,
+                                        const uint8_t *gBn = nullptr,
+                                        const uint8_t *gAn = nullptr) {
   constexpr int TBW = TB<NW>(), NWW = NW;
   constexpr int L = 2 * LP<NW>();
   const int wave = tid >> 6;
   const int wj = wave / (NWW / 2), wi = wave % (NWW / 2);
   const DmaOffsets d = dma_offsets_w<NW>(rowsB, rowsA, tid);
   const uint32_t ring = lds_offset(lds);
+  if (!CHAIN_IN) {
 #pragma unroll
-  for (int t = 0; t < SW - 1; ++t)
-    if (t < nk) {
+    for (int t = 0; t < SW - 1; ++t)
+      if (t < nk) {
 #pragma unroll
-      for (int idx = 0; idx < L; ++idx)
-        dma_one_w<NW>(idx, gB, gA, d, kbeg + (int64_t)t * BK, ring + t * STAGEW);
-    }
-  if (SW - 1 < nk)
-    dma_part_w<NW, 0>(gB, gA, d, kbeg + (int64_t)(SW - 1) * BK, ring + (SW - 1) * STAGEW);
+        for (int idx = 0; idx < L; ++idx)
+          dma_one_w<NW>(idx, gB, gA, d, kbeg + (int64_t)t * BK, ring + t * STAGEW);
+      }
+    if (SW - 1 < nk)
+      dma_part_w<NW, 0>(gB, gA, d, kbeg + (int64_t)(SW - 1) * BK, ring + (SW - 1) * STAGEW);
+  }
   if (SW - 1 < nk)
     wait_vm<(SW - 2) * L + L / 4>();
   else
@@ -355,12 +372,16 @@ __device__ __forceinline__ void kloop_w(const uint8_t *gB, const uint8_t *gA, in
   // the trips whose stages all load a later stage run without the checks
   int j = 0;
   for (; j + 1 + SW < nk; j += 2) {
-    stage_iter_w<NW, true>(j, nk, gB, gA, d, kbeg, lds, ring, fa0, fa1, fb, acc, tid);
-    stage_iter_w<NW, true>(j + 1, nk, gB, gA, d, kbeg, lds, ring, fa1, fa0, fb, acc, tid);
+    stage_iter_w<NW, true, false>(j, nk, gB, gA, gB, gA, d, kbeg, lds, ring, fa0, fa1, fb, acc,
+                                  tid);
+    stage_iter_w<NW, true, false>(j + 1, nk, gB, gA, gB, gA, d, kbeg, lds, ring, fa1, fa0, fb,
+                                  acc, tid);
   }
   for (; j < nk; j += 2) {
-    stage_iter_w<NW, false>(j, nk, gB, gA, d, kbeg, lds, ring, fa0, fa1, fb, acc, tid);
-    stage_iter_w<NW, false>(j + 1, nk, gB, gA, d, kbeg, lds, ring, fa1, fa0, fb, acc, tid);
+    stage_iter_w<NW, false, CHAIN_OUT>(j, nk, gB, gA, gBn, gAn, d, kbeg, lds, ring, fa0, fa1, fb,
+                                       acc, tid);
+    stage_iter_w<NW, false, CHAIN_OUT>(j + 1, nk, gB, gA, gBn, gAn, d, kbeg, lds, ring, fa1, fa0,
+                                       fb, acc, tid);
   }
   __builtin_amdgcn_s_barrier();
 }
@@ -449,11 +470,14 @@ __device__ __forceinline__ void karatsuba_tile_w(const uint8_t *Asl, const uint8
 
   pin_agpr(acc);
   const int third = 3 - second;
-  kloop_w<NWW>(B0, A0, np, mp, kbeg, nk, lds, acc, tid);                         // X = C1
+  kloop_w<NWW, false, true>(B0, A0, np, mp, kbeg, nk, lds, acc, tid, B0 + second * sB,
+                            A0 + second * sA);                                      // X = C1
   fold_w(acc, mul_a, p, inv);
-  kloop_w<NWW>(B0 + second * sB, A0 + second * sA, np, mp, kbeg, nk, lds, acc, tid);  // + Y
+  kloop_w<NWW, true, true>(B0 + second * sB, A0 + second * sA, np, mp, kbeg, nk, lds, acc, tid,
+                           B0 + third * sB, A0 + third * sA);                       // + Y
   fold_w(acc, mul_b, p, inv);
-  kloop_w<NWW>(B0 + third * sB, A0 + third * sA, np, mp, kbeg, nk, lds, acc, tid);    // + Z
+  kloop_w<NWW, true, false>(B0 + third * sB, A0 + third * sA, np, mp, kbeg, nk, lds, acc,
+                            tid);                                                   // + Z
 
   const int lane = tid & 63, wave = tid >> 6;
   const int wj = wave / (NWW / 2), wi = wave % (NWW / 2);
@@ -564,11 +588,13 @@ __device__ __forceinline__ void square_tile_w(const uint8_t *Asl, const uint8_t 
       for (int v = 0; v < 16; ++v) acc[tj][ti][v] = 0.0f;
 
   pin_agpr(acc);
-  kloop_w<NWW>(B0 + sB, A0, np, mp, kbeg, nk, lds, acc, tid);       // A1 B2
+  kloop_w<NWW, false, true>(B0 + sB, A0, np, mp, kbeg, nk, lds, acc, tid, B0,
+                            A0 + sA);                                               // A1 B2
   pin_agpr(acc);
-  kloop_w<NWW>(B0, A0 + sA, np, mp, kbeg, nk, lds, acc, tid);       // + A2 B1
+  kloop_w<NWW, true, true>(B0, A0 + sA, np, mp, kbeg, nk, lds, acc, tid, B0 + sB,
+                           A0 + sA);                                                // + A2 B1
   fold_s(acc, s, inv_s);
-  kloop_w<NWW>(B0 + sB, A0 + sA, np, mp, kbeg, nk, lds, acc, tid);  // + A2 B2
+  kloop_w<NWW, true, false>(B0 + sB, A0 + sA, np, mp, kbeg, nk, lds, acc, tid);     // + A2 B2
 
   const int lane = tid & 63, wave = tid >> 6;
   const int wj = wave / (NWW / 2), wi = wave % (NWW / 2);
@@ -730,11 +756,13 @@ __device__ __forceinline__ void fp8_tile_w(const uint8_t *Asl, const uint8_t *Bs
       for (int v = 0; v < 16; ++v) acc[tj][ti][v] = 0.0f;
 
   pin_agpr(acc);
-  kloop_w<NWW>(B0 + b1 * sB, A0 + a1 * sA, np, mp, kbeg, nk, lds, acc, tid);
+  kloop_w<NWW, false, true>(B0 + b1 * sB, A0 + a1 * sA, np, mp, kbeg, nk, lds, acc, tid,
+                            B0 + b2 * sB, A0 + a2 * sA);
   fold_g(acc, (float)p, inv, m1, (float)p, inv);
-  kloop_w<NWW>(B0 + b2 * sB, A0 + a2 * sA, np, mp, kbeg, nk, lds, acc, tid);
+  kloop_w<NWW, true, true>(B0 + b2 * sB, A0 + a2 * sA, np, mp, kbeg, nk, lds, acc, tid,
+                           B0 + b3 * sB, A0 + a3 * sA);
   fold_g(acc, q2, iq2, m2, (float)p, ir2);
-  kloop_w<NWW>(B0 + b3 * sB, A0 + a3 * sA, np, mp, kbeg, nk, lds, acc, tid);
+  kloop_w<NWW, true, false>(B0 + b3 * sB, A0 + a3 * sA, np, mp, kbeg, nk, lds, acc, tid);
 
   const int lane = tid & 63, wave = tid >> 6;
   const int wj = wave / (NWW / 2), wi = wave % (NWW / 2);

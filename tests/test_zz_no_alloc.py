@@ -1,9 +1,10 @@
 """ozaki2_dgemm_noalloc (the entry point for callers that cannot allocate)
 through the C ABI against ozaki2_dgemm on the same inputs: C bit for bit on
 two calls in a row, the second smaller than the first (the fixed scratch
-buffer keeps the first call's contents), with transposes and alpha/beta; a
-problem beyond the scratch buffer is refused before anything is launched,
-and m/n blocking brings it back within the buffer."""
+buffer keeps the first call's contents), with transposes and alpha/beta,
+and with k split over several parts; a problem beyond the scratch buffer is
+refused before anything is launched, and m/n blocking brings it back within
+the buffer."""
 import numpy as np
 import pytest
 import torch
@@ -64,6 +65,24 @@ def test_noalloc_fast_mode_and_int8():
     finally:
         oz.ozaki2_set_mode("accurate")
         oz.ozaki2_set_moduli_list("hybrid")
+
+
+def test_noalloc_split_products_and_bound():
+    # one output tile with a long k: the products run in k parts (plane
+    # copies) and the bound product in parts summed by a second launch, all
+    # inside the scratch buffer; then a smaller call on the same buffer
+    m, n, k = 256, 256, 8192
+    parts, bparts = oz.ozaki2_workspace_parts(m, n, k, 12)
+    assert parts > 1 and bparts > 1
+    assert oz.ozaki2_workspace_bytes(m, n, k, 12) <= oz.NOALLOC_SCRATCH_BYTES
+    A = phi_matrix(m, k, 1.0, 95)
+    B = phi_matrix(k, n, 1.0, 96)
+    print(f"noalloc: {m} x {n} x {k}, {parts} product parts, {bparts} bound parts", flush=True)
+    _pair(A, B, 12)
+    a = phi_matrix(100, 5000, 1.0, 97)
+    b = phi_matrix(5000, 90, 1.0, 98)
+    print("noalloc: 100 x 90 x 5000", flush=True)
+    _pair(a, b, 12, ta="T")
 
 
 def test_noalloc_refuses_beyond_scratch_and_blocking_fits():

@@ -48,9 +48,11 @@ __host__ __device__ __forceinline__ bool any_below(const uint32_t (&x)[L], int p
   return acc != 0;
 }
 
-// RN-even of X 2^-t for a non-negative integer X (L limbs).
+// RN-even of X 2^-t for a non-negative integer X (L limbs), bit by bit: the
+// 53 kept bits, the round bit and the sticky bits at the position the result's
+// exponent gives, gradual underflow included.
 template <int L>
-__host__ __device__ __forceinline__ double scaled_rn(const uint32_t (&X)[L], int t) {
+__host__ __device__ __forceinline__ double scaled_rn_exact(const uint32_t (&X)[L], int t) {
   int hb = -1;
 #pragma unroll
   for (int q = 0; q < L; ++q)
@@ -67,6 +69,40 @@ __host__ __device__ __forceinline__ double scaled_rn(const uint32_t (&X)[L], int
     if (rbit && (sticky || (Q & 1ull))) Q += 1;
   }
   return ldexp((double)Q, lsb - t);
+}
+
+// RN-even of X 2^-t for a non-negative integer X (L limbs).  With h the top
+// nonzero limb and c the leading zeros of X[h], the 64 bits below the leading
+// bit, U = floor(X 2^(c + 32 - 32 h)) (limbs h, h - 1, h - 2 shifted left by
+// c), hold the 53 kept bits and the round bit of X; any bit of X below U is
+// folded into U's lowest bit, which lies below the round bit, so RN(U') =
+// RN(X 2^(c + 32 - 32 h)).  RN(U') is one fused multiply-add of two exact
+// halves, and scaling it by 2^(32 h - 32 - c - t) is exact when the result is
+// normal (it overflows to infinity exactly when RN(X 2^-t) does).  A result
+// below 2^-1022 takes the bit-by-bit rounding, whose position depends on the
+// exponent.
+template <int L>
+__host__ __device__ __forceinline__ double scaled_rn(const uint32_t (&X)[L], int t) {
+  int h = -1;
+#pragma unroll
+  for (int q = 0; q < L; ++q)
+    if (X[q]) h = q;
+  if (h < 0) return 0.0;
+  uint32_t T2 = 0, T1 = 0, T0 = 0, below = 0;
+#pragma unroll
+  for (int q = 0; q < L; ++q) {
+    T2 = (q == h) ? X[q] : T2;
+    T1 = (q == h - 1) ? X[q] : T1;
+    T0 = (q == h - 2) ? X[q] : T0;
+    below |= (q < h - 2) ? X[q] : 0u;
+  }
+  const int c = __builtin_clz(T2);
+  if (32 * h + 31 - c - t < -1022) return scaled_rn_exact<L>(X, t);
+  const uint64_t lo = (((uint64_t)T1 << 32) | T0) << c;
+  const uint32_t u2 = (T2 << c) | ((T1 >> 1) >> (31 - c));  // no shift by 32 for c = 0
+  const uint32_t u1 = (uint32_t)(lo >> 32) | ((below | (uint32_t)lo) != 0u ? 1u : 0u);
+  const double u = fma((double)u2, 0x1p32, (double)u1);
+  return ldexp(u, 32 * h - 32 - c - t);
 }
 
 // D = sum_q r[q] 2^(32 q) for integers |r[q]| < 2^49 and |D| < 2^(32 L): its

@@ -8,18 +8,6 @@
 
 namespace oz2 {
 
-// Split a finite double into |x| = mant * 2^q with mant < 2^53 (an integer).
-__device__ __forceinline__ void split_double(uint64_t bits, uint64_t &mant, int &q) {
-  int ex = (int)((bits >> 52) & 0x7FF);
-  mant = bits & ((1ull << 52) - 1);
-  if (ex == 0) {
-    q = -1074;
-  } else {
-    mant |= 1ull << 52;
-    q = ex - 1075;
-  }
-}
-
 // floor(log2 |x|) of a finite nonzero double given its bits.
 __device__ __forceinline__ int ufp_exponent(uint64_t bits) {
   int ex = (int)((bits >> 52) & 0x7FF);
@@ -32,48 +20,21 @@ __device__ __forceinline__ bool is_nonfinite(uint64_t bits) {
   return ((bits >> 52) & 0x7FF) == 0x7FF;
 }
 
-// E4M3 code of the smallest E4M3 value >= |x| * 2^sh for a finite double
-// (given as bits) whose scaled magnitude is below 2^8 + 1 (Section III-E cast
-// of mu'|A| in round-up mode).  Exact integer arithmetic throughout.
-__device__ __forceinline__ uint32_t e4m3_round_up(uint64_t bits, int sh) {
-  uint64_t mant;
-  int q;
-  split_double(bits & 0x7FFFFFFFFFFFFFFFull, mant, q);
-  if (mant == 0) return 0u;
-  int bl = 64 - __clzll((long long)mant);  // bit length of mant
-  int bexp = bl - 1 + q + sh;              // floor(log2 of the scaled value)
-  if (bexp >= -6) {
-    // normal: 4 significant bits, rounded up
-    int drop = bl - 4;                     // >= 0 since mant of a normal double has 53 bits
-    uint64_t Q;
-    if (drop > 0) {
-      Q = mant >> drop;
-      if (mant & ((1ull << drop) - 1)) Q += 1;
-    } else {
-      Q = mant << (-drop);
-    }
-    if (Q == 16) {
-      Q = 8;
-      bexp += 1;
-    }
-    return (uint32_t)(((bexp + 7) << 3) | (int)(Q - 8));
-  }
-  // subnormal grid 2^-9: Q = ceil(value / 2^-9) in [1, 8]; Q = 8 is the code
-  // of 2^-6, the smallest normal
-  // value / 2^-9 = mant * 2^s2; s2 <= 3 - bitlength(mant), so s2 > 0 only
-  // for the few-bit mantissas of subnormal doubles
-  int s2 = q + sh + 9;
-  uint64_t Q;
-  if (s2 >= 0) {
-    Q = mant << s2;
-  } else if (-s2 >= 64) {
-    Q = 1;
-  } else {
-    int r = -s2;
-    Q = mant >> r;
-    if (mant & ((1ull << r) - 1)) Q += 1;
-  }
-  return (uint32_t)Q;
+// E4M3 code of the smallest E4M3 value >= |a| 2^sh for a finite nonzero
+// double a whose scaled magnitude y = |a| 2^sh is below 2^8 + 1 (Section
+// III-E cast of mu'|A| in round-up mode).  With e = max(floor(log2 y), -6)
+// the E4M3 values near y are spaced 2^(e - 3) (below 2^-6 the subnormal
+// spacing 2^-9 = 2^(-6 - 3)), so the result is Q 2^(e - 3) with
+// Q = ceil(y 2^(3 - e)) in [1, 16], and its code is 8 (e + 7) + Q - 8:
+// Q = 16 carries into the next binade's code, and at e = -6 the codes 1..8
+// are the subnormals and the smallest normal.  The scaling by
+// 2^(sh + 3 - e) is exact unless its result falls below 2^-1022, where y is
+// far below one spacing and Q = 1; hence the maximum with one.
+__device__ __forceinline__ uint32_t e4m3_round_up(double a, int sh) {
+  const int fl = __builtin_amdgcn_frexp_exp(a) - 1 + sh;  // floor(log2 y)
+  const int e = fl > -6 ? fl : -6;
+  const double Q = fmax(ceil(ldexp(fabs(a), sh + 3 - e)), 1.0);
+  return (uint32_t)(8 * e + 48 + (int)Q);
 }
 
 // E4M3 code of a small integer d with |d| <= 16 (exact in the format).

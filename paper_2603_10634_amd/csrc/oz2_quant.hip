@@ -16,11 +16,16 @@ namespace {
 
 constexpr uint64_t kAbsMask = 0x7FFFFFFFFFFFFFFFull;
 constexpr uint64_t kInfBits = 0x7FF0000000000000ull;
+// class mask of the finite nonzero doubles (negative and positive normal and
+// subnormal numbers)
+constexpr int kFiniteNonzero = 0x198;
 
 __device__ __forceinline__ void fill_zero(uint32_t *p, int64_t count, int64_t blk,
                                           int64_t nblk) {
   for (int64_t i = blk * 256 + threadIdx.x; i < count; i += nblk * 256) p[i] = 0u;
 }
+
+constexpr int kLmaxU = 8;  // independent loads per trip of the line-maximum loops
 
 // Maxima of |x| over finite entries, per line; non-finite entries flag the line.
 // Lines with contiguous k: one wave per line and k-chunk.
@@ -35,7 +40,22 @@ __device__ __forceinline__ void line_max_kcontig(const Operand &op, const LmaxSh
   const double *row = op.ptr + r * op.sr;
   uint64_t m = 0;
   int bad = 0;
-  for (int64_t h = h0 + lane; h < h1; h += 64) {
+  int64_t h = h0 + lane;
+  // kLmaxU loads in flight per trip, then a remainder of single loads
+  for (; h + 64 * (kLmaxU - 1) < h1; h += 64 * kLmaxU) {
+    uint64_t b[kLmaxU];
+#pragma unroll
+    for (int u = 0; u < kLmaxU; ++u)
+      b[u] = (uint64_t)__double_as_longlong(row[h + 64 * u]) & kAbsMask;
+#pragma unroll
+    for (int u = 0; u < kLmaxU; ++u) {
+      if (b[u] >= kInfBits)
+        bad = 1;
+      else
+        m = b[u] > m ? b[u] : m;
+    }
+  }
+  for (; h < h1; h += 64) {
     uint64_t b = (uint64_t)__double_as_longlong(row[h]) & kAbsMask;
     if (b >= kInfBits)
       bad = 1;
@@ -63,7 +83,21 @@ __device__ __forceinline__ void line_max_lcontig(const Operand &op, const LmaxSh
   const int64_t h1 = min(op.k, h0 + sh.hchunk);
   uint64_t m = 0;
   int bad = 0;
-  for (int64_t h = h0; h < h1; ++h) {
+  int64_t h = h0;
+  for (; h + kLmaxU <= h1; h += kLmaxU) {
+    uint64_t b[kLmaxU];
+#pragma unroll
+    for (int u = 0; u < kLmaxU; ++u)
+      b[u] = (uint64_t)__double_as_longlong(op.ptr[r + (h + u) * op.sh]) & kAbsMask;
+#pragma unroll
+    for (int u = 0; u < kLmaxU; ++u) {
+      if (b[u] >= kInfBits)
+        bad = 1;
+      else
+        m = b[u] > m ? b[u] : m;
+    }
+  }
+  for (; h < h1; ++h) {
     uint64_t b = (uint64_t)__double_as_longlong(op.ptr[r + h * op.sh]) & kAbsMask;
     if (b >= kInfBits)
       bad = 1;
@@ -157,9 +191,8 @@ __device__ __forceinline__ void bound_operand_tile(const Operand &op, int64_t li
 #pragma unroll
     for (int z = 0; z < 4; ++z) {
       const double v = tile[tile_at(rl, b * 8 + w * 4 + z)];
-      const uint64_t bits = (uint64_t)__double_as_longlong(v);
-      uint32_t code = 0;
-      if ((bits & kAbsMask) < kInfBits) code = e4m3_round_up(bits, sh7);
+      const uint32_t code =
+          __builtin_amdgcn_class(v, kFiniteNonzero) ? e4m3_round_up(v, sh7) : 0u;
       word |= code << (8 * z);
     }
     packed[w] = word;
@@ -205,8 +238,9 @@ __device__ __forceinline__ void bound_norm_tile(const Operand &op, int64_t r0, i
   uint64_t sum = 0;
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
-    const uint64_t bits = (uint64_t)__double_as_longlong(tile[tile_at(rl, b * 8 + q)]);
-    const uint32_t q9 = (bits & kAbsMask) < kInfBits ? e4m3_q9(e4m3_round_up(bits, sh7)) : 0u;
+    const double v = tile[tile_at(rl, b * 8 + q)];
+    const uint32_t q9 =
+        __builtin_amdgcn_class(v, kFiniteNonzero) ? e4m3_q9(e4m3_round_up(v, sh7)) : 0u;
     sum += (uint64_t)q9 * q9;
   }
   // the 16 threads of a line are 16 consecutive lanes
@@ -233,11 +267,16 @@ __global__ __launch_bounds__(256) void k_bound_norm(Problem P1, Group G) {
 // Residues of a' (eq. def:A') for every modulus, split into digits, for one
 // tile (lines r0.., k h0..).
 //
-// Each finite input is |a| = mant 2^qe with mant < 2^53; with s = log2 mu_r
-// the integer is a' = sign (mant 2^t) for t = qe + s > 0, else
-// sign floor(mant 2^t) (eq. def:A': truncation toward zero).  Per input the
-// signed integer x = sign mant 2^min(t, 10) (t > 0) or a' (t <= 0) is held
-// exactly in a double (|x| < 2^63).  Per modulus, x mod p is taken in FP64:
+// Each finite nonzero input is |a| = F 2^(E - 53) with E its frexp exponent
+// and F < 2^53 an integer (also for subnormal a); with s = log2 mu_r the
+// integer is a' = sign (F 2^t) for t = E - 53 + s > 0, else sign floor(F 2^t)
+// (eq. def:A': truncation toward zero).  Per input the signed integer
+// x = sign F 2^min(t, 10) (t > 0) or a' (t <= 0) is held exactly in a double
+// (|x| < 2^63): x = trunc(a 2^(s - max(t - 10, 0))), where the scaling is
+// exact whenever the result is at least 2^-1022 and otherwise is below one in
+// magnitude, so that the truncation gives zero either way.  Zero, infinite and
+// NaN inputs give x = +0 (their lines are flagged, or their digits are zero).
+// Per modulus, x mod p is taken in FP64:
 // q = rint(x p^-1) is within 21 of the rounded quotient (within one when
 // |x| < 2^53), and f = x - q p is exact in one fused multiply-add
 // (|f| < 2^15).  One FP32 step f - p rint(f p^-1) then removes the nearest
@@ -260,12 +299,14 @@ constexpr int kDirectT = 10;  // powers 2^t applied in FP64 directly
 constexpr int kRE = kQK * kQL / 256;  // inputs per thread of a quantization tile (8)
 
 struct ResidueIn {
-  double x[kRE];  // sign mant 2^min(t, 10) (t > 0) or signed a' (t <= 0), exact
+  double x[kRE];  // sign F 2^min(t, 10) (t > 0) or signed a' (t <= 0), exact, never -0
   int t[kRE];     // t > 10: the power of two t - 10 still to apply, else 0
-  bool huge;      // some lane of the wave has t > 10
 };
 
-template <int KIND, bool EVEN>
+// HUGE: some lane of the wave has t > 10 (a wave-uniform choice of the
+// whole modulus loop, so that the common loop carries nothing of the table
+// lookup of 2^(t - 10) mod p).
+template <int KIND, bool EVEN, bool HUGE>
 __device__ __forceinline__ void modulus_pass(const ResidueIn &in, const Tables *__restrict__ tab,
                                              int l, uint8_t *dst, int64_t slice_stride) {
   const int p = tab->p[l];
@@ -280,7 +321,7 @@ __device__ __forceinline__ void modulus_pass(const ResidueIn &in, const Tables *
     const float f = (float)fma(-rint(x * invpd), pd, x);
     fu[q] = fmaf(-rintf(f * invpf), pf, f);
   }
-  if (in.huge) {
+  if (HUGE) {
 #pragma unroll
     for (int q = 0; q < kRE; ++q) {
       if (in.t[q] > 0) {
@@ -330,18 +371,50 @@ __device__ __forceinline__ void modulus_pass(const ResidueIn &in, const Tables *
         x3[z] = x1[z] + x2[z];
       }
     }
-    w1[g] = __builtin_amdgcn_cvt_pk_fp8_f32(x1[0], x1[1], 0, false);
+    // the first conversion's old word is a register no longer needed (the
+    // residues themselves): its upper half is replaced by the second one
+    w1[g] = __builtin_amdgcn_cvt_pk_fp8_f32(x1[0], x1[1], __float_as_int(fu[4 * g]), false);
     w1[g] = __builtin_amdgcn_cvt_pk_fp8_f32(x1[2], x1[3], w1[g], true);
-    w2[g] = __builtin_amdgcn_cvt_pk_fp8_f32(x2[0], x2[1], 0, false);
+    w2[g] = __builtin_amdgcn_cvt_pk_fp8_f32(x2[0], x2[1], __float_as_int(fu[4 * g + 1]), false);
     w2[g] = __builtin_amdgcn_cvt_pk_fp8_f32(x2[2], x2[3], w2[g], true);
     if (KIND == 1) {
-      w3[g] = __builtin_amdgcn_cvt_pk_fp8_f32(x3[0], x3[1], 0, false);
+      w3[g] = __builtin_amdgcn_cvt_pk_fp8_f32(x3[0], x3[1], __float_as_int(fu[4 * g + 2]), false);
       w3[g] = __builtin_amdgcn_cvt_pk_fp8_f32(x3[2], x3[3], w3[g], true);
     }
   }
   *(uint2 *)dst = make_uint2(w1[0], w1[1]);
   *(uint2 *)(dst + slice_stride) = make_uint2(w2[0], w2[1]);
   if (KIND == 1) *(uint2 *)(dst + 2 * slice_stride) = make_uint2(w3[0], w3[1]);
+}
+
+// Every modulus of one thread's inputs, kind by kind.
+template <bool HUGE>
+__device__ __forceinline__ void residue_moduli(const ResidueIn &in, const Tables *__restrict__ tab,
+                                               int N, int nsq, int nka, uint8_t *base,
+                                               int64_t slice_stride) {
+  // p is uniform: the parity test is a branch, not a select
+  int l = 0;
+  for (; l < nsq; ++l) {
+    uint8_t *dst = base + (int64_t)tab->slice0[l] * slice_stride;
+    if (tab->p[l] & 1)
+      modulus_pass<0, false, HUGE>(in, tab, l, dst, slice_stride);
+    else
+      modulus_pass<0, true, HUGE>(in, tab, l, dst, slice_stride);
+  }
+  for (; l < nsq + nka; ++l) {
+    uint8_t *dst = base + (int64_t)tab->slice0[l] * slice_stride;
+    if (tab->p[l] & 1)
+      modulus_pass<1, false, HUGE>(in, tab, l, dst, slice_stride);
+    else
+      modulus_pass<1, true, HUGE>(in, tab, l, dst, slice_stride);
+  }
+  for (; l < N; ++l) {
+    uint8_t *dst = base + (int64_t)tab->slice0[l] * slice_stride;
+    if (tab->p[l] & 1)
+      modulus_pass<2, false, HUGE>(in, tab, l, dst, slice_stride);
+    else
+      modulus_pass<2, true, HUGE>(in, tab, l, dst, slice_stride);
+  }
 }
 
 __device__ __forceinline__ void residues_tile(const Operand &op, int64_t kp, int64_t lines_pad,
@@ -361,54 +434,24 @@ __device__ __forceinline__ void residues_tile(const Operand &op, int64_t kp, int
   bool huge = false;
 #pragma unroll
   for (int q = 0; q < kRE; ++q) {
-    const uint64_t bits = (uint64_t)__double_as_longlong(tile[tile_at(rl, b * kRE + q)]);
-    uint64_t m = 0;
-    int t = 0;
-    if ((bits & kAbsMask) < kInfBits) {
-      uint64_t mant;
-      int qe;
-      split_double(bits, mant, qe);
-      const int e2 = qe + s;
-      if (e2 > 0) {
-        m = mant;
-        t = e2 < kPowT ? e2 : kPowT - 1;
-      } else if (e2 > -64) {
-        m = mant >> (-e2);
-      }
-    }
-    // exact: m < 2^53, times 2^min(t, 10); never -0 (a zero digit encodes as +0)
-    const double md = ldexp((double)m, t < kDirectT ? t : kDirectT);
-    in.x[q] = ((bits >> 63) && m) ? -md : md;
-    in.t[q] = t > kDirectT ? t - kDirectT : 0;
-    huge |= t > kDirectT;
+    const double a = tile[tile_at(rl, b * kRE + q)];
+    const bool nz = __builtin_amdgcn_class(a, kFiniteNonzero);
+    int t = nz ? __builtin_amdgcn_frexp_exp(a) - 53 + s : 0;
+    t = t < kPowT ? t : kPowT - 1;
+    const int tt = t > kDirectT ? t - kDirectT : 0;
+    // + 0 turns the -0 of a negative input with |a'| < 1 into +0
+    const double x = trunc(ldexp(a, s - tt)) + 0.0;
+    in.x[q] = nz ? x : 0.0;
+    in.t[q] = tt;
+    huge |= tt > 0;
   }
-  in.huge = __any(huge);
 
   const int64_t slice_stride = lines_pad * kp;
   uint8_t *base = slices + kblocked(r, h0 + b * kRE, lines_pad);
-  // p is uniform: the parity test is a branch, not a select
-  int l = 0;
-  for (; l < nsq; ++l) {
-    uint8_t *dst = base + (int64_t)tab->slice0[l] * slice_stride;
-    if (tab->p[l] & 1)
-      modulus_pass<0, false>(in, tab, l, dst, slice_stride);
-    else
-      modulus_pass<0, true>(in, tab, l, dst, slice_stride);
-  }
-  for (; l < nsq + nka; ++l) {
-    uint8_t *dst = base + (int64_t)tab->slice0[l] * slice_stride;
-    if (tab->p[l] & 1)
-      modulus_pass<1, false>(in, tab, l, dst, slice_stride);
-    else
-      modulus_pass<1, true>(in, tab, l, dst, slice_stride);
-  }
-  for (; l < N; ++l) {
-    uint8_t *dst = base + (int64_t)tab->slice0[l] * slice_stride;
-    if (tab->p[l] & 1)
-      modulus_pass<2, false>(in, tab, l, dst, slice_stride);
-    else
-      modulus_pass<2, true>(in, tab, l, dst, slice_stride);
-  }
+  if (__any(huge))
+    residue_moduli<true>(in, tab, N, nsq, nka, base, slice_stride);
+  else
+    residue_moduli<false>(in, tab, N, nsq, nka, base, slice_stride);
 }
 
 template <bool GROUPED, int SIDE>

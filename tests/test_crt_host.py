@@ -75,6 +75,19 @@ def _targets(P, rng, count):
     for e in (39, 40, 41):
         edge = h - (P >> e)
         out += [edge + d for d in range(-2, 3)] + [-(edge + d) for d in range(-2, 3)]
+    # leading bits at and next to the 32-bit limb boundaries, with the bits
+    # below the 53 kept ones a tie, a tie plus one, or a round bit and one far
+    # sticky bit
+    for bl in (31, 32, 33, 63, 64, 65, 95, 96, 97, 127, 128, 129):
+        if bl >= P.bit_length():
+            continue
+        top = rng.getrandbits(53) | (1 << 52)
+        k = bl - 53
+        if k < 2:
+            out.append(top << max(k, 0))
+            continue
+        tie = (top << k) | (1 << (k - 1))
+        out += [tie, -tie, tie + 1, tie - 1, tie | 1]
     for _ in range(count):
         r = rng.random()
         if r < 0.4:

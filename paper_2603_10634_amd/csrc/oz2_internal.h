@@ -35,6 +35,8 @@ struct Tables {
                               // see the residue products
   float inv_p[kMaxN];         // 1/p, float
   double inv_pd[kMaxN];       // 1/p, double
+  double inv_pair[kMaxN];     // 1/(p_l p_(l+1)), double (the residue pass reduces two
+                              // consecutive moduli of one kind in one FP64 step)
   float inv_s[kMaxN];         // 1/s, float
   uint16_t pw[kMaxN][kPowT];  // 2^t mod p, t < kPowT
   uint32_t w[kMaxN][kLimbs];  // CRT weights q_l P / p_l, little-endian limbs

@@ -276,12 +276,14 @@ __global__ __launch_bounds__(256) void k_bound_norm(Problem P1, Group G) {
 // exact whenever the result is at least 2^-1022 and otherwise is below one in
 // magnitude, so that the truncation gives zero either way.  Zero, infinite and
 // NaN inputs give x = +0 (their lines are flagged, or their digits are zero).
-// Per modulus, x mod p is taken in FP64:
-// q = rint(x p^-1) is within 21 of the rounded quotient (within one when
-// |x| < 2^53), and f = x - q p is exact in one fused multiply-add
-// (|f| < 2^15).  One FP32 step f - p rint(f p^-1) then removes the nearest
-// multiple of p: the computed quotient is within |f / p| 2^-23 < 2^-8 / p of
-// f / p, while for odd p an integer f / p is at least 1 / (2p) from a tie,
+// One FP64 step serves two consecutive moduli p, p' of one kind (R = p p' <
+// 2^21), or one modulus alone (R = p): q = rint(x R^-1) is within
+// 2^63 / R 2^-52 = 2^11 / R of x / R (both roundings), so
+// |f| = |x - q R| < R / 2 + 2^11 < 2^20 + 2^11, and f is exact in one fused
+// multiply-add.  Per modulus, one FP32 step f - p rint(f p^-1) then removes
+// the nearest multiple of p: the computed quotient is within
+// |f / p| 2^-23 < 1 / (8p) (1 + 2^-9) of f / p (f is exact in FP32), while
+// for odd p an integer f / p is at least 1 / (2p) from a tie,
 // so the result is exactly in [-(p - 1)/2, (p - 1)/2]; for even p it is
 // in [-p/2, p/2] and a tie's +p/2 is moved to -p/2, giving the symmetric
 // range [-floor(p/2), ceil(p/2) - 1] in both cases.  Inputs with t > 10 (only
@@ -306,21 +308,24 @@ struct ResidueIn {
 // HUGE: some lane of the wave has t > 10 (a wave-uniform choice of the
 // whole modulus loop, so that the common loop carries nothing of the table
 // lookup of 2^(t - 10) mod p).
+// The FP64 step: f = x - R rint(x R^-1), exact, |f| < 2^20 + 2^11.
+__device__ __forceinline__ void fp64_step(const ResidueIn &in, double R, double invR,
+                                          float (&f)[kRE]) {
+#pragma unroll
+  for (int q = 0; q < kRE; ++q) f[q] = (float)fma(-rint(in.x[q] * invR), R, in.x[q]);
+}
+
 template <int KIND, bool EVEN, bool HUGE>
-__device__ __forceinline__ void modulus_pass(const ResidueIn &in, const Tables *__restrict__ tab,
-                                             int l, uint8_t *dst, int64_t slice_stride) {
+__device__ __forceinline__ void modulus_pass(const float (&f)[kRE], const ResidueIn &in,
+                                             const Tables *__restrict__ tab, int l, uint8_t *dst,
+                                             int64_t slice_stride) {
   const int p = tab->p[l];
   const float pf = (float)p;
   const float hif = (float)(p - 1 - (p >> 1));
-  const double pd = (double)p, invpd = tab->inv_pd[l];
   const float invpf = tab->inv_p[l];
   float fu[kRE];
 #pragma unroll
-  for (int q = 0; q < kRE; ++q) {
-    const double x = in.x[q];
-    const float f = (float)fma(-rint(x * invpd), pd, x);
-    fu[q] = fmaf(-rintf(f * invpf), pf, f);
-  }
+  for (int q = 0; q < kRE; ++q) fu[q] = fmaf(-rintf(f[q] * invpf), pf, f[q]);
   if (HUGE) {
 #pragma unroll
     for (int q = 0; q < kRE; ++q) {
@@ -387,34 +392,45 @@ __device__ __forceinline__ void modulus_pass(const ResidueIn &in, const Tables *
   if (KIND == 1) *(uint2 *)(dst + 2 * slice_stride) = make_uint2(w3[0], w3[1]);
 }
 
+template <int KIND, bool HUGE>
+__device__ __forceinline__ void one_modulus(const float (&f)[kRE], const ResidueIn &in,
+                                            const Tables *__restrict__ tab, int l, uint8_t *base,
+                                            int64_t slice_stride) {
+  uint8_t *dst = base + (int64_t)tab->slice0[l] * slice_stride;
+  // p is uniform: the parity test is a branch, not a select
+  if (tab->p[l] & 1)
+    modulus_pass<KIND, false, HUGE>(f, in, tab, l, dst, slice_stride);
+  else
+    modulus_pass<KIND, true, HUGE>(f, in, tab, l, dst, slice_stride);
+}
+
+// The moduli l0 .. l1 - 1 of one kind, two per FP64 step (one per step on
+// the rare path with t > 10, which holds more registers).
+template <int KIND, bool HUGE>
+__device__ __forceinline__ void kind_moduli(const ResidueIn &in, const Tables *__restrict__ tab,
+                                            int l0, int l1, uint8_t *base, int64_t slice_stride) {
+  int l = l0;
+  for (; !HUGE && l + 1 < l1; l += 2) {
+    float f[kRE];
+    fp64_step(in, (double)(tab->p[l] * tab->p[l + 1]), tab->inv_pair[l], f);
+    one_modulus<KIND, HUGE>(f, in, tab, l, base, slice_stride);
+    one_modulus<KIND, HUGE>(f, in, tab, l + 1, base, slice_stride);
+  }
+  for (; l < l1; ++l) {
+    float f[kRE];
+    fp64_step(in, (double)tab->p[l], tab->inv_pd[l], f);
+    one_modulus<KIND, HUGE>(f, in, tab, l, base, slice_stride);
+  }
+}
+
 // Every modulus of one thread's inputs, kind by kind.
 template <bool HUGE>
 __device__ __forceinline__ void residue_moduli(const ResidueIn &in, const Tables *__restrict__ tab,
                                                int N, int nsq, int nka, uint8_t *base,
                                                int64_t slice_stride) {
-  // p is uniform: the parity test is a branch, not a select
-  int l = 0;
-  for (; l < nsq; ++l) {
-    uint8_t *dst = base + (int64_t)tab->slice0[l] * slice_stride;
-    if (tab->p[l] & 1)
-      modulus_pass<0, false, HUGE>(in, tab, l, dst, slice_stride);
-    else
-      modulus_pass<0, true, HUGE>(in, tab, l, dst, slice_stride);
-  }
-  for (; l < nsq + nka; ++l) {
-    uint8_t *dst = base + (int64_t)tab->slice0[l] * slice_stride;
-    if (tab->p[l] & 1)
-      modulus_pass<1, false, HUGE>(in, tab, l, dst, slice_stride);
-    else
-      modulus_pass<1, true, HUGE>(in, tab, l, dst, slice_stride);
-  }
-  for (; l < N; ++l) {
-    uint8_t *dst = base + (int64_t)tab->slice0[l] * slice_stride;
-    if (tab->p[l] & 1)
-      modulus_pass<2, false, HUGE>(in, tab, l, dst, slice_stride);
-    else
-      modulus_pass<2, true, HUGE>(in, tab, l, dst, slice_stride);
-  }
+  kind_moduli<0, HUGE>(in, tab, 0, nsq, base, slice_stride);
+  kind_moduli<1, HUGE>(in, tab, nsq, nsq + nka, base, slice_stride);
+  kind_moduli<2, HUGE>(in, tab, nsq + nka, N, base, slice_stride);
 }
 
 __device__ __forceinline__ void residues_tile(const Operand &op, int64_t kp, int64_t lines_pad,

@@ -167,6 +167,9 @@ bool build_tables(int N, int list, Tables *t) {
     slice += square ? 2 : (int8 ? 1 : 3);
     t->inv_p[l] = 1.0f / (float)p[l];
     t->inv_pd[l] = 1.0 / (double)p[l];
+    t->inv_pair[l] = l + 1 < N ? 1.0 / ((double)p[l] * (double)p[l + 1]) : 0.0;
+    // the residue pass's shared FP64 step needs p_l p_(l+1) < 2^21
+    if (l + 1 < N && (int64_t)p[l] * p[l + 1] >= (1 << 21)) return false;
     t->inv_s[l] = 1.0f / (float)t->s[l];
     if (!square && !int8) {
       const int q = p[l];

@@ -20,9 +20,10 @@ The largest magnitudes are covered exhaustively near the top of each range
 every modulus of all three lists up to N = 33.
 
 And the residue pass of the quantization kernel (x mod p for the scaled
-integers): the FP64 step x - rint(x fl(1/p)) p for integers |x| < 2^53 and
-|x| = mant 2^10 < 2^63 near ties, then one FP32 step with no further
-correction for odd p (one for even p) must give the symmetric residue;
+integers): the FP64 step x - rint(x fl(1/R)) R, for R = p alone or for
+R = p p' (two consecutive moduli of one kind), for integers |x| < 2^53 and
+|x| = mant 2^10 < 2^63 near ties, then one FP32 step per modulus with no
+further correction for odd p (one for even p) must give the symmetric residue;
 likewise for the later multiplication by 2^t mod p; and the square digit
 rint(u fl(1/s)) must equal round(u / s) with ties away from zero for odd s."""
 import numpy as np
@@ -165,6 +166,47 @@ def test_residue_pass_reduction(p):
         f = x - q * p                                       # the exact fma
         assert np.all(np.abs(f) < 2 ** 15)
         assert np.array_equal(_fp32_step(f, p), _sym(x, p))
+
+
+def _pairs():
+    """The moduli the residue pass reduces two at a time: consecutive moduli of
+    one kind, paired from the kind's first (a run of odd length leaves its
+    last modulus alone).  The pairs of N = 33 contain those of every N."""
+    out = set()
+    for name in ("hybrid", "karatsuba", "int8"):
+        table = ref.moduli_table(33, name)
+        l = 0
+        while l < len(table):
+            end = l
+            while end < len(table) and table[end][1] == table[l][1]:
+                end += 1
+            for a in range(l, end - 1, 2):
+                out.add((table[a][0], table[a + 1][0]))
+            l = end
+    return sorted(out)
+
+
+@pytest.mark.parametrize("p,p2", _pairs())
+def test_residue_pass_paired_reduction(p, p2):
+    # one FP64 step modulo R = p p2 (< 2^21), then the FP32 step of each modulus
+    R = p * p2
+    assert R < 2 ** 21
+    inv = np.float64(1.0) / np.float64(R)
+    small = np.concatenate([_near_ties(p, 2 ** 53, 1 << 13), _near_ties(p2, 2 ** 53, 1 << 13),
+                            _near_ties(R, 2 ** 53, 1 << 13),
+                            RNG.integers(-2 ** 53 + 1, 2 ** 53, 1 << 14, dtype=np.int64),
+                            np.arange(-3 * R, 3 * R + 1, 97, dtype=np.int64)])
+    mant = np.concatenate([_near_ties(q, 2 ** 53, 1 << 12) // q * q for q in (p, p2, R)])
+    big = np.concatenate([mant * 1024, (mant + RNG.integers(0, R, mant.size)) * 1024,
+                          np.array([(2 ** 53 - 1) * 1024, -(2 ** 53 - 1) * 1024])])
+    for x in (small, big):
+        xf = x.astype(np.float64)
+        assert np.all(xf.astype(np.int64) == x)            # exact doubles
+        q = np.rint(xf * inv).astype(np.int64)
+        f = x - q * R                                       # the exact fma
+        assert np.all(np.abs(f) < 2 ** 20 + 2 ** 11)
+        assert np.array_equal(_fp32_step(f, p), _sym(x, p))
+        assert np.array_equal(_fp32_step(f, p2), _sym(x, p2))
 
 
 @pytest.mark.parametrize("p", _all_moduli())

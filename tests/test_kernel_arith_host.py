@@ -25,7 +25,11 @@ R = p p' (two consecutive moduli of one kind), for integers |x| < 2^53 and
 |x| = mant 2^10 < 2^63 near ties, then one FP32 step per modulus with no
 further correction for odd p (one for even p) must give the symmetric residue;
 likewise for the later multiplication by 2^t mod p; and the square digit
-rint(u fl(1/s)) must equal round(u / s) with ties away from zero for odd s."""
+rint(u fl(1/s)) must equal round(u / s) with ties away from zero for odd s.
+The bound operands' E4M3 round-up code 8 e + 48 + Q is checked against the
+oracle's round-up over all E4M3 values of rows from subnormal to huge, and
+the residue pass's integer x 2^tt (x = trunc(a 2^(s - tt))) against the
+oracle's a' = trunc(a 2^s)."""
 import numpy as np
 import pytest
 
@@ -217,6 +221,73 @@ def test_residue_pass_power_step(p):
     prod = (u[:, None] * pw[None, :]).ravel()
     assert np.all(np.abs(prod) < 2 ** 20)
     assert np.array_equal(_fp32_step(prod, p), _sym(prod, p))
+
+
+def _residue_integer(a, s):
+    """The residue pass's integer as the kernel forms it: t = frexp exponent
+    - 53 + s (clamped below 192), tt = max(t - 10, 0), x = trunc(a 2^(s - tt))
+    + 0 for finite nonzero a, else +0; a' = x 2^tt."""
+    _, E = np.frexp(a)
+    nz = np.isfinite(a) & (a != 0)
+    t = np.where(nz, np.minimum(E - 53 + s, 191), 0)
+    tt = np.where(t > 10, t - 10, 0)
+    with np.errstate(over="ignore", invalid="ignore"):
+        x = np.trunc(np.ldexp(a, s - tt)) + 0.0
+    return np.where(nz, x, 0.0), tt
+
+
+def test_residue_integer_formation():
+    # a' = trunc(a 2^s) (eq. def:A') from x 2^tt, over doubles from subnormal
+    # to huge and shifts giving t from -120 (a' = 0) to 181
+    for _ in range(40):
+        E = int(RNG.integers(-1074, 1024))
+        a = np.ldexp(RNG.random(2048) + 0.5, E - RNG.integers(0, 60, 2048))
+        a = np.concatenate([a, np.ldexp(RNG.integers(1, 1 << 52, 64).astype(np.float64), -1074)])
+        a = a[np.isfinite(a) & (a > 0)]
+        a = np.concatenate([a, -a, [0.0, -0.0]])
+        _, Ea = np.frexp(np.max(np.abs(a)))
+        for t_top in (-120, -1, 0, 1, 10, 11, 53, 120, 181):
+            s = t_top - (int(Ea) - 53)                  # the largest input gets t = t_top
+            x, tt = _residue_integer(a, s)
+            assert np.all(np.abs(x) < 2.0 ** 63) and np.all(np.trunc(x) == x)
+            assert not np.any(np.signbit(x) & (x == 0))  # never -0
+            want = ref.to_integers(a[None, :], np.array([s]), axis=0)[0]
+            with np.errstate(over="ignore"):
+                got = np.ldexp(x, tt)
+            ok = np.isfinite(want)
+            assert np.array_equal(got[ok], want[ok]), (E, t_top)
+
+
+def _round_up_code(a, sh):
+    """The bound operands' E4M3 round-up as the kernel computes it: with
+    fl = frexp exponent - 1 + sh = floor(log2 |a| 2^sh) and e = max(fl, -6),
+    Q = max(ceil(|a| 2^(sh + 3 - e)), 1) and the code is 8 e + 48 + Q."""
+    _, E = np.frexp(a)
+    e = np.maximum(E - 1 + sh, -6)
+    Q = np.maximum(np.ceil(np.ldexp(np.abs(a), sh + 3 - e)), 1.0)
+    return 8 * e + 48 + Q.astype(np.int64)
+
+
+def test_bound_round_up_code_formula():
+    # rows with ufp exponent E (sh = 7 - E), from subnormal to huge doubles:
+    # every E4M3 value of the row's range, its neighbours one double ulp
+    # away, random magnitudes over 80 binades, and subnormal doubles
+    grid = ref.E4M3_NONNEG[1:]
+    for E in list(range(-1074, -1000, 3)) + list(range(-1000, 1024, 37)) + [1023]:
+        sh = 7 - E
+        with np.errstate(over="ignore"):    # grid values past the largest double
+            top = np.ldexp(1.0, E) * (1.0 + RNG.random(64))        # the row maxima
+            on = np.ldexp(grid, -sh)                                 # E4M3 values of the row
+            near = np.concatenate([on, np.nextafter(on, 0.0), np.nextafter(on, np.inf)])
+            end = np.ldexp(2.0, E)                                   # the row's binade end
+        rnd = np.ldexp(RNG.random(4096) + 0.5, E - RNG.integers(0, 80, 4096))
+        sub = np.ldexp(RNG.integers(1, 1 << 20, 256).astype(np.float64), -1074)
+        a = np.concatenate([top, near, rnd, sub])
+        a = a[(a > 0) & (a < end) & np.isfinite(a)]
+        a = np.concatenate([a, -a])
+        want = ref.e4m3_encode_exact(ref.round_up_e4m3(np.ldexp(np.abs(a), sh), a != 0))
+        got = _round_up_code(a, sh)
+        assert np.array_equal(got, want.astype(np.int64)), E
 
 
 @pytest.mark.parametrize("p,s", [(p, s) for p, s in _moduli("square") if s % 2 == 1])

@@ -1,6 +1,6 @@
-// Device helpers shared by the kernels: exact bit-level handling of FP64
-// inputs and of the FP8 E4M3 (OCP E4M3FN: bias 7, max 448, no infinities)
-// encodings used for the bound operands and the residue digits.
+// Device helpers shared by the kernels: exact handling of FP64 inputs and of
+// the FP8 E4M3 (OCP E4M3FN: bias 7, max 448, no infinities) encodings used
+// for the bound operands and the residue digits.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -14,10 +14,6 @@ __device__ __forceinline__ int ufp_exponent(uint64_t bits) {
   if (ex != 0) return ex - 1023;
   uint64_t man = bits & ((1ull << 52) - 1);
   return (63 - __clzll((long long)man)) - 1074;
-}
-
-__device__ __forceinline__ bool is_nonfinite(uint64_t bits) {
-  return ((bits >> 52) & 0x7FF) == 0x7FF;
 }
 
 // E4M3 code of the smallest E4M3 value >= |a| 2^sh for a finite nonzero
@@ -35,16 +31,6 @@ __device__ __forceinline__ uint32_t e4m3_round_up(double a, int sh) {
   const int e = fl > -6 ? fl : -6;
   const double Q = fmax(ceil(ldexp(fabs(a), sh + 3 - e)), 1.0);
   return (uint32_t)(8 * e + 48 + (int)Q);
-}
-
-// E4M3 code of a small integer d with |d| <= 16 (exact in the format).
-__device__ __forceinline__ uint32_t e4m3_of_small_int(int d) {
-  uint32_t a = (uint32_t)(d < 0 ? -d : d);
-  if (a == 0) return 0u;
-  int e = 31 - __clz((int)a);               // 0..4
-  uint32_t man = ((a << 3) >> e) - 8u;      // 3 mantissa bits, exact
-  uint32_t code = ((uint32_t)(e + 7) << 3) | man;
-  return d < 0 ? (code | 0x80u) : code;
 }
 
 // 2^9 x the value of a non-negative E4M3 code (sign bit clear): an integer

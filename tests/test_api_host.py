@@ -130,7 +130,7 @@ def _library(cmd):
 def test_host_logic_sanitized_matches_library(host_api):
     import torch
     if torch.cuda.is_available():
-        pytest.skip("compares host-only paths; on a GPU box valid calls would launch")
+        pytest.skip("compares host-only paths; with a GPU present, valid calls would launch")
     rng = random.Random(2603)
     cmds = _commands(rng)
     text = "".join(" ".join(str(v) for v in c) + "\n" for c in cmds)
